@@ -1,0 +1,530 @@
+/*
+ * hdmd_oracle.c -- plain, slow, single-threaded CPU oracle for the
+ * d-dimensional MD hot path of Hoy & Interiano-Alberto (arXiv:2112.12271).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant with the HIP
+ * library.  Compile with -O2 -ffp-contract=off (no -march=native, no fast-math)
+ * so that every operation below is rounded exactly as written.
+ *
+ * Conventions (all FP64):
+ *   positions x[n*d], row-major (atom i, axis k at x[i*d+k]), wrapped into
+ *   the periodic hypercube [-L/2, L/2)^d centred at the origin (Sec. II.A).
+ *   diameters sig[n]; masses are 1 and epsilon is one global value.
+ *
+ * Each function names the passage of the paper it follows.  Where the paper is
+ * silent or garbled the reading taken is stated next to the code.
+ */
+#define _DEFAULT_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_WCA 0
+#define ORC_HARMONIC 1
+
+/* ------------------------------------------------------------------------- */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Volume of a d-dimensional ball of diameter sigma, Sec. II.A eq. (vofsigma):
+ * pi^(d/2) sigma^d / (2^d Gamma(1 + d/2)). */
+double orc_sphere_volume(int d, double sigma) {
+  return pow(3.14159265358979323846, 0.5 * d) * pow(sigma, d) / (pow(2.0, d) * tgamma(1.0 + 0.5 * d));
+}
+
+/* Subcells per axis, Sec. II.C eq. (setnc): floor(L / r_list_max), at least
+ * one.  The paper's r_c^max is the largest interaction range plus the skin.
+ * Reading: the count is lowered while a subcell would be narrower than the
+ * list radius by more than rounding can explain, so that two atoms closer
+ * than r_list_max along an axis never land two subcells apart. */
+int orc_ncell(double L, double rlmax) {
+  double q = floor(L / rlmax);
+  int n = q < 1.0 ? 1 : (q > 1.0e6 ? 1000000 : (int)q);
+  while (n > 1 && L / (double)n < rlmax * (1.0 + 1.0e-9)) n--;
+  return n;
+}
+
+/* Wrap one coordinate into [-L/2, L/2): one periodic shift, then a guard for
+ * the case where x + L rounds up onto +L/2 (periodic boundaries, Sec. II.A). */
+double orc_wrap1(double x, double L) {
+  double h = 0.5 * L;
+  if (x >= h) x = x - L;
+  else if (x < -h) x = x + L;
+  if (x >= h) x = -h;
+  return x;
+}
+
+/* Minimum-image displacement along one axis, dx = x_j - x_i shifted by one box
+ * length when it exceeds half the box.  The paper's distance formula (Sec.
+ * II.B, the pair-distance equation) is printed as a plain sum of components;
+ * the reading taken is the Euclidean norm of the minimum-image vector. */
+static double min_image(double dx, double L) {
+  double h = 0.5 * L;
+  if (dx > h) dx = dx - L;
+  else if (dx < -h) dx = dx + L;
+  return dx;
+}
+
+/* Squared minimum-image distance, accumulated axis by axis as a fused
+ * multiply-add (the sum of squares, each term added with one rounding). */
+static double dist2(int d, const double* xi, const double* xj, double L) {
+  double r2 = 0.0;
+  for (int k = 0; k < d; k++) {
+    double dx = min_image(xj[k] - xi[k], L);
+    r2 = fma(dx, dx, r2);
+  }
+  return r2;
+}
+
+/* Verlet-list radius for one pair: r_l = c * sigma_ij + s with the
+ * Lorentz-Berthelot diameter sigma_ij = (sigma_i + sigma_j)/2 (Sec. II.A) and
+ * the skin s (Sec. II.C).  Reading: the radius is per pair, not the global
+ * r_c^max; the global value only sizes the subcells. */
+static double list_radius2(double si, double sj, double c, double s) {
+  double sij = 0.5 * (si + sj);
+  double rl = c * sij + s;
+  return rl * rl;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Neighbour lists                                                           */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t n;
+  int64_t* row_ptr; /* n+1 */
+  int32_t* cols;
+  int64_t nnz, cap;
+} orc_list;
+
+static orc_list* list_new(int64_t n) {
+  orc_list* l = (orc_list*)calloc(1, sizeof(orc_list));
+  l->n = n;
+  l->row_ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  l->cap = 16 * (n > 0 ? n : 1);
+  l->cols = (int32_t*)malloc((size_t)l->cap * sizeof(int32_t));
+  return l;
+}
+
+static void list_push(orc_list* l, int32_t j) {
+  if (l->nnz == l->cap) {
+    l->cap *= 2;
+    l->cols = (int32_t*)realloc(l->cols, (size_t)l->cap * sizeof(int32_t));
+  }
+  l->cols[l->nnz++] = j;
+}
+
+void orc_list_free(orc_list* l) {
+  if (!l) return;
+  free(l->row_ptr);
+  free(l->cols);
+  free(l);
+}
+int64_t orc_list_nnz(const orc_list* l) { return l->nnz; }
+void orc_list_copy(const orc_list* l, int64_t* row_ptr, int32_t* cols) {
+  memcpy(row_ptr, l->row_ptr, (size_t)(l->n + 1) * sizeof(int64_t));
+  memcpy(cols, l->cols, (size_t)l->nnz * sizeof(int32_t));
+}
+
+/* The definition of the Verlet list: j is in the list of i iff j != i and the
+ * squared minimum-image distance is strictly below r_l,ij^2.  Every pair is
+ * examined; rows come out in ascending j. */
+orc_list* orc_nlist_brute(int d, int64_t n, double L, const double* x, const double* sig, double c,
+                          double s) {
+  orc_list* l = list_new(n);
+  for (int64_t i = 0; i < n; i++) {
+    l->row_ptr[i] = l->nnz;
+    for (int64_t j = 0; j < n; j++) {
+      if (j == i) continue;
+      double r2 = dist2(d, x + i * d, x + j * d, L);
+      if (r2 < list_radius2(sig[i], sig[j], c, s)) list_push(l, (int32_t)j);
+    }
+  }
+  l->row_ptr[n] = l->nnz;
+  return l;
+}
+
+/* One row of the definition above (for sampled checks on large systems). */
+int64_t orc_nlist_row(int d, int64_t n, double L, const double* x, const double* sig, double c,
+                      double s, int64_t i, int32_t* out, int64_t cap) {
+  int64_t m = 0;
+  for (int64_t j = 0; j < n; j++) {
+    if (j == i) continue;
+    double r2 = dist2(d, x + i * d, x + j * d, L);
+    if (r2 < list_radius2(sig[i], sig[j], c, s)) {
+      if (m < cap) out[m] = (int32_t)j;
+      m++;
+    }
+  }
+  return m;
+}
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t u = *(const int32_t*)a, v = *(const int32_t*)b;
+  return (u > v) - (u < v);
+}
+
+/* Subcell of one atom along one axis: C = floor((x + L/2) n / L), clamped to
+ * [0, n-1] (Sec. II.C; subcells are numbered from the box corner). */
+static int cell_coord(double x, double L, int nc) {
+  int c = (int)floor((x + 0.5 * L) * ((double)nc / L));
+  if (c < 0) c = 0;
+  if (c > nc - 1) c = nc - 1;
+  return c;
+}
+
+/* The paper's cell path (Sec. II.C, Fig. 1): subcells of side L/n_cell with
+ * flat index I = sum_k C_k n^(d-1-k); an outer loop over subcells, a second
+ * loop over the 3^d linked subcells found on the fly by decoding a mixed-radix
+ * counter, then the atoms of the subcell and the atoms of the linked subcell.
+ * Reading for n_cell < 3 (the paper switches to an O(N^2) routine there): the
+ * per-axis offsets -1, 0, +1 taken modulo n_cell are deduplicated, so each
+ * linked subcell is visited once; with n_cell = 1 or 2 this visits every
+ * subcell, which is the all-pairs search.  Rows are then sorted so the result
+ * can be compared with the definition as a set.
+ * ncell_override > 0 forces a smaller subcell count (any count whose subcells
+ * are at least r_list_max wide gives the same list). */
+orc_list* orc_nlist_cells(int d, int64_t n, double L, const double* x, const double* sig, double c,
+                          double s, int ncell_override) {
+  double smax = 0.0;
+  for (int64_t i = 0; i < n; i++)
+    if (sig[i] > smax) smax = sig[i];
+  double rlmax = c * smax + s;
+  int nc = orc_ncell(L, rlmax);
+  if (ncell_override > 0 && ncell_override < nc) nc = ncell_override;
+  int64_t ncells = 1;
+  for (int k = 0; k < d; k++) ncells *= nc;
+
+  /* linked subcells: atoms of each subcell in ascending id */
+  int64_t* cell_of = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* start = (int64_t*)calloc((size_t)ncells + 1, sizeof(int64_t));
+  int64_t* members = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t I = 0;
+    for (int k = 0; k < d; k++) I = I * nc + cell_coord(x[i * d + k], L, nc);
+    cell_of[i] = I;
+    start[I + 1]++;
+  }
+  for (int64_t I = 0; I < ncells; I++) start[I + 1] += start[I];
+  int64_t* fill = (int64_t*)malloc((size_t)ncells * sizeof(int64_t));
+  memcpy(fill, start, (size_t)ncells * sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) members[fill[cell_of[i]]++] = i;
+  free(fill);
+
+  /* per-axis offsets after deduplication */
+  int radix = nc < 3 ? nc : 3;
+  int offs[3];
+  if (nc >= 3) { offs[0] = -1; offs[1] = 0; offs[2] = 1; }
+  else if (nc == 2) { offs[0] = 0; offs[1] = 1; }
+  else { offs[0] = 0; }
+  int64_t nstencil = 1;
+  for (int k = 0; k < d; k++) nstencil *= radix;
+
+  /* gather hits per atom, then emit sorted rows */
+  int64_t* cnt = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+  int64_t hcap = 16 * (n > 0 ? n : 1), nh = 0;
+  int32_t* hi = (int32_t*)malloc((size_t)hcap * sizeof(int32_t));
+  int32_t* hj = (int32_t*)malloc((size_t)hcap * sizeof(int32_t));
+  int* C = (int*)malloc((size_t)d * sizeof(int));
+
+  for (int64_t I = 0; I < ncells; I++) {
+    if (start[I] == start[I + 1]) continue; /* no atom i in this subcell */
+    /* decode I into subcell coordinates, axis 0 most significant */
+    int64_t t = I;
+    for (int k = d - 1; k >= 0; k--) { C[k] = (int)(t % nc); t /= nc; }
+    for (int64_t q = 0; q < nstencil; q++) {
+      /* decode the stencil counter and form the linked subcell index */
+      int64_t u = q, J = 0, w = 1;
+      for (int k = d - 1; k >= 0; k--) {
+        int o = offs[u % radix];
+        u /= radix;
+        int cj = ((C[k] + o) % nc + nc) % nc;
+        J += cj * w;
+        w *= nc;
+      }
+      for (int64_t a = start[I]; a < start[I + 1]; a++) {
+        int64_t i = members[a];
+        for (int64_t b = start[J]; b < start[J + 1]; b++) {
+          int64_t j = members[b];
+          if (j == i) continue;
+          double r2 = dist2(d, x + i * d, x + j * d, L);
+          if (r2 < list_radius2(sig[i], sig[j], c, s)) {
+            if (nh == hcap) {
+              hcap *= 2;
+              hi = (int32_t*)realloc(hi, (size_t)hcap * sizeof(int32_t));
+              hj = (int32_t*)realloc(hj, (size_t)hcap * sizeof(int32_t));
+            }
+            hi[nh] = (int32_t)i;
+            hj[nh] = (int32_t)j;
+            nh++;
+            cnt[i]++;
+          }
+        }
+      }
+    }
+  }
+  orc_list* l = list_new(n);
+  for (int64_t i = 0; i < n; i++) l->row_ptr[i + 1] = l->row_ptr[i] + cnt[i];
+  l->cap = nh > 0 ? nh : 1;
+  l->cols = (int32_t*)realloc(l->cols, (size_t)l->cap * sizeof(int32_t));
+  int64_t* pos = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) pos[i] = l->row_ptr[i];
+  for (int64_t h = 0; h < nh; h++) l->cols[pos[hi[h]]++] = hj[h];
+  l->nnz = nh;
+  for (int64_t i = 0; i < n; i++)
+    qsort(l->cols + l->row_ptr[i], (size_t)(l->row_ptr[i + 1] - l->row_ptr[i]), sizeof(int32_t),
+          cmp_i32);
+  free(pos); free(C); free(hi); free(hj); free(cnt);
+  free(cell_of); free(start); free(members);
+  return l;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pair potentials and forces                                                */
+/* ------------------------------------------------------------------------- */
+
+/* One pair: returns U and sets *fcoef = -U'(r)/r, so that the force on i is
+ * fcoef * (x_i - x_j).  Interaction iff r < r_c = c * sigma_ij.
+ *  WCA: U = 4 eps [(sigma/r)^12 - (sigma/r)^6] + eps, the paper's Mie form with
+ *       n = 6 (Sec. II.A) rewritten with sigma at the zero crossing and shifted
+ *       so that U(2^(1/6) sigma) = 0.
+ *  Harmonic soft spheres: U = eps/2 (1 - r/sigma)^2. */
+static double pair(int pot, double r2, double sij, double eps, double* fcoef) {
+  if (pot == ORC_WCA) {
+    double s2 = sij * sij / r2;
+    double s6 = s2 * s2 * s2;
+    *fcoef = 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
+    return 4.0 * eps * (s6 * s6 - s6) + eps;
+  } else {
+    double r = sqrt(r2);
+    double g = 1.0 - r / sij;
+    *fcoef = eps * g / (sij * r);
+    return 0.5 * eps * g * g;
+  }
+}
+
+/* Force and per-atom energy from a full Verlet list (the paper's getforce,
+ * Sec. II.B): F_i = sum over j in the row, in row order, of fcoef*(x_i - x_j)
+ * for pairs inside the cutoff; e_i = half the sum of the pair energies.
+ * Returns the total energy sum_{i<j} U_ij accumulated in ascending (i, j). */
+double orc_forces(int d, int64_t n, double L, const double* x, const double* sig, int pot, double c,
+                  double eps, const int64_t* row_ptr, const int32_t* cols, double* F,
+                  double* e_atom) {
+  double etot = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    double ei = 0.0;
+    for (int k = 0; k < d; k++) F[i * d + k] = 0.0;
+    for (int64_t a = row_ptr[i]; a < row_ptr[i + 1]; a++) {
+      int64_t j = cols[a];
+      double sij = 0.5 * (sig[i] + sig[j]);
+      double rc = c * sij;
+      double r2 = dist2(d, x + i * d, x + j * d, L);
+      if (!(r2 < rc * rc)) continue;
+      double fc;
+      double u = pair(pot, r2, sij, eps, &fc);
+      for (int k = 0; k < d; k++) {
+        double dx = min_image(x[j * d + k] - x[i * d + k], L);
+        F[i * d + k] -= fc * dx;
+      }
+      ei += 0.5 * u;
+      if (j > i) etot += u;
+    }
+    if (e_atom) e_atom[i] = ei;
+  }
+  return etot;
+}
+
+/* Force on one atom by the definition (every other atom, ascending j). */
+double orc_force_one(int d, int64_t n, double L, const double* x, const double* sig, int pot,
+                     double c, double eps, int64_t i, double* Fi) {
+  double ei = 0.0;
+  for (int k = 0; k < d; k++) Fi[k] = 0.0;
+  for (int64_t j = 0; j < n; j++) {
+    if (j == i) continue;
+    double sij = 0.5 * (sig[i] + sig[j]);
+    double rc = c * sij;
+    double r2 = dist2(d, x + i * d, x + j * d, L);
+    if (!(r2 < rc * rc)) continue;
+    double fc;
+    double u = pair(pot, r2, sij, eps, &fc);
+    for (int k = 0; k < d; k++) {
+      double dx = min_image(x[j * d + k] - x[i * d + k], L);
+      Fi[k] -= fc * dx;
+    }
+    ei += 0.5 * u;
+  }
+  return ei;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Integrators                                                               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  int d;
+  int64_t n;
+  double L;
+  int pot;
+  double c, s, eps;
+} orc_sys;
+
+typedef struct {
+  orc_list* nl;
+  double* xref;
+  int64_t builds;
+} orc_nlstate;
+
+static void rebuild(const orc_sys* S, const double* x, const double* sig, orc_nlstate* st) {
+  orc_list_free(st->nl);
+  st->nl = orc_nlist_cells(S->d, S->n, S->L, x, sig, S->c, S->s, 0);
+  memcpy(st->xref, x, (size_t)(S->n * S->d) * sizeof(double));
+  st->builds++;
+}
+
+/* Rebuild trigger: the largest minimum-image displacement since the last
+ * build exceeds half the skin (compared squared).  This is the rule the
+ * hot path uses; the paper's own needsrebuild (Sec. II.C) checks a 0.1 %
+ * quantile as well and only every n_bet steps. */
+static int needs_rebuild(const orc_sys* S, const double* x, const orc_nlstate* st) {
+  double hs2 = 0.25 * S->s * S->s, dmax = 0.0;
+  for (int64_t i = 0; i < S->n; i++) {
+    double r2 = dist2(S->d, st->xref + i * S->d, x + i * S->d, S->L);
+    if (r2 > dmax) dmax = r2;
+  }
+  return dmax > hs2;
+}
+
+static double kinetic(int64_t m, const double* v) {
+  double ke = 0.0;
+  for (int64_t a = 0; a < m; a++) ke += v[a] * v[a];
+  return 0.5 * ke;
+}
+
+/* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B with unit masses
+ * and no thermostat (NVE): per step v += dt/2 F; x += dt v; wrap; rebuild if
+ * needed; F = F(x); v += dt/2 F.  The first list is built at step 0.
+ * thermo (optional) receives nsteps+1 rows of (KE, PE) at the full steps.
+ * Returns the number of list builds. */
+int64_t orc_vv(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
+               double* v, const double* sig, int64_t nsteps, double dt, double* thermo) {
+  orc_sys S = {d, n, L, pot, c, s, eps};
+  int64_t m = n * d;
+  orc_nlstate st = {0};
+  st.xref = (double*)malloc((size_t)m * sizeof(double));
+  double* F = (double*)malloc((size_t)m * sizeof(double));
+  for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a], L);
+  rebuild(&S, x, sig, &st);
+  double pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
+  if (thermo) { thermo[0] = kinetic(m, v); thermo[1] = pe; }
+  for (int64_t t = 1; t <= nsteps; t++) {
+    for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
+    for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a] + dt * v[a], L);
+    if (needs_rebuild(&S, x, &st)) rebuild(&S, x, sig, &st);
+    pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
+    for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
+    if (thermo) { thermo[2 * t] = kinetic(m, v); thermo[2 * t + 1] = pe; }
+  }
+  int64_t b = st.builds;
+  orc_list_free(st.nl);
+  free(st.xref);
+  free(F);
+  return b;
+}
+
+/* FIRE 2.0 parameters.  The paper (Sec. II.B) uses the semi-implicit-Euler
+ * variant of FIRE 2.0 but prints no parameter values; these fields carry the
+ * values of the FIRE 2.0 publication it cites. */
+typedef struct {
+  double dt0, dtmax, dtmin;
+  double finc, fdec, alpha0, falpha;
+  int64_t ndelay, nneg_max, maxiter;
+  int64_t initial_delay;
+  double ftol; /* stop when max_i |F_i| < ftol */
+  double etol; /* or when PE/N < etol (0 disables) */
+} orc_fire_params;
+
+typedef struct {
+  int64_t iters;
+  int64_t builds;
+  double fmax;
+  double energy;
+  int64_t status; /* 0 converged, 1 not converged */
+} orc_fire_result;
+
+/* FIRE 2.0 with the semi-implicit Euler integrator (unit masses), Sec. II.B.
+ * Each iteration: P = F.v; on P > 0 count up and, after the delay, grow dt
+ * and shrink alpha; on P <= 0 count down, shrink dt and reset alpha (except
+ * inside the initial delay), step back x -= dt/2 v and zero v; then
+ * v += dt F, mix v = (1-alpha) v + alpha |v| F/|F| with norms over all dN
+ * components, x += dt v, wrap, rebuild if needed, recompute F.
+ * Convergence is checked on the fresh force before each iteration. */
+void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
+              const double* sig, const orc_fire_params* p, orc_fire_result* res) {
+  orc_sys S = {d, n, L, pot, c, s, eps};
+  int64_t m = n * d;
+  orc_nlstate st = {0};
+  st.xref = (double*)malloc((size_t)m * sizeof(double));
+  double* F = (double*)malloc((size_t)m * sizeof(double));
+  double* v = (double*)calloc((size_t)m, sizeof(double));
+  for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a], L);
+  rebuild(&S, x, sig, &st);
+  double pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
+  double dt = p->dt0, alpha = p->alpha0;
+  int64_t npos = 0, nneg = 0, it = 0;
+  int64_t status = 1;
+  double fmax2 = 0.0;
+  for (;;) {
+    fmax2 = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+      double f2 = 0.0;
+      for (int k = 0; k < d; k++) f2 += F[i * d + k] * F[i * d + k];
+      if (f2 > fmax2) fmax2 = f2;
+    }
+    if (sqrt(fmax2) < p->ftol || (p->etol > 0.0 && pe / (double)n < p->etol)) { status = 0; break; }
+    if (it >= p->maxiter) break;
+    double P = 0.0;
+    for (int64_t a = 0; a < m; a++) P += F[a] * v[a];
+    if (P > 0.0) {
+      npos++;
+      nneg = 0;
+      if (npos > p->ndelay) {
+        dt = fmin(dt * p->finc, p->dtmax);
+        alpha *= p->falpha;
+      }
+    } else {
+      npos = 0;
+      nneg++;
+      if (nneg > p->nneg_max) break;
+      if (!(p->initial_delay && it < p->ndelay)) {
+        if (dt * p->fdec >= p->dtmin) dt *= p->fdec;
+        alpha = p->alpha0;
+      }
+      for (int64_t a = 0; a < m; a++) x[a] = x[a] - 0.5 * dt * v[a];
+      for (int64_t a = 0; a < m; a++) v[a] = 0.0;
+    }
+    for (int64_t a = 0; a < m; a++) v[a] += dt * F[a];
+    double vv = 0.0, ff = 0.0;
+    for (int64_t a = 0; a < m; a++) { vv += v[a] * v[a]; ff += F[a] * F[a]; }
+    double vn = sqrt(vv), fn = sqrt(ff);
+    if (fn > 0.0) {
+      double mixf = alpha * vn / fn;
+      for (int64_t a = 0; a < m; a++) v[a] = (1.0 - alpha) * v[a] + mixf * F[a];
+    }
+    for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a] + dt * v[a], L);
+    if (needs_rebuild(&S, x, &st)) rebuild(&S, x, sig, &st);
+    pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
+    it++;
+  }
+  res->iters = it;
+  res->builds = st.builds;
+  res->fmax = sqrt(fmax2);
+  res->energy = pe;
+  res->status = status;
+  orc_list_free(st.nl);
+  free(st.xref);
+  free(F);
+  free(v);
+}
