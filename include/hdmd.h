@@ -1,0 +1,203 @@
+/*
+ * hdmd.h -- C ABI of the MI355X (gfx950) hot path of d-dimensional molecular
+ * dynamics after Hoy & Interiano-Alberto, "Efficient d-dimensional molecular
+ * dynamics simulations for studies of the glass-jamming transition"
+ * (arXiv:2112.12271).
+ *
+ * The library (libhdmd.so) runs every step on the GPU in hand-written HIP
+ * kernels.  It never allocates device memory: the caller owns positions,
+ * velocities, diameters, outputs and one opaque workspace per system (and one
+ * table workspace per batch), all device pointers.  Work is enqueued on the
+ * caller's stream (a hipStream_t passed as void*; NULL = the null stream).
+ *
+ * Layouts (caller side): positions, velocities and forces are row-major
+ * [n][d] FP64 (atom i, axis k at p[i*d + k]); diameters are [n] FP64.  The
+ * box is the periodic hypercube [-L/2, L/2)^d centred at the origin (Sec.
+ * II.A); positions are wrapped into it on entry.  Masses are 1 and the pair
+ * energy scale epsilon is one global value.
+ *
+ * Errors: every entry point returns an int status (hdmd_status).  Calls that
+ * report host-side results (required widths, statistics, FIRE results)
+ * synchronise the stream.  No C++ exception crosses this boundary; the text
+ * of the last failure on the calling thread is returned by hdmd_last_error().
+ * A workspace may be used by one stream at a time.
+ */
+#ifndef HDMD_H
+#define HDMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HDMD_OK = 0,
+  HDMD_NOT_CONVERGED = 1,      /* FIRE stopped at maxiter or after too many P<=0 steps */
+  HDMD_ERR_ARG = -1,           /* bad d (2..10), n < 2, L <= 0, skin < 0, null pointer, diameter
+                                  outside (0, sigma_max], position outside [-3L/2, 3L/2) */
+  HDMD_ERR_BOX = -2,           /* L < 2 c sigma_max: the minimum-image rule would be ambiguous */
+  HDMD_ERR_WORKSPACE = -3,     /* workspace smaller than hdmd_workspace_bytes() */
+  HDMD_ERR_NLIST_OVERFLOW = -4,/* a Verlet row exceeded max_neighbors; *required_width is set */
+  HDMD_ERR_NONFINITE = -5,     /* NaN/Inf in inputs or in the energy during a run */
+  HDMD_ERR_HIP = -6,           /* a HIP runtime call failed */
+  HDMD_ERR_STATE = -7          /* workspace not initialised for this system, or batch misuse */
+} hdmd_status;
+
+typedef enum { HDMD_WCA = 0, HDMD_HARMONIC = 1 } hdmd_potential;
+typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
+
+/* One system (Sec. II.A-C).  Pair (i,j) interacts for r < r_c = cutoff*sigma_ij
+ * with sigma_ij = (sigma_i + sigma_j)/2 (Lorentz-Berthelot, Sec. II.A) and is
+ * in the Verlet list for r < cutoff*sigma_ij + skin (Sec. II.C).
+ *   potential  HDMD_WCA: U = 4 eps [(sigma/r)^12 - (sigma/r)^6] + eps (the
+ *              paper's Mie n=6 form, Sec. II.A, with cutoff 2^(1/6));
+ *              HDMD_HARMONIC: U = eps/2 (1 - r/sigma)^2 (cutoff 1).
+ *   precision  HDMD_FP64: everything in FP64.  HDMD_MIXED: distances, forces
+ *              and velocities in FP32; positions, energy sums and FIRE's
+ *              reductions in FP64.  Verlet lists are FP64-exact in both.
+ *   sigma_max  largest diameter present; it sizes the subcells (eq. setnc).
+ *   max_neighbors  Verlet row capacity W of the workspace. */
+typedef struct {
+  int32_t d;
+  int32_t potential;
+  int32_t precision;
+  int32_t max_neighbors;
+  int64_t n;
+  double box_l;
+  double cutoff;
+  double skin;
+  double epsilon;
+  double sigma_max;
+} hdmd_system;
+
+/* FIRE 2.0 controls (Sec. II.B cites FIRE 2.0 with the semi-implicit Euler
+ * integrator but prints no values; hdmd_fire_defaults() fills the published
+ * defaults: N_delay 20, f_inc 1.1, f_dec 0.5, alpha_start 0.25, f_alpha 0.99,
+ * dt_max = 10 dt0, dt_min = 0.02 dt0, N_neg_max 2000, initial delay on). */
+typedef struct {
+  double dt0, dt_max, dt_min;
+  double f_inc, f_dec, alpha0, f_alpha;
+  int64_t n_delay, n_neg_max, max_iter;
+  int64_t initial_delay;
+  double f_tol;  /* stop when max_i |F_i| < f_tol */
+  double e_tol;  /* or when E/N < e_tol (0 disables; the paper's pushoff rule) */
+} hdmd_fire_params;
+
+typedef struct {
+  int64_t iterations;
+  int64_t builds;
+  double fmax;
+  double energy;
+  int32_t status;  /* HDMD_OK, HDMD_NOT_CONVERGED or an error */
+  int32_t pad;
+} hdmd_fire_result;
+
+typedef struct {
+  int64_t steps_done;
+  int64_t builds;     /* Verlet-list builds during the call */
+  double ke, pe;      /* at the last full step */
+  int32_t max_row;    /* longest Verlet row at the last build */
+  int32_t pad;
+  /* Filled only when the environment variable HDMD_PROFILE=1 is set: the call
+   * then launches kernels one by one (no graph) and brackets every fused-step
+   * kernel and every list-build kernel that did build with HIP events on the
+   * caller's stream. */
+  double step_kernel_ms;   /* summed duration of the fused-step kernels */
+  int64_t step_kernels;    /* their number */
+  double build_kernel_ms;  /* summed duration of the list-build kernels that built */
+  int64_t build_kernels;
+} hdmd_step_stats;
+
+/* Fills *p with the FIRE 2.0 defaults for initial step dt0 and tolerance f_tol. */
+void hdmd_fire_defaults(hdmd_fire_params* p, double dt0, double f_tol, int64_t max_iter);
+
+/* Bytes of the per-system workspace (256-byte aligned device memory). */
+size_t hdmd_workspace_bytes(const hdmd_system* sys);
+
+/* Subcell count per axis chosen for sys (eq. setnc with a rounding guard),
+ * or <= 0 with the status of the failed validation. */
+int hdmd_cells_per_axis(const hdmd_system* sys);
+
+/* Verlet-list build, Sec. II.C (Fig. 1): loads pos/diam into ws, bins atoms
+ * into n_cell^d subcells (flat index sum_k C_k n^(d-1-k)), sorts them by
+ * (subcell, atom id), and lists j for i iff r_ij^2 < (c sigma_ij + s)^2 over
+ * the 3^d linked subcells (deduplicated per axis when n_cell < 3).  On
+ * HDMD_ERR_NLIST_OVERFLOW *required_width holds the longest row; grow
+ * max_neighbors (and the workspace) and call again.  Synchronises. */
+int hdmd_build_nlist(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
+                     size_t ws_bytes, int32_t* required_width, void* stream);
+
+/* Exports the list held in ws as canonical CSR in caller atom ids, each row
+ * ascending: row_ptr [n+1] int64 (device), cols [cols_cap] int32 (device).
+ * *nnz (host) receives the entry count; cols untouched beyond cols_cap
+ * (HDMD_ERR_WORKSPACE if too small).  Synchronises. */
+int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_t* cols,
+                      int64_t cols_cap, int64_t* nnz, void* stream);
+
+/* Forces and energy, Sec. II.B (getforce): builds the list for pos, then
+ * F_i = sum_j -U'(r_ij)/r_ij (x_i - x_j) over listed pairs with r < r_c, in
+ * caller order [n][d] FP64 (device); *energy (device FP64) = sum_{i<j} U_ij.
+ * Synchronises (to report list overflow). */
+int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
+                size_t ws_bytes, double* force, double* energy, void* stream);
+
+/* NVE velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B: per step
+ * v += dt/2 F; x += dt v (wrapped); rebuild the list when the largest
+ * displacement since the last build exceeds skin/2; F = F(x); v += dt/2 F.
+ * pos and vel ([n][d] FP64, device) are read on entry and written on exit.
+ * thermo (device, may be NULL) receives floor(nsteps/thermo_every)+1 rows of
+ * (step, KE, PE, KE+PE) FP64 at steps 0, thermo_every, ...  Synchronises. */
+int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
+              size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
+              hdmd_step_stats* stats, void* stream);
+
+/* FIRE 2.0 energy minimisation with the semi-implicit Euler update (Sec.
+ * II.B), unit masses, global norms: pos ([n][d] FP64, device) in and out.
+ * Synchronises. */
+int hdmd_fire_minimize(const hdmd_system* sys, double* pos, const double* diam, void* ws,
+                       size_t ws_bytes, const hdmd_fire_params* params, hdmd_fire_result* result,
+                       void* stream);
+
+/* ---- Batches of uneven replicas (one persistent launch per kernel and
+ * d, replayed from a captured hipGraph).  A batch table holds up to
+ * max_slots systems; each slot has its own system workspace.  Slots are
+ * filled and emptied while other slots keep running (continuous batching). */
+
+#define HDMD_SLOT_EMPTY 0
+#define HDMD_SLOT_RUNNING 1
+#define HDMD_SLOT_DONE 2
+
+size_t hdmd_batch_bytes(int32_t max_slots, int64_t max_atoms, int64_t max_cells);
+/* Initialises a batch table in table_ws (device). */
+int hdmd_batch_init(void* table_ws, size_t table_bytes, int32_t max_slots, int64_t max_atoms,
+                    int64_t max_cells, void* stream);
+/* Loads a FIRE minimisation into slot: copies pos/diam into ws, builds the
+ * list and the initial forces.  pos/diam may be freed after the call returns
+ * (the stream is synchronised). */
+int hdmd_batch_add_fire(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
+                        const double* diam, void* ws, size_t ws_bytes,
+                        const hdmd_fire_params* params, void* stream);
+/* Loads an NVE run of nsteps velocity-Verlet steps of size dt into slot. */
+int hdmd_batch_add_md(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
+                      const double* vel, const double* diam, void* ws, size_t ws_bytes,
+                      int64_t nsteps, double dt, void* stream);
+/* Advances every running slot by `iterations` FIRE iterations or MD steps
+ * (asynchronous: enqueued as a captured graph). */
+int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream);
+/* Synchronises and fills state[max_slots] (HDMD_SLOT_*) and, where non-NULL,
+ * iters[max_slots] (iterations or steps done). */
+int hdmd_batch_poll(void* table_ws, int32_t* state, int64_t* iters, void* stream);
+/* Copies a finished slot out (pos [n][d], vel may be NULL), fills *result,
+ * and empties the slot.  Synchronises. */
+int hdmd_batch_take(void* table_ws, int32_t slot, double* pos, double* vel,
+                    hdmd_fire_result* result, void* stream);
+
+/* Text of the last non-OK status on this thread. */
+const char* hdmd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDMD_H */

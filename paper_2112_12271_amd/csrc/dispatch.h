@@ -1,0 +1,37 @@
+// dispatch.h -- host-side launchers of the dimension-templated kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "hdmd_dev.h"
+
+namespace hdmd {
+
+struct DKernels {
+  void (*load)(bool mix, SysDev* s, int grid, hipStream_t st, const double* pos,
+               const double* diam, const double* vel);
+  void (*unload)(bool mix, const SysDev* s, int grid, hipStream_t st, double* pos, double* vel,
+                 double* force);
+  void (*bin)(const KArgs& a, int grid, hipStream_t st);
+  void (*cellsort)(bool mix, const KArgs& a, int grid, hipStream_t st);
+  void (*build)(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st);
+  void (*force)(bool mix, const KArgs& a, int grid, int fire, hipStream_t st);
+  void (*step)(bool mix, const KArgs& a, int grid, hipStream_t st);
+  void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
+};
+
+const DKernels* dkernels(int d);
+
+// dimension-independent kernels (common.hip)
+void launch_setdesc(SysDev* dst, const SysDev& val, hipStream_t st);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_scan1(const KArgs& a, int grid, hipStream_t st);
+void launch_scan2(const KArgs& a, int grid, hipStream_t st);
+void launch_scatter(const KArgs& a, int grid, hipStream_t st);
+void launch_finalize(const KArgs& a, int grid, hipStream_t st);
+void launch_fire_ctrl(const KArgs& a, int grid, hipStream_t st);
+void launch_reduce_pe(const SysDev* s, double* out, hipStream_t st);
+void launch_export(const SysDev* s, int n, int64_t* row_ptr, int32_t* cols, hipStream_t st,
+                   int phase);
+void launch_set_status(SysDev* s, int32_t status, hipStream_t st);
+void launch_poll(const Table* t, int max_slots, int32_t* state, int64_t* iters, hipStream_t st);
+
+}  // namespace hdmd

@@ -1,0 +1,296 @@
+// hdmd_dev.h -- device-side data structures and helpers of the HIP hot path.
+//
+// Internal layout of one system (all in the caller's workspace):
+//   x[2]      positions, atom-major (AoS) [npad][DP] FP64, DP = d rounded up to
+//             even so an atom is whole 16-byte loads; double-buffered
+//             (a step reads x[cur] and writes x[cur^1]).
+//   v[2]      velocities, axis-major (SoA) [d][npad], FP64 or FP32.
+//   sig[2], oid[2]  diameter and caller id of each slot; the [2] buffers are
+//             the source and destination of the permutation at a rebuild.
+//   f         forces [d][npad] (FP64 or FP32), written by the force kernels.
+//   xref      positions at the last build [d][npad] FP64 (rebuild trigger).
+//   ycell     FP32 offsets of each atom from its subcell centre [npad][DY],
+//             DY = d rounded up to a multiple of 4 (prefilter of the build).
+//   nl, nlen  Verlet rows in ELL form, column-major nl[k*npad + i], i.e. entry
+//             k of every row is contiguous so a wave reads it coalesced.
+// Atoms are stored in subcell order (canonical: by subcell, then caller id),
+// rebuilt at every list build.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace hdmd {
+
+constexpr int kMaxD = 10;
+constexpr int kMinD = 2;
+constexpr int kTile = 256;      // atoms per atom tile = threads per workgroup
+constexpr int kWave = 64;
+constexpr int kChunk = 1024;    // subcells per scan chunk
+constexpr int kSortCap = 4096;  // subcell occupancy sorted in LDS (larger: in global memory)
+constexpr int kPart = 8;        // doubles per wave in the partial-sum array
+constexpr int kMaxSlots = 1024;
+constexpr int kQCap = 16;       // per-lane prefilter queue of the build
+
+enum Mode : int32_t { MODE_NONE = 0, MODE_FIRE = 1, MODE_MD = 2, MODE_STATIC = 3 };
+enum Slot : int32_t { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };
+enum Err : int32_t {
+  ERR_ARG = 1,        // position far outside the box, bad diameter
+  ERR_NONFINITE = 2,  // NaN/Inf in inputs
+  ERR_OVERFLOW = 4,   // a Verlet row longer than the ELL width
+  ERR_RUN_NAN = 8,    // non-finite energy during a run
+};
+// partial-sum record of one wave
+enum Part : int { P_PE = 0, P_KE = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_FMAX2 = 5 };
+
+struct FireCtl {
+  double dt0, dtmax, dtmin, finc, fdec, alpha0, falpha, ftol, etol;
+  int64_t ndelay, nnegmax, maxiter, initdelay;
+};
+
+struct SysDev {
+  // ---- static, written by the host
+  int32_t d, potential, precision, n;
+  int32_t npad, ncell, radix, ncells;
+  int32_t nstencil, width, nchunks, ntiles;
+  int32_t mode, wrap, nwaves, pad0;
+  double L, hL, cutoff, skin, eps, sigma_max;
+  double rlmax, lsc, inv_lsc, halfskin2;
+  float rl2f, lscf, Lf, pad1;
+  double* x[2];
+  void* v[2];
+  double* sig[2];
+  int32_t* oid[2];
+  void* f;
+  double* xref;
+  float* ycell;
+  int32_t* cell_of;
+  int32_t* rank;
+  int32_t* cell_count;
+  int32_t* cell_local;
+  int32_t* chunk_sum;
+  int32_t* chunk_off;
+  int32_t* key;
+  int32_t* src;
+  int32_t* nl;
+  int32_t* nlen;
+  double* part;
+  double* thermo;
+  double dt;
+  int64_t nsteps, thermo_every;
+  FireCtl fc;
+  // ---- dynamic, written by the kernels
+  int32_t xcur, pcur, force_rebuild, err;
+  unsigned long long maxdisp2;  // bit pattern of a non-negative double
+  int32_t max_row, max_cell, status, fstatus;
+  int64_t step, builds, iters;
+  double ke, pe;
+  double fdt, falpha, fmax, c_dt, c_keep, c_mix;
+  int32_t npos, nneg, c_zero, pad2;
+};
+
+// Tile tables of a batch: one list per dimension class (index d).
+struct Table {
+  int32_t max_slots, pad;
+  int32_t n_atom[kMaxD + 1];
+  int32_t n_cell[kMaxD + 1];
+  int32_t n_cell_nowrap[kMaxD + 1];  // cell tiles of systems with n_cell >= 3 come first
+  int32_t n_chunk;
+  int32_t n_sys;
+  int2* atom_tiles[kMaxD + 1];  // (slot, tile)
+  int2* cell_tiles[kMaxD + 1];  // (slot, cell)
+  int2* chunk_tiles;            // (slot, chunk)
+  int32_t* sys_list;            // slots of the current composition
+  SysDev* sys[kMaxSlots];
+};
+
+// Kernel arguments: either one system (tile = blockIdx) or a batch table.
+// part selects a sub-range of the cell tiles: 0 all, 1 systems with
+// n_cell >= 3, 2 systems with n_cell <= 2 (the two list-build variants).
+struct KArgs {
+  SysDev* single;
+  Table* tab;
+  int32_t cls;
+  int32_t part;
+};
+
+__device__ inline bool fetch_atom_tile(const KArgs& a, int t, SysDev*& s, int& tile) {
+  if (a.single) {
+    s = a.single;
+    tile = t;
+    return t < s->ntiles;
+  }
+  if (t >= a.tab->n_atom[a.cls]) return false;
+  int2 e = a.tab->atom_tiles[a.cls][t];
+  s = a.tab->sys[e.x];
+  tile = e.y;
+  return true;
+}
+
+__device__ inline bool fetch_cell_tile(const KArgs& a, int t, SysDev*& s, int& cell) {
+  if (a.single) {
+    s = a.single;
+    cell = t;
+    return t < s->ncells;
+  }
+  int lo = 0, hi = a.tab->n_cell[a.cls];
+  if (a.part == 1) hi = a.tab->n_cell_nowrap[a.cls];
+  else if (a.part == 2) lo = a.tab->n_cell_nowrap[a.cls];
+  if (t >= hi - lo) return false;
+  int2 e = a.tab->cell_tiles[a.cls][lo + t];
+  s = a.tab->sys[e.x];
+  cell = e.y;
+  return true;
+}
+
+__device__ inline bool fetch_chunk_tile(const KArgs& a, int t, SysDev*& s, int& chunk) {
+  if (a.single) {
+    s = a.single;
+    chunk = t;
+    return t < s->nchunks;
+  }
+  if (t >= a.tab->n_chunk) return false;
+  int2 e = a.tab->chunk_tiles[t];
+  s = a.tab->sys[e.x];
+  chunk = e.y;
+  return true;
+}
+
+__device__ inline bool fetch_sys(const KArgs& a, int t, SysDev*& s) {
+  if (a.single) {
+    s = a.single;
+    return t == 0;
+  }
+  if (t >= a.tab->n_sys) return false;
+  s = a.tab->sys[a.tab->sys_list[t]];
+  return true;
+}
+
+__device__ inline bool running(const SysDev* s) { return s->status == SLOT_RUNNING; }
+
+__device__ inline bool need_rebuild(const SysDev* s) {
+  return s->force_rebuild != 0 || __longlong_as_double((long long)s->maxdisp2) > s->halfskin2;
+}
+
+// Subcell start (exclusive prefix of occupancies), split in chunk-local part
+// and chunk offset; start(ncells) = n.
+__device__ inline int cell_start(const SysDev* s, int c) {
+  if (c >= s->ncells) return s->n;
+  return s->cell_local[c] + s->chunk_off[c / kChunk];
+}
+
+// One periodic shift into [-L/2, L/2), then a guard for x + L rounding onto
+// +L/2 (same rule as the per-step wrap of positions).
+__device__ inline double wrap1(double x, double L, double h) {
+  if (x >= h) x = x - L;
+  else if (x < -h) x = x + L;
+  if (x >= h) x = -h;
+  return x;
+}
+
+__device__ inline double min_image(double dx, double L, double h) {
+  if (dx > h) dx = dx - L;
+  else if (dx < -h) dx = dx + L;
+  return dx;
+}
+
+template <int D>
+struct Dims {
+  static constexpr int DP = (D + 1) & ~1;  // FP64 AoS stride
+  static constexpr int DY = (D + 3) & ~3;  // FP32 AoS stride
+};
+
+template <int D>
+__device__ inline void load_x(const double* __restrict__ xb, int i, double (&x)[D]) {
+  constexpr int DP = Dims<D>::DP;
+  const double2* p = reinterpret_cast<const double2*>(xb + (size_t)i * DP);
+#pragma unroll
+  for (int k = 0; k < DP / 2; k++) {
+    double2 t = p[k];
+    x[2 * k] = t.x;
+    if (2 * k + 1 < D) x[2 * k + 1] = t.y;
+  }
+}
+
+template <int D>
+__device__ inline void store_x(double* __restrict__ xb, int i, const double (&x)[D]) {
+  constexpr int DP = Dims<D>::DP;
+  double2* p = reinterpret_cast<double2*>(xb + (size_t)i * DP);
+#pragma unroll
+  for (int k = 0; k < DP / 2; k++) {
+    double2 t;
+    t.x = x[2 * k];
+    t.y = (2 * k + 1 < D) ? x[2 * k + 1] : 0.0;
+    p[k] = t;
+  }
+}
+
+// Squared minimum-image distance accumulated axis by axis with a fused
+// multiply-add; identical operation sequence to the list definition.
+template <int D>
+__device__ inline double dist2_exact(const double (&xi)[D], const double (&xj)[D], double L,
+                                     double h) {
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    double dx = min_image(xj[k] - xi[k], L, h);
+    r2 = __builtin_fma(dx, dx, r2);
+  }
+  return r2;
+}
+
+// Per-pair list radius squared: (c * (si+sj)/2 + s)^2, each op rounded once.
+__device__ inline double list_r2(double si, double sj, double c, double s) {
+  double sij = 0.5 * (si + sj);
+  double rl = c * sij + s;
+  return rl * rl;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide deterministic sum of per-thread values (fixed tree order).
+template <int BS>
+__device__ inline double block_sum(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = sh[t] + sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+template <int BS>
+__device__ inline double block_max(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace hdmd

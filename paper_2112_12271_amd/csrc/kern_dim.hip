@@ -1,0 +1,60 @@
+// kern_dim.hip -- instantiates the kernels for one dimension HDMD_DIM and
+// exports their launchers.  Built once per d = 2..10.
+#include "kernels.h"
+#include "dispatch.h"
+
+#ifndef HDMD_DIM
+#error "HDMD_DIM must be defined"
+#endif
+
+namespace hdmd {
+namespace {
+constexpr int D = HDMD_DIM;
+
+void l_load(bool mix, SysDev* s, int grid, hipStream_t st, const double* pos, const double* diam,
+            const double* vel) {
+  if (mix) k_load<D, float><<<grid, kTile, 0, st>>>(s, pos, diam, vel);
+  else k_load<D, double><<<grid, kTile, 0, st>>>(s, pos, diam, vel);
+}
+void l_unload(bool mix, const SysDev* s, int grid, hipStream_t st, double* pos, double* vel,
+              double* force) {
+  if (mix) k_unload<D, float><<<grid, kTile, 0, st>>>(s, pos, vel, force);
+  else k_unload<D, double><<<grid, kTile, 0, st>>>(s, pos, vel, force);
+}
+void l_bin(const KArgs& a, int grid, hipStream_t st) { k_bin<D><<<grid, kTile, 0, st>>>(a); }
+void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
+  if (mix) k_cellsort<D, float><<<grid, kTile, 0, st>>>(a);
+  else k_cellsort<D, double><<<grid, kTile, 0, st>>>(a);
+}
+void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
+  if (wrap) {
+    if (blk <= 64) k_build<D, true, 64><<<grid, 64, 0, st>>>(a);
+    else if (blk <= 128) k_build<D, true, 128><<<grid, 128, 0, st>>>(a);
+    else k_build<D, true, 256><<<grid, 256, 0, st>>>(a);
+  } else {
+    if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
+    else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
+    else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);
+  }
+}
+void l_force(bool mix, const KArgs& a, int grid, int fire, hipStream_t st) {
+  if (mix) k_force<D, true><<<grid, kTile, 0, st>>>(a, fire);
+  else k_force<D, false><<<grid, kTile, 0, st>>>(a, fire);
+}
+void l_step(bool mix, const KArgs& a, int grid, hipStream_t st) {
+  if (mix) k_step<D, true><<<grid, kTile, 0, st>>>(a);
+  else k_step<D, false><<<grid, kTile, 0, st>>>(a);
+}
+void l_fire_update(bool mix, const KArgs& a, int grid, hipStream_t st) {
+  if (mix) k_fire_update<D, true><<<grid, kTile, 0, st>>>(a);
+  else k_fire_update<D, false><<<grid, kTile, 0, st>>>(a);
+}
+const DKernels table = {l_load, l_unload, l_bin, l_cellsort, l_build, l_force, l_step,
+                        l_fire_update};
+}  // namespace
+
+#define HDMD_CAT2(a, b) a##b
+#define HDMD_CAT(a, b) HDMD_CAT2(a, b)
+const DKernels* HDMD_CAT(dkernels_d, HDMD_DIM)() { return &table; }
+
+}  // namespace hdmd

@@ -1,0 +1,1132 @@
+// runtime.hip -- host runtime behind the C ABI (include/hdmd.h): workspace
+// layout, validation, launch sequences, hipGraph capture of step / iteration
+// chunks, the build-tile autotuner, and the batch tables of uneven replicas.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "dispatch.h"
+#include "hdmd.h"
+
+namespace hdmd {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(HDMD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// geometry and workspace plan
+// ---------------------------------------------------------------------------
+struct Plan {
+  int d = 0, dp = 0, dy = 0;
+  int n = 0, npad = 0, ncell = 0, radix = 0, ncells = 0, nstencil = 0, nchunks = 0;
+  int ntiles = 0, nwaves = 0, width = 0;
+  bool wrap = false, mix = false;
+  double rlmax = 0;
+  size_t off_desc = 0, off_x[2] = {0, 0}, off_v[2] = {0, 0}, off_sig[2] = {0, 0},
+         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_cell_of = 0,
+         off_rank = 0, off_cell_count = 0, off_cell_local = 0, off_chunk_sum = 0,
+         off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0;
+  size_t bytes = 0;
+};
+
+static int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; i++) {
+    r *= b;
+    if (r > (int64_t(1) << 40)) return r;
+  }
+  return r;
+}
+
+// Subcells per axis: floor(L / r_list_max) (eq. setnc with the largest
+// diameter sigma_max and skin s), lowered while a subcell would be narrower
+// than the list radius by more than rounding, and while the subcell count
+// would exceed 2^26 or four per atom (fewer, wider subcells list the same
+// pairs).
+static int choose_ncell(const hdmd_system& s, double rlmax) {
+  double q = std::floor(s.box_l / rlmax);
+  int nc = q < 1.0 ? 1 : (q > 4096.0 ? 4096 : (int)q);
+  while (nc > 1 && s.box_l / (double)nc < rlmax * (1.0 + 1.0e-9)) nc--;
+  const int64_t cap = std::min<int64_t>(int64_t(1) << 26, std::max<int64_t>(64, 4 * s.n));
+  while (nc > 1 && ipow(nc, s.d) > cap) nc--;
+  return nc;
+}
+
+static int make_plan(const hdmd_system* s, Plan& p) {
+  if (!s) return fail(HDMD_ERR_ARG, "null system");
+  if (s->d < kMinD || s->d > kMaxD) return fail(HDMD_ERR_ARG, "d must be in [2, 10]");
+  if (s->n < 2 || s->n > (int64_t(1) << 30)) return fail(HDMD_ERR_ARG, "n must be in [2, 2^30]");
+  if (!(s->box_l > 0) || !std::isfinite(s->box_l)) return fail(HDMD_ERR_ARG, "box_l must be > 0");
+  if (!(s->cutoff > 0) || !std::isfinite(s->cutoff)) return fail(HDMD_ERR_ARG, "cutoff must be > 0");
+  if (!(s->skin >= 0) || !std::isfinite(s->skin)) return fail(HDMD_ERR_ARG, "skin must be >= 0");
+  if (!(s->epsilon > 0) || !std::isfinite(s->epsilon)) return fail(HDMD_ERR_ARG, "epsilon must be > 0");
+  if (!(s->sigma_max > 0) || !std::isfinite(s->sigma_max)) return fail(HDMD_ERR_ARG, "sigma_max must be > 0");
+  if (s->potential != HDMD_WCA && s->potential != HDMD_HARMONIC) return fail(HDMD_ERR_ARG, "bad potential");
+  if (s->precision != HDMD_FP64 && s->precision != HDMD_MIXED) return fail(HDMD_ERR_ARG, "bad precision");
+  if (s->max_neighbors < 1 || s->max_neighbors > (1 << 20)) return fail(HDMD_ERR_ARG, "max_neighbors must be in [1, 2^20]");
+  if (s->box_l < 2.0 * s->cutoff * s->sigma_max)
+    return fail(HDMD_ERR_BOX, "box_l < 2 * cutoff * sigma_max: minimum image is ambiguous");
+  p.d = s->d;
+  p.dp = (s->d + 1) & ~1;
+  p.dy = (s->d + 3) & ~3;
+  p.n = (int)s->n;
+  p.npad = (int)((s->n + kTile - 1) / kTile * kTile);
+  p.rlmax = s->cutoff * s->sigma_max + s->skin;
+  p.ncell = choose_ncell(*s, p.rlmax);
+  p.radix = p.ncell < 3 ? p.ncell : 3;
+  p.ncells = (int)ipow(p.ncell, p.d);
+  p.nstencil = (int)ipow(p.radix, p.d);
+  p.nchunks = (p.ncells + kChunk - 1) / kChunk;
+  p.ntiles = p.npad / kTile;
+  p.nwaves = p.npad / kWave;
+  p.width = s->max_neighbors;
+  p.wrap = p.ncell <= 2;
+  p.mix = s->precision == HDMD_MIXED;
+  const size_t np = (size_t)p.npad, vsz = p.mix ? 4 : 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  p.off_desc = take(sizeof(SysDev));
+  for (int b = 0; b < 2; b++) p.off_x[b] = take(np * p.dp * 8);
+  for (int b = 0; b < 2; b++) p.off_v[b] = take(np * p.d * vsz);
+  for (int b = 0; b < 2; b++) p.off_sig[b] = take(np * 8);
+  for (int b = 0; b < 2; b++) p.off_oid[b] = take(np * 4);
+  p.off_f = take(np * p.d * vsz);
+  p.off_xref = take(np * p.d * 8);
+  p.off_ycell = take(np * p.dy * 4);
+  p.off_cell_of = take(np * 4);
+  p.off_rank = take(np * 4);
+  p.off_cell_count = take((size_t)p.ncells * 4);
+  p.off_cell_local = take((size_t)p.ncells * 4);
+  p.off_chunk_sum = take((size_t)p.nchunks * 4);
+  p.off_chunk_off = take((size_t)p.nchunks * 4);
+  p.off_key = take(np * 4);
+  p.off_src = take(np * 4);
+  p.off_nl = take((size_t)p.width * np * 4);
+  p.off_nlen = take(np * 4);
+  p.off_part = take((size_t)p.nwaves * kPart * 8);
+  p.bytes = o;
+  return HDMD_OK;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
+  SysDev h;
+  std::memset(&h, 0, sizeof(h));
+  h.d = p.d;
+  h.potential = s->potential;
+  h.precision = s->precision;
+  h.n = p.n;
+  h.npad = p.npad;
+  h.ncell = p.ncell;
+  h.radix = p.radix;
+  h.ncells = p.ncells;
+  h.nstencil = p.nstencil;
+  h.width = p.width;
+  h.nchunks = p.nchunks;
+  h.ntiles = p.ntiles;
+  h.mode = MODE_STATIC;
+  h.wrap = p.wrap;
+  h.nwaves = p.nwaves;
+  h.L = s->box_l;
+  h.hL = 0.5 * s->box_l;
+  h.cutoff = s->cutoff;
+  h.skin = s->skin;
+  h.eps = s->epsilon;
+  h.sigma_max = s->sigma_max;
+  h.rlmax = p.rlmax;
+  h.lsc = s->box_l / (double)p.ncell;
+  h.inv_lsc = (double)p.ncell / s->box_l;
+  h.halfskin2 = 0.25 * s->skin * s->skin;
+  // FP32 prefilter radius: the largest list radius enlarged by a relative
+  // 1e-4 plus 1e-5 L, far above the FP32 rounding of offsets from subcell
+  // centres (|y| <= L_sc) and of the box length.
+  const double rf = p.rlmax * (1.0 + 1.0e-4) + 1.0e-5 * s->box_l;
+  h.rl2f = std::nextafter((float)(rf * rf), INFINITY);
+  h.lscf = (float)h.lsc;
+  h.Lf = (float)s->box_l;
+  for (int b = 0; b < 2; b++) {
+    h.x[b] = at<double>(ws, p.off_x[b]);
+    h.v[b] = at<void>(ws, p.off_v[b]);
+    h.sig[b] = at<double>(ws, p.off_sig[b]);
+    h.oid[b] = at<int32_t>(ws, p.off_oid[b]);
+  }
+  h.f = at<void>(ws, p.off_f);
+  h.xref = at<double>(ws, p.off_xref);
+  h.ycell = at<float>(ws, p.off_ycell);
+  h.cell_of = at<int32_t>(ws, p.off_cell_of);
+  h.rank = at<int32_t>(ws, p.off_rank);
+  h.cell_count = at<int32_t>(ws, p.off_cell_count);
+  h.cell_local = at<int32_t>(ws, p.off_cell_local);
+  h.chunk_sum = at<int32_t>(ws, p.off_chunk_sum);
+  h.chunk_off = at<int32_t>(ws, p.off_chunk_off);
+  h.key = at<int32_t>(ws, p.off_key);
+  h.src = at<int32_t>(ws, p.off_src);
+  h.nl = at<int32_t>(ws, p.off_nl);
+  h.nlen = at<int32_t>(ws, p.off_nlen);
+  h.part = at<double>(ws, p.off_part);
+  h.force_rebuild = 1;
+  h.status = SLOT_RUNNING;
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// build-tile autotuner: workgroup size of the list build per (d, wrap,
+// occupancy bucket), chosen by timing every variant on the first build that
+// meets the key.  All variants produce identical lists.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune;
+
+static bool tuning_enabled() {
+  const char* e = std::getenv("HDMD_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+static int occ_bucket(const Plan& p) {
+  double occ = (double)p.n / (double)p.ncells;
+  int b = 0;
+  while (occ >= 2.0 && b < 20) {
+    occ *= 0.5;
+    b++;
+  }
+  return b;
+}
+
+static int default_blk(const Plan& p) {
+  const char* e = std::getenv("HDMD_BUILD_BLK");
+  if (e) return std::atoi(e);
+  double occ = (double)p.n / (double)p.ncells;
+  return occ > 160 ? 256 : (occ > 80 ? 128 : 64);
+}
+
+static int lookup_blk(const Plan& p, bool* known) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find({p.d, (int)p.wrap, occ_bucket(p)});
+  if (it == g_tune.end()) {
+    *known = false;
+    return default_blk(p);
+  }
+  *known = true;
+  return it->second;
+}
+
+extern "C" int hdmd_tuned_blk(int d, int wrap, int bucket) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find({d, wrap, bucket});
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+static inline hipStream_t S(void* st) { return reinterpret_cast<hipStream_t>(st); }
+
+static KArgs single_args(SysDev* dev, int d) {
+  KArgs a;
+  a.single = dev;
+  a.tab = nullptr;
+  a.cls = d;
+  a.part = 0;
+  return a;
+}
+
+// bin -> scan -> scatter -> per-subcell sort/permute -> list build; every
+// kernel exits at once for systems that need no rebuild.
+static void chain_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+  const DKernels* K = dkernels(p.d);
+  KArgs a = single_args(dev, p.d);
+  K->bin(a, p.ntiles, st);
+  launch_scan1(a, p.nchunks, st);
+  launch_scan2(a, 1, st);
+  launch_scatter(a, p.ntiles, st);
+  K->cellsort(p.mix, a, p.ncells, st);
+  K->build(p.wrap, blk, a, p.ncells, st);
+}
+
+static int read_desc(const SysDev* dev, SysDev* host, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(host, dev, sizeof(SysDev), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HDMD_OK;
+}
+
+static int err_to_status(int32_t err, const char* where) {
+  if (err & ERR_NONFINITE) return fail(HDMD_ERR_NONFINITE, std::string(where) + ": non-finite input");
+  if (err & ERR_ARG) return fail(HDMD_ERR_ARG, std::string(where) + ": position outside [-3L/2, 3L/2) or diameter outside (0, sigma_max]");
+  if (err & ERR_OVERFLOW) return fail(HDMD_ERR_NLIST_OVERFLOW, std::string(where) + ": Verlet row longer than max_neighbors");
+  if (err & ERR_RUN_NAN) return fail(HDMD_ERR_NONFINITE, std::string(where) + ": non-finite energy during the run");
+  return HDMD_OK;
+}
+
+// Loads a system into ws and builds its list (the descriptor ends in
+// MODE_STATIC, running, with current buffers holding the sorted state).
+static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
+                       const double* diam, const double* vel, void* ws, size_t ws_bytes,
+                       hipStream_t st, int* blk_out) {
+  if (!pos || !diam || !ws) return fail(HDMD_ERR_ARG, "null device pointer");
+  if (ws_bytes < p.bytes)
+    return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h = make_desc(sys, p, ws);
+  launch_setdesc(dev, h, st);
+  launch_fill_i32(h.cell_count, p.ncells, 0, st);
+  const DKernels* K = dkernels(p.d);
+  K->load(p.mix, dev, p.ntiles, st, pos, diam, vel);
+  bool known = false;
+  int blk = lookup_blk(p, &known);
+  if (!known && tuning_enabled()) {
+    // run the chain up to the build, then time each build variant
+    KArgs a = single_args(dev, p.d);
+    K->bin(a, p.ntiles, st);
+    launch_scan1(a, p.nchunks, st);
+    launch_scan2(a, 1, st);
+    launch_scatter(a, p.ntiles, st);
+    K->cellsort(p.mix, a, p.ncells, st);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_blk = blk;
+    for (int cand : {64, 128, 256}) {
+      K->build(p.wrap, cand, a, p.ncells, st);  // warm-up
+      HIPCHK(hipEventRecord(e0, st));
+      K->build(p.wrap, cand, a, p.ncells, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_blk = cand;
+      }
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    blk = best_blk;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune[{p.d, (int)p.wrap, occ_bucket(p)}] = blk;
+    }
+    K->build(p.wrap, blk, a, p.ncells, st);
+  } else {
+    chain_single(p, dev, st, blk);
+  }
+  launch_finalize(single_args(dev, p.d), 1, st);
+  HIPCHK(hipGetLastError());
+  if (blk_out) *blk_out = blk;
+  return HDMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph cache (chunks of steps / iterations captured once per workspace)
+// ---------------------------------------------------------------------------
+struct GraphKey {
+  void* ws;
+  int kind, chunk, d, mix, wrap, blk, ntiles, ncells, nchunks;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(ws, kind, chunk, d, mix, wrap, blk, ntiles, ncells, nchunks) <
+           std::tie(o.ws, o.kind, o.chunk, o.d, o.mix, o.wrap, o.blk, o.ntiles, o.ncells,
+                    o.nchunks);
+  }
+};
+static std::mutex g_graph_mu;
+static std::map<GraphKey, hipGraphExec_t> g_graphs;
+static hipStream_t g_capture_stream = nullptr;
+
+static bool graphs_enabled() {
+  const char* e = std::getenv("HDMD_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+typedef void (*EnqueueFn)(const Plan& p, SysDev* dev, hipStream_t st, int blk);
+
+static void enqueue_md_step(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+  const DKernels* K = dkernels(p.d);
+  KArgs a = single_args(dev, p.d);
+  K->step(p.mix, a, p.ntiles, st);
+  chain_single(p, dev, st, blk);
+  launch_finalize(a, 1, st);
+}
+
+static void enqueue_fire_iter(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+  const DKernels* K = dkernels(p.d);
+  KArgs a = single_args(dev, p.d);
+  launch_fire_ctrl(a, 1, st);
+  K->fire_update(p.mix, a, p.ntiles, st);
+  chain_single(p, dev, st, blk);
+  launch_finalize(a, 1, st);
+  K->force(p.mix, a, p.ntiles, 1, st);
+}
+
+static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p, SysDev* dev,
+                     hipStream_t st, int blk) {
+  if (!graphs_enabled()) {
+    for (int k = 0; k < chunk; k++) fn(p, dev, st, blk);
+    HIPCHK(hipGetLastError());
+    return HDMD_OK;
+  }
+  GraphKey key{ws, kind, chunk, p.d, (int)p.mix, (int)p.wrap, blk, p.ntiles, p.ncells, p.nchunks};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+    if (!exec) {
+      if (!g_capture_stream) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < chunk; k++) fn(p, dev, g_capture_stream, blk);
+      hipGraph_t graph;
+      HIPCHK(hipStreamEndCapture(g_capture_stream, &graph));
+      HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(graph));
+      g_graphs[key] = exec;
+    }
+  }
+  HIPCHK(hipGraphLaunch(exec, st));
+  return HDMD_OK;
+}
+
+static void set_i32(SysDev* dev, size_t off, int32_t v, hipStream_t st) {
+  launch_fill_i32(reinterpret_cast<int32_t*>(reinterpret_cast<char*>(dev) + off), 1, v, st);
+}
+
+}  // namespace hdmd
+
+using namespace hdmd;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* hdmd_last_error(void) { return g_err.c_str(); }
+
+void hdmd_fire_defaults(hdmd_fire_params* p, double dt0, double f_tol, int64_t max_iter) {
+  p->dt0 = dt0;
+  p->dt_max = 10.0 * dt0;
+  p->dt_min = 0.02 * dt0;
+  p->f_inc = 1.1;
+  p->f_dec = 0.5;
+  p->alpha0 = 0.25;
+  p->f_alpha = 0.99;
+  p->n_delay = 20;
+  p->n_neg_max = 2000;
+  p->max_iter = max_iter;
+  p->initial_delay = 1;
+  p->f_tol = f_tol;
+  p->e_tol = 0.0;
+}
+
+size_t hdmd_workspace_bytes(const hdmd_system* sys) {
+  Plan p;
+  if (make_plan(sys, p) != HDMD_OK) return 0;
+  return p.bytes;
+}
+
+int hdmd_cells_per_axis(const hdmd_system* sys) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  return rc == HDMD_OK ? p.ncell : rc;
+}
+
+int hdmd_build_nlist(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
+                     size_t ws_bytes, int32_t* required_width, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr);
+  if (rc) return rc;
+  SysDev h;
+  rc = read_desc(at<SysDev>(ws, p.off_desc), &h, st);
+  if (rc) return rc;
+  if (required_width) *required_width = h.max_row;
+  return err_to_status(h.err, "hdmd_build_nlist");
+}
+
+int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_t* cols,
+                      int64_t cols_cap, int64_t* nnz, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!ws || !row_ptr || !nnz) return fail(HDMD_ERR_ARG, "null pointer");
+  hipStream_t st = S(stream);
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  if (h.n != p.n || h.d != p.d) return fail(HDMD_ERR_STATE, "workspace holds another system");
+  launch_export(dev, p.n, row_ptr, cols, st, 0);
+  launch_export(dev, p.n, row_ptr, cols, st, 1);
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, row_ptr + p.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *nnz = total;
+  if (total > cols_cap || (total > 0 && !cols))
+    return fail(HDMD_ERR_WORKSPACE, "cols_cap smaller than the entry count");
+  launch_export(dev, p.n, row_ptr, cols, st, 2);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return HDMD_OK;
+}
+
+int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
+                size_t ws_bytes, double* force, double* energy, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!force || !energy) return fail(HDMD_ERR_ARG, "null output pointer");
+  hipStream_t st = S(stream);
+  rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr);
+  if (rc) return rc;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  const DKernels* K = dkernels(p.d);
+  K->force(p.mix, single_args(dev, p.d), p.ntiles, 0, st);
+  launch_reduce_pe(dev, energy, st);
+  K->unload(p.mix, dev, p.ntiles, st, nullptr, nullptr, force);
+  HIPCHK(hipGetLastError());
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  return err_to_status(h.err, "hdmd_forces");
+}
+
+static int step_chunk_len() {
+  const char* e = std::getenv("HDMD_CHUNK");
+  int c = e ? std::atoi(e) : 50;
+  return c < 1 ? 1 : c;
+}
+
+int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
+              size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
+              hdmd_step_stats* stats, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!vel) return fail(HDMD_ERR_ARG, "null velocity pointer");
+  if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HDMD_ERR_ARG, "need nsteps >= 0 and dt > 0");
+  hipStream_t st = S(stream);
+  int blk = 0;
+  rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
+  if (rc) return rc;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  rc = err_to_status(h.err, "hdmd_step");
+  if (rc) {
+    if (stats) stats->max_row = h.max_row;
+    return rc;
+  }
+  const int64_t builds0 = h.builds;
+  // switch the descriptor to MD mode
+  h.mode = MODE_MD;
+  h.dt = dt;
+  h.nsteps = nsteps;
+  h.thermo = thermo;
+  h.thermo_every = thermo_every > 0 ? thermo_every : 0;
+  h.step = 0;
+  launch_setdesc(dev, h, st);
+  // steps 0..nsteps (nsteps+1 force evaluations), in captured chunks
+  const char* prof_env = std::getenv("HDMD_PROFILE");
+  const bool profile = prof_env && prof_env[0] == '1';
+  std::vector<hipEvent_t> ev;
+  if (profile) {
+    // one launch at a time, fused-step and list-build kernels bracketed by events
+    const DKernels* K = dkernels(p.d);
+    KArgs a = single_args(dev, p.d);
+    ev.resize(4 * (size_t)(nsteps + 1));
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int64_t k = 0; k <= nsteps; k++) {
+      HIPCHK(hipEventRecord(ev[4 * k], st));
+      K->step(p.mix, a, p.ntiles, st);
+      HIPCHK(hipEventRecord(ev[4 * k + 1], st));
+      K->bin(a, p.ntiles, st);
+      launch_scan1(a, p.nchunks, st);
+      launch_scan2(a, 1, st);
+      launch_scatter(a, p.ntiles, st);
+      K->cellsort(p.mix, a, p.ncells, st);
+      HIPCHK(hipEventRecord(ev[4 * k + 2], st));
+      K->build(p.wrap, blk, a, p.ncells, st);
+      HIPCHK(hipEventRecord(ev[4 * k + 3], st));
+      launch_finalize(a, 1, st);
+    }
+    HIPCHK(hipGetLastError());
+  } else {
+    const int chunk = step_chunk_len();
+    int64_t todo = nsteps + 1;
+    while (todo > 0) {
+      int c = (int)std::min<int64_t>(chunk, todo);
+      if (c < chunk && graphs_enabled()) c = chunk;  // surplus steps are no-ops once done
+      rc = run_chunk(ws, 1, enqueue_md_step, c, p, dev, st, blk);
+      if (rc) return rc;
+      todo -= c;
+    }
+  }
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  if (stats) {
+    stats->steps_done = h.step > 0 ? h.step - 1 : 0;
+    stats->builds = h.builds - builds0;
+    stats->ke = h.ke;
+    stats->pe = h.pe;
+    stats->max_row = h.max_row;
+    stats->step_kernel_ms = 0;
+    stats->step_kernels = 0;
+    stats->build_kernel_ms = 0;
+    stats->build_kernels = 0;
+    if (profile) {
+      std::vector<float> bt;
+      for (int64_t k = 0; k <= nsteps; k++) {
+        float a = 0, b = 0;
+        HIPCHK(hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]));
+        HIPCHK(hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]));
+        stats->step_kernel_ms += a;
+        stats->step_kernels++;
+        bt.push_back(b);
+      }
+      // the launches that built are the longest ones (the others exit at once)
+      std::sort(bt.begin(), bt.end());
+      const int64_t nb = std::min<int64_t>(stats->builds, (int64_t)bt.size());
+      for (int64_t k = 0; k < nb; k++) stats->build_kernel_ms += bt[bt.size() - 1 - k];
+      stats->build_kernels = nb;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  rc = err_to_status(h.err, "hdmd_step");
+  if (rc) return rc;  // caller arrays untouched
+  dkernels(p.d)->unload(p.mix, dev, p.ntiles, st, pos, vel, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return HDMD_OK;
+}
+
+static void set_fire(SysDev& h, const hdmd_fire_params* fp) {
+  h.mode = MODE_FIRE;
+  h.fc.dt0 = fp->dt0;
+  h.fc.dtmax = fp->dt_max;
+  h.fc.dtmin = fp->dt_min;
+  h.fc.finc = fp->f_inc;
+  h.fc.fdec = fp->f_dec;
+  h.fc.alpha0 = fp->alpha0;
+  h.fc.falpha = fp->f_alpha;
+  h.fc.ftol = fp->f_tol;
+  h.fc.etol = fp->e_tol;
+  h.fc.ndelay = fp->n_delay;
+  h.fc.nnegmax = fp->n_neg_max;
+  h.fc.maxiter = fp->max_iter;
+  h.fc.initdelay = fp->initial_delay;
+  h.fdt = fp->dt0;
+  h.falpha = fp->alpha0;
+  h.npos = 0;
+  h.nneg = 0;
+  h.iters = 0;
+  h.fstatus = 0;
+}
+
+static int check_fire_params(const hdmd_fire_params* fp) {
+  if (!fp) return fail(HDMD_ERR_ARG, "null FIRE parameters");
+  if (!(fp->dt0 > 0) || !(fp->dt_max >= fp->dt0) || !(fp->dt_min > 0) || !(fp->f_tol >= 0) ||
+      fp->max_iter < 0)
+    return fail(HDMD_ERR_ARG, "bad FIRE parameters");
+  return HDMD_OK;
+}
+
+// load + build, switch to FIRE mode, first forces (velocities start at zero)
+static int fire_start(const hdmd_system* sys, const Plan& p, const double* pos, const double* diam,
+                      void* ws, size_t ws_bytes, const hdmd_fire_params* fp, hipStream_t st,
+                      int* blk) {
+  int rc = check_fire_params(fp);
+  if (rc) return rc;
+  rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, blk);
+  if (rc) return rc;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  rc = err_to_status(h.err, "FIRE setup");
+  if (rc) return rc;
+  set_fire(h, fp);
+  launch_setdesc(dev, h, st);
+  dkernels(p.d)->force(p.mix, single_args(dev, p.d), p.ntiles, 1, st);
+  HIPCHK(hipGetLastError());
+  return HDMD_OK;
+}
+
+static void fill_result(const SysDev& h, int64_t builds0, hdmd_fire_result* r) {
+  r->iterations = h.iters;
+  r->builds = h.builds - builds0;
+  r->fmax = h.fmax;
+  r->energy = h.pe;
+  r->status = h.fstatus;
+  r->pad = 0;
+}
+
+int hdmd_fire_minimize(const hdmd_system* sys, double* pos, const double* diam, void* ws,
+                       size_t ws_bytes, const hdmd_fire_params* params, hdmd_fire_result* result,
+                       void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  int blk = 0;
+  rc = fire_start(sys, p, pos, diam, ws, ws_bytes, params, st, &blk);
+  if (rc) return rc;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  const int chunk = step_chunk_len();
+  SysDev h;
+  for (;;) {
+    rc = run_chunk(ws, 2, enqueue_fire_iter, chunk, p, dev, st, blk);
+    if (rc) return rc;
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+    if (h.status != SLOT_RUNNING) break;
+  }
+  if (result) fill_result(h, 0, result);
+  rc = err_to_status(h.err, "hdmd_fire_minimize");
+  if (rc) return rc;
+  dkernels(p.d)->unload(p.mix, dev, p.ntiles, st, pos, nullptr, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return h.fstatus == 0 ? HDMD_OK : HDMD_NOT_CONVERGED;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batches of uneven replicas
+// ===========================================================================
+namespace hdmd {
+
+struct SlotInfo {
+  bool used = false;
+  Plan p;
+  SysDev* dev = nullptr;
+  void* ws = nullptr;
+  int mode = 0;
+  int blk = 64;
+};
+
+struct HostBatch {
+  int max_slots = 0;
+  int64_t cap_atom = 0, cap_cell = 0, cap_chunk = 0;
+  Table* dtab = nullptr;
+  int2* d_atom = nullptr;
+  int2* d_cell = nullptr;
+  int2* d_chunk = nullptr;
+  int32_t* d_syslist = nullptr;
+  int32_t* d_state = nullptr;
+  int64_t* d_iters = nullptr;
+  std::vector<SlotInfo> slots;
+  bool dirty = true;
+  // current composition
+  int n_atom[kMaxD + 1] = {0}, n_cell[kMaxD + 1] = {0}, n_nowrap[kMaxD + 1] = {0};
+  int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};
+  bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
+       has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
+};
+
+static std::mutex g_batch_mu;
+static std::unordered_map<void*, HostBatch*> g_batches;
+
+struct BatchLayout {
+  size_t off_tab, off_atom, off_cell, off_chunk, off_sys, off_state, off_iters, bytes;
+};
+
+static BatchLayout batch_layout(int max_slots, int64_t cap_atom, int64_t cap_cell,
+                                int64_t cap_chunk) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o = align256(o + b);
+    return r;
+  };
+  L.off_tab = take(sizeof(Table));
+  L.off_atom = take((size_t)cap_atom * sizeof(int2));
+  L.off_cell = take((size_t)cap_cell * sizeof(int2));
+  L.off_chunk = take((size_t)cap_chunk * sizeof(int2));
+  L.off_sys = take((size_t)max_slots * 4);
+  L.off_state = take((size_t)max_slots * 4);
+  L.off_iters = take((size_t)max_slots * 8);
+  L.bytes = o;
+  return L;
+}
+
+static void caps(int max_slots, int64_t max_atoms, int64_t max_cells, int64_t& ca, int64_t& cc,
+                 int64_t& ch) {
+  ca = max_atoms / kTile + max_slots;
+  cc = max_cells + max_slots;
+  ch = max_cells / kChunk + max_slots;
+}
+
+static HostBatch* find_batch(void* table_ws) {
+  std::lock_guard<std::mutex> g(g_batch_mu);
+  auto it = g_batches.find(table_ws);
+  return it == g_batches.end() ? nullptr : it->second;
+}
+
+// Rebuilds and uploads the tile tables for the current set of slots.
+static int upload_tables(HostBatch* B, hipStream_t st) {
+  std::vector<int2> atom, cell, chunk;
+  std::vector<int32_t> sys;
+  Table t;
+  std::memset(&t, 0, sizeof(t));
+  t.max_slots = B->max_slots;
+  std::memset(B->n_atom, 0, sizeof(B->n_atom));
+  std::memset(B->n_cell, 0, sizeof(B->n_cell));
+  std::memset(B->n_nowrap, 0, sizeof(B->n_nowrap));
+  B->has_fire = B->has_md = false;
+  for (int d = 0; d <= kMaxD; d++) B->has_wrap[d] = B->has_nowrap[d] = B->mix[d] = false;
+  int64_t atom_base = 0, cell_base = 0;
+  int64_t a_off[kMaxD + 1], c_off[kMaxD + 1];
+  for (int d = kMinD; d <= kMaxD; d++) {
+    a_off[d] = atom_base;
+    c_off[d] = cell_base;
+    int occ_tot = 0, occ_n = 0;
+    for (int s = 0; s < B->max_slots; s++) {
+      const SlotInfo& S = B->slots[s];
+      if (!S.used || S.p.d != d) continue;
+      for (int k = 0; k < S.p.ntiles; k++) atom.push_back(make_int2(s, k));
+      B->n_atom[d] += S.p.ntiles;
+      if (S.p.mix) B->mix[d] = true;
+      occ_tot += S.p.n;
+      occ_n += S.p.ncells;
+    }
+    // cell tiles: systems with n_cell >= 3 first, then the wrap systems
+    for (int pass = 0; pass < 2; pass++) {
+      for (int s = 0; s < B->max_slots; s++) {
+        const SlotInfo& S = B->slots[s];
+        if (!S.used || S.p.d != d || (int)S.p.wrap != pass) continue;
+        for (int k = 0; k < S.p.ncells; k++) cell.push_back(make_int2(s, k));
+        B->n_cell[d] += S.p.ncells;
+        if (pass == 0) B->n_nowrap[d] += S.p.ncells, B->has_nowrap[d] = true;
+        else B->has_wrap[d] = true;
+      }
+    }
+    atom_base += B->n_atom[d];
+    cell_base += B->n_cell[d];
+    double occ = occ_n ? (double)occ_tot / occ_n : 1.0;
+    B->blk[d] = occ > 160 ? 256 : (occ > 80 ? 128 : 64);
+  }
+  for (int s = 0; s < B->max_slots; s++) {
+    const SlotInfo& S = B->slots[s];
+    if (!S.used) continue;
+    for (int k = 0; k < S.p.nchunks; k++) chunk.push_back(make_int2(s, k));
+    sys.push_back(s);
+    t.sys[s] = S.dev;
+    if (S.mode == MODE_FIRE) B->has_fire = true;
+    if (S.mode == MODE_MD) B->has_md = true;
+  }
+  if ((int64_t)atom.size() > B->cap_atom || (int64_t)cell.size() > B->cap_cell ||
+      (int64_t)chunk.size() > B->cap_chunk)
+    return fail(HDMD_ERR_WORKSPACE, "batch table capacity exceeded (max_atoms / max_cells)");
+  B->n_chunk = (int)chunk.size();
+  B->n_sys = (int)sys.size();
+  for (int d = kMinD; d <= kMaxD; d++) {
+    t.n_atom[d] = B->n_atom[d];
+    t.n_cell[d] = B->n_cell[d];
+    t.n_cell_nowrap[d] = B->n_nowrap[d];
+    t.atom_tiles[d] = B->d_atom + a_off[d];
+    t.cell_tiles[d] = B->d_cell + c_off[d];
+  }
+  t.n_chunk = B->n_chunk;
+  t.n_sys = B->n_sys;
+  t.chunk_tiles = B->d_chunk;
+  t.sys_list = B->d_syslist;
+  if (!atom.empty()) HIPCHK(hipMemcpyAsync(B->d_atom, atom.data(), atom.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  if (!cell.empty()) HIPCHK(hipMemcpyAsync(B->d_cell, cell.data(), cell.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  if (!chunk.empty()) HIPCHK(hipMemcpyAsync(B->d_chunk, chunk.data(), chunk.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  if (!sys.empty()) HIPCHK(hipMemcpyAsync(B->d_syslist, sys.data(), sys.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(B->dtab, &t, sizeof(Table), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // host vectors die here
+  B->dirty = false;
+  return HDMD_OK;
+}
+
+static inline int pow2_grid(int n, int cap) {
+  int g = 1;
+  while (g < n && g < cap) g <<= 1;
+  return g;
+}
+
+static KArgs batch_args(HostBatch* B, int d, int part = 0) {
+  KArgs a;
+  a.single = nullptr;
+  a.tab = B->dtab;
+  a.cls = d;
+  a.part = part;
+  return a;
+}
+
+// One iteration over every running slot: FIRE control and update, MD steps,
+// the shared rebuild chain, finalisation, then the FIRE forces.
+static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipStream_t st) {
+  const int gsys = grids[0], gchunk = grids[1];
+  auto ga = [&](int d) { return grids[2 + 3 * (d - kMinD)]; };
+  auto gc = [&](int d) { return grids[3 + 3 * (d - kMinD)]; };
+  KArgs a0 = batch_args(B, 0);
+  if (B->has_fire) {
+    launch_fire_ctrl(a0, gsys, st);
+    for (int d = kMinD; d <= kMaxD; d++)
+      if (B->n_atom[d]) dkernels(d)->fire_update(B->mix[d], batch_args(B, d), ga(d), st);
+  }
+  if (B->has_md)
+    for (int d = kMinD; d <= kMaxD; d++)
+      if (B->n_atom[d]) dkernels(d)->step(B->mix[d], batch_args(B, d), ga(d), st);
+  for (int d = kMinD; d <= kMaxD; d++)
+    if (B->n_atom[d]) dkernels(d)->bin(batch_args(B, d), ga(d), st);
+  launch_scan1(a0, gchunk, st);
+  launch_scan2(a0, gsys, st);
+  for (int d = kMinD; d <= kMaxD; d++)
+    if (B->n_atom[d]) launch_scatter(batch_args(B, d), ga(d), st);
+  for (int d = kMinD; d <= kMaxD; d++)
+    if (B->n_cell[d]) dkernels(d)->cellsort(B->mix[d], batch_args(B, d), gc(d), st);
+  for (int d = kMinD; d <= kMaxD; d++) {
+    if (B->has_nowrap[d]) dkernels(d)->build(false, B->blk[d], batch_args(B, d, 1), gc(d), st);
+    if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
+  }
+  launch_finalize(a0, gsys, st);
+  if (B->has_fire)
+    for (int d = kMinD; d <= kMaxD; d++)
+      if (B->n_atom[d]) dkernels(d)->force(B->mix[d], batch_args(B, d), ga(d), 1, st);
+}
+
+}  // namespace hdmd
+
+extern "C" {
+
+size_t hdmd_batch_bytes(int32_t max_slots, int64_t max_atoms, int64_t max_cells) {
+  if (max_slots < 1 || max_slots > kMaxSlots || max_atoms < 0 || max_cells < 0) return 0;
+  int64_t ca, cc, ch;
+  caps(max_slots, max_atoms, max_cells, ca, cc, ch);
+  return batch_layout(max_slots, ca, cc, ch).bytes;
+}
+
+int hdmd_batch_init(void* table_ws, size_t table_bytes, int32_t max_slots, int64_t max_atoms,
+                    int64_t max_cells, void* stream) {
+  if (!table_ws) return fail(HDMD_ERR_ARG, "null table workspace");
+  if (max_slots < 1 || max_slots > kMaxSlots) return fail(HDMD_ERR_ARG, "max_slots must be in [1, 1024]");
+  int64_t ca, cc, ch;
+  caps(max_slots, max_atoms, max_cells, ca, cc, ch);
+  BatchLayout L = batch_layout(max_slots, ca, cc, ch);
+  if (table_bytes < L.bytes) return fail(HDMD_ERR_WORKSPACE, "table workspace too small");
+  HostBatch* B = new HostBatch();
+  B->max_slots = max_slots;
+  B->cap_atom = ca;
+  B->cap_cell = cc;
+  B->cap_chunk = ch;
+  B->dtab = at<Table>(table_ws, L.off_tab);
+  B->d_atom = at<int2>(table_ws, L.off_atom);
+  B->d_cell = at<int2>(table_ws, L.off_cell);
+  B->d_chunk = at<int2>(table_ws, L.off_chunk);
+  B->d_syslist = at<int32_t>(table_ws, L.off_sys);
+  B->d_state = at<int32_t>(table_ws, L.off_state);
+  B->d_iters = at<int64_t>(table_ws, L.off_iters);
+  B->slots.resize(max_slots);
+  {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    auto it = g_batches.find(table_ws);
+    if (it != g_batches.end()) {
+      for (auto& kv : it->second->graphs) hipGraphExecDestroy(kv.second);
+      delete it->second;
+    }
+    g_batches[table_ws] = B;
+  }
+  return upload_tables(B, S(stream));
+}
+
+static int batch_add(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
+                     const double* vel, const double* diam, void* ws, size_t ws_bytes,
+                     const hdmd_fire_params* fp, int64_t nsteps, double dt, void* stream) {
+  HostBatch* B = find_batch(table_ws);
+  if (!B) return fail(HDMD_ERR_STATE, "batch table not initialised");
+  if (slot < 0 || slot >= B->max_slots) return fail(HDMD_ERR_ARG, "slot out of range");
+  if (B->slots[slot].used) return fail(HDMD_ERR_STATE, "slot is occupied");
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  int blk = 64;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  if (fp) {
+    rc = fire_start(sys, p, pos, diam, ws, ws_bytes, fp, st, &blk);
+    if (rc) return rc;
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+  } else {
+    if (nsteps < 0 || !(dt > 0)) return fail(HDMD_ERR_ARG, "need nsteps >= 0 and dt > 0");
+    if (!vel) return fail(HDMD_ERR_ARG, "null velocity pointer");
+    rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
+    if (rc) return rc;
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+    rc = err_to_status(h.err, "hdmd_batch_add_md");
+    if (rc) return rc;
+    h.mode = MODE_MD;
+    h.dt = dt;
+    h.nsteps = nsteps;
+    h.thermo = nullptr;
+    h.thermo_every = 0;
+    h.step = 0;
+    launch_setdesc(dev, h, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  SlotInfo& S_ = B->slots[slot];
+  S_.used = true;
+  S_.p = p;
+  S_.dev = dev;
+  S_.ws = ws;
+  S_.mode = fp ? MODE_FIRE : MODE_MD;
+  S_.blk = blk;
+  B->dirty = true;
+  return HDMD_OK;
+}
+
+int hdmd_batch_add_fire(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
+                        const double* diam, void* ws, size_t ws_bytes,
+                        const hdmd_fire_params* params, void* stream) {
+  if (!params) return fail(HDMD_ERR_ARG, "null FIRE parameters");
+  return batch_add(table_ws, slot, sys, pos, nullptr, diam, ws, ws_bytes, params, 0, 0.0, stream);
+}
+
+int hdmd_batch_add_md(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
+                      const double* vel, const double* diam, void* ws, size_t ws_bytes,
+                      int64_t nsteps, double dt, void* stream) {
+  return batch_add(table_ws, slot, sys, pos, vel, diam, ws, ws_bytes, nullptr, nsteps, dt, stream);
+}
+
+int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
+  HostBatch* B = find_batch(table_ws);
+  if (!B) return fail(HDMD_ERR_STATE, "batch table not initialised");
+  if (iterations < 1) return fail(HDMD_ERR_ARG, "iterations must be >= 1");
+  hipStream_t st = S(stream);
+  if (B->dirty) {
+    int rc = upload_tables(B, st);
+    if (rc) return rc;
+  }
+  if (B->n_sys == 0) return HDMD_OK;
+  // persistent grids rounded up to powers of two so that a captured graph
+  // stays valid while the composition changes within the same sizes
+  std::vector<int> grids;
+  grids.push_back(pow2_grid(B->n_sys, 1024));
+  grids.push_back(pow2_grid(B->n_chunk, 2048));
+  for (int d = kMinD; d <= kMaxD; d++) {
+    grids.push_back(B->n_atom[d] ? pow2_grid(B->n_atom[d], 4096) : 0);
+    grids.push_back(B->n_cell[d] ? pow2_grid(B->n_cell[d], 8192) : 0);
+    grids.push_back(B->blk[d] * 4 + (B->has_wrap[d] ? 2 : 0) + (B->has_nowrap[d] ? 1 : 0) +
+                    (B->mix[d] ? 1024 : 0));
+  }
+  grids.push_back(B->has_fire ? 1 : 0);
+  grids.push_back(B->has_md ? 1 : 0);
+  grids.push_back(iterations);
+  if (!graphs_enabled()) {
+    for (int k = 0; k < iterations; k++) enqueue_batch_iter(B, grids, st);
+    HIPCHK(hipGetLastError());
+    return HDMD_OK;
+  }
+  hipGraphExec_t exec = nullptr;
+  auto it = B->graphs.find(grids);
+  if (it != B->graphs.end()) exec = it->second;
+  if (!exec) {
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    if (!g_capture_stream) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < iterations; k++) enqueue_batch_iter(B, grids, g_capture_stream);
+    hipGraph_t graph;
+    HIPCHK(hipStreamEndCapture(g_capture_stream, &graph));
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(graph));
+    B->graphs[grids] = exec;
+  }
+  HIPCHK(hipGraphLaunch(exec, st));
+  return HDMD_OK;
+}
+
+int hdmd_batch_poll(void* table_ws, int32_t* state, int64_t* iters, void* stream) {
+  HostBatch* B = find_batch(table_ws);
+  if (!B) return fail(HDMD_ERR_STATE, "batch table not initialised");
+  if (!state) return fail(HDMD_ERR_ARG, "null state array");
+  hipStream_t st = S(stream);
+  if (B->dirty) {
+    int rc = upload_tables(B, st);
+    if (rc) return rc;
+  }
+  launch_poll(B->dtab, B->max_slots, B->d_state, B->d_iters, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(state, B->d_state, (size_t)B->max_slots * 4, hipMemcpyDeviceToHost, st));
+  if (iters) HIPCHK(hipMemcpyAsync(iters, B->d_iters, (size_t)B->max_slots * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HDMD_OK;
+}
+
+int hdmd_batch_take(void* table_ws, int32_t slot, double* pos, double* vel,
+                    hdmd_fire_result* result, void* stream) {
+  HostBatch* B = find_batch(table_ws);
+  if (!B) return fail(HDMD_ERR_STATE, "batch table not initialised");
+  if (slot < 0 || slot >= B->max_slots || !B->slots[slot].used)
+    return fail(HDMD_ERR_STATE, "slot is empty");
+  hipStream_t st = S(stream);
+  SlotInfo& S_ = B->slots[slot];
+  SysDev h;
+  int rc = read_desc(S_.dev, &h, st);
+  if (rc) return rc;
+  if (result) {
+    if (S_.mode == MODE_FIRE) {
+      fill_result(h, 0, result);
+    } else {
+      result->iterations = h.step > 0 ? h.step - 1 : 0;
+      result->builds = h.builds;
+      result->fmax = 0.0;
+      result->energy = h.pe + h.ke;
+      result->status = 0;
+      result->pad = 0;
+    }
+  }
+  int status = err_to_status(h.err, "batch slot");
+  if (status == HDMD_OK && (pos || vel)) {
+    dkernels(S_.p.d)->unload(S_.p.mix, S_.dev, S_.p.ntiles, st, pos, vel, nullptr);
+    HIPCHK(hipGetLastError());
+  }
+  S_.used = false;
+  S_.dev = nullptr;
+  B->dirty = true;
+  rc = upload_tables(B, st);  // the slot's workspace may be released after this call
+  if (rc) return rc;
+  if (status) return status;
+  if (S_.mode == MODE_FIRE && h.fstatus != 0) return HDMD_NOT_CONVERGED;
+  return HDMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+"""Batched uneven replicas: each result in the mix equals the same system run
+alone, bit for bit (FIRE and MD), including slots admitted mid-run."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_12271_amd import hdmd as H
+from paper_2112_12271_amd import inputs
+from tests.gpu_util import dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _fire_case(d, n, phi, seed):
+    sig = inputs.bidisperse(n, 1.0, 1.4, seed)
+    L = inputs.box_for_packing(d, sig, phi)
+    x = inputs.uniform_positions(n, d, L, seed + 1)
+    sysd = H.System(d=d, n=n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0, skin=0.25,
+                    sigma_max=1.4, max_neighbors=64)
+    sysd, _ = H.build_with_width(sysd, dev(x), dev(sig), slack=2.0)
+    return sysd, x, sig
+
+
+def _alone_fire(sysd, x, sig, params):
+    """Runs alone (regrowing the row width if a row overflows) and returns the
+    final positions, result and the width used, which the batch then reuses:
+    the width only sizes the workspace, it does not change any result."""
+    X = dev(x)
+    sysf, res = H.fire_auto(sysd, X, dev(sig), params)
+    return X.cpu().numpy(), res, sysf
+
+
+CASES = [(3, 700, 0.62, 1), (4, 450, 0.44, 2), (5, 900, 0.3, 3), (6, 1300, 0.2, 4),
+         (3, 2500, 0.66, 5), (6, 600, 0.22, 6)]
+
+
+@pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
+def test_fire_mix_equals_alone(prec):
+    params = H.hdmd_fire_defaults(0.05, 1e-10 if prec == H.HDMD_FP64 else 1e-5, 3000)
+    systems = []
+    for d, n, phi, seed in CASES:
+        sysd, x, sig = _fire_case(d, n, phi, seed)
+        sysd.precision = prec
+        systems.append((sysd, x, sig))
+    alone = [_alone_fire(s, x, sig, params) for s, x, sig in systems]
+    systems = [(a[2], x, sig) for a, (s, x, sig) in zip(alone, systems)]
+    B = H.Batch(max_slots=8, max_atoms=20000, max_cells=200000)
+    keep = []
+    for k, (s, x, sig) in enumerate(systems[:4]):
+        ws = H.workspace(s)
+        X, SG = dev(x), dev(sig)
+        keep.append((X, SG))
+        B.hdmd_batch_add_fire(k, s, X, SG, ws, params)
+    done = {}
+    admitted = 4
+    for rnd in range(10000):
+        B.hdmd_batch_run(25)
+        state, iters = B.hdmd_batch_poll()
+        for k in range(8):
+            if state[k] == H.HDMD_SLOT_DONE:
+                pos, _, res = B.hdmd_batch_take(k)
+                done[k if k < 4 else k] = (pos.cpu().numpy(), res)
+        # admit the remaining systems into fresh slots while others run
+        if rnd == 2:
+            for k in range(4, len(systems)):
+                s, x, sig = systems[k]
+                ws = H.workspace(s)
+                X, SG = dev(x), dev(sig)
+                keep.append((X, SG))
+                B.hdmd_batch_add_fire(k, s, X, SG, ws, params)
+            admitted = len(systems)
+        if len(done) == admitted == len(systems):
+            break
+    assert len(done) == len(systems)
+    for k in range(len(systems)):
+        xb, rb = done[k]
+        xa, ra, _ = alone[k]
+        assert rb.iterations == ra.iterations, k
+        assert rb.status == ra.status
+        assert np.array_equal(xb, xa), k
+        assert rb.energy == ra.energy
+
+
+def test_md_mix_equals_alone():
+    cases = [(3, 8, 1.12, 1), (4, 5, 1.1, 2), (6, 4, 1.05, 3)]
+    nsteps, dt = 60, 0.003
+    alone, states = [], []
+    for d, m, a, seed in cases:
+        x, L = inputs.jittered_lattice(d, m, a, 0.12 * a, seed)
+        n = len(x)
+        sig = inputs.bidisperse(n, 1.0, 1.2, seed)
+        v = inputs.gaussian_velocities(n, d, 1.0, seed + 1)
+        sysd = H.System(d=d, n=n, box_l=L, cutoff=inputs.WCA_CUT, skin=0.3, sigma_max=1.2,
+                        max_neighbors=64)
+        sysd, _ = H.build_with_width(sysd, dev(x), dev(sig), slack=2.0)
+        ws = H.workspace(sysd)
+        X, V = dev(x), dev(v)
+        H.hdmd_step(sysd, X, V, dev(sig), ws, nsteps, dt)
+        alone.append((X.cpu().numpy(), V.cpu().numpy()))
+        states.append((sysd, x, v, sig))
+    B = H.Batch(max_slots=4, max_atoms=10000, max_cells=100000)
+    for k, (s, x, v, sig) in enumerate(states):
+        B.hdmd_batch_add_md(k, s, dev(x), dev(v), dev(sig), H.workspace(s), nsteps, dt)
+    for _ in range(100):
+        B.hdmd_batch_run(10)
+        state, iters = B.hdmd_batch_poll()
+        if all(state[k] == H.HDMD_SLOT_DONE for k in range(len(states))):
+            break
+    for k in range(len(states)):
+        pos, vel, res = B.hdmd_batch_take(k, want_vel=True)
+        assert res.iterations == nsteps
+        assert np.array_equal(pos.cpu().numpy(), alone[k][0])
+        assert np.array_equal(vel.cpu().numpy(), alone[k][1])

@@ -1,0 +1,138 @@
+"""GPU Verlet lists against the oracle's definition: bit-exact sets (FP64
+decisions in both precision forms)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2112_12271_amd import hdmd as H
+from paper_2112_12271_amd import inputs
+from tests.gpu_util import csr_equal, gpu_list, partnered
+
+pytestmark = pytest.mark.gpu
+C6 = inputs.WCA_CUT
+
+
+@pytest.mark.parametrize("d", range(2, 11))
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
+def test_list_equals_definition_small(orc, d, nc):
+    c, s = C6, 0.3
+    rlmax = c * 1.4 + s
+    L = nc * rlmax * 1.05 if nc > 1 else max(2.0 * c * 1.4, 1.2 * rlmax)
+    n = int(min(1200, max(64, 3 * nc ** min(d, 4))))
+    x, sig = partnered(d, n, L, 1000 * d + nc, rlmax)
+    ref = orc.nlist_brute(x, sig, L, c, s)
+    for prec in (H.HDMD_FP64, H.HDMD_MIXED):
+        sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4, precision=prec,
+                        max_neighbors=8)
+        got, sysf, _ = gpu_list(sysd, x, sig)
+        assert H.hdmd_cells_per_axis(sysf) <= max(nc, 1) or nc >= 3
+        assert csr_equal(got, ref), (d, nc, prec)
+
+
+def _boundary(d, L, rl, n_pairs, seed):
+    g = np.random.default_rng(seed)
+    h = 0.5 * L
+    xs = []
+    for p in range(n_pairs):
+        a = g.uniform(-h, h, d)
+        if p % 3 == 1:
+            a[g.integers(d)] = -h
+        elif p % 3 == 2:
+            a[:] = np.where(g.uniform(size=d) < 0.5, -h, h - 1e-12)
+        u = g.normal(size=d)
+        u /= np.linalg.norm(u)
+        r = rl + g.integers(-4, 5) * np.spacing(rl)
+        b = a + r * u
+        b = np.where(b >= h, b - L, b)
+        b = np.where(b < -h, b + L, b)
+        b = np.where(b >= h, -h, b)
+        xs += [a, b]
+    return np.array(xs)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 6, 8])
+@pytest.mark.parametrize("nc", [2, 3, 5])
+def test_boundary_band_bit_exact(orc, d, nc):
+    """Pairs at r_l +- a few ulps across subcell and periodic faces and corners."""
+    c, s = 1.0, 0.25
+    rl = c + s
+    L = nc * rl * (1.0 + 4e-9) if nc > 2 else 2.02 * rl
+    x = _boundary(d, L, rl, 200, seed=31 * d + nc)
+    sig = np.ones(len(x))
+    ref = orc.nlist_brute(x, sig, L, c, s)
+    sysd = H.System(d=d, n=len(x), box_l=L, cutoff=c, skin=s, sigma_max=1.0, max_neighbors=8)
+    got, _, _ = gpu_list(sysd, x, sig)
+    assert csr_equal(got, ref)
+
+
+@pytest.mark.parametrize("d,m,kmax", [(3, 6, 4), (4, 5, 4), (6, 4, 2), (8, 3, 2), (10, 3, 1)])
+def test_lattice_shells(d, m, kmax):
+    """Closed-form coordination shells of a lattice filling the periodic box."""
+    x, L = inputs.jittered_lattice(d, m, 1.0, 0.0, 0)
+    c = math.comb
+    shells = {1: 2 * d, 2: 4 * c(d, 2), 3: 8 * c(d, 3), 4: 2 * d + 16 * c(d, 4)}
+    expect = sum(shells[k] for k in range(1, kmax + 1))
+    rl = 0.5 * (math.sqrt(kmax) + math.sqrt(kmax + 1))
+    sysd = H.System(d=d, n=len(x), box_l=L, cutoff=1.0, skin=rl - 1.0, sigma_max=1.0,
+                    max_neighbors=expect + 4)
+    (rp, cols), _, _ = gpu_list(sysd, x, np.ones(len(x)))
+    assert np.all(np.diff(rp) == expect)
+
+
+def test_c1_shape(orc):
+    """C1-shaped input: d=3, N=1000, 50:50 sigma 1.0/1.4 at number density 0.8."""
+    cfg = inputs.C1
+    sig = cfg.diameters()
+    L = cfg.box(sig)
+    x = cfg.positions(L)
+    ref = orc.nlist_cells(x, sig, L, C6, cfg.skin)
+    sysd = H.System(d=3, n=cfg.n, box_l=L, cutoff=C6, skin=cfg.skin, sigma_max=1.4)
+    got, _, _ = gpu_list(sysd, x, sig)
+    assert csr_equal(got, ref)
+
+
+def test_d4_4096(orc):
+    d, n = 4, 4096
+    sig = np.ones(n)
+    L = inputs.box_for_packing(d, sig, 0.4)
+    x = inputs.uniform_positions(n, d, L, 4)
+    ref = orc.nlist_cells(x, sig, L, C6, 0.3)
+    got, _, _ = gpu_list(H.System(d=d, n=n, box_l=L, cutoff=C6, skin=0.3, sigma_max=1.0), x, sig)
+    assert csr_equal(got, ref)
+
+
+def test_one_big_subcell_global_sort(orc):
+    """n_cell = 1 with 6000 atoms: the subcell sort and the row export take their
+    global-memory paths (more than 4096 entries)."""
+    d, n, L = 2, 6000, 2.6
+    x = inputs.uniform_positions(n, d, L, 8)
+    sig = np.full(n, 1.0)
+    ref = orc.nlist_brute(x, sig, L, 1.0, 0.4)
+    sysd = H.System(d=d, n=n, box_l=L, cutoff=1.0, skin=0.4, sigma_max=1.0,
+                    potential=H.HDMD_HARMONIC, max_neighbors=6000)
+    assert H.hdmd_cells_per_axis(sysd) == 1
+    got, _, _ = gpu_list(sysd, x, sig)
+    assert csr_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_full_size_sampled_rows(orc, name):
+    """Full-size C3 (d=6, N=262144) and C5 (d=8, N=131072, n_cell = 2) inputs:
+    sampled rows against the definition, plus list symmetry as a whole."""
+    cfg = inputs.CONFIGS[name]
+    sig = cfg.diameters()
+    L = cfg.box(sig)
+    x = cfg.positions(L)
+    width = 320 if name == "c3" else 1600
+    sysd = H.System(d=cfg.d, n=cfg.n, box_l=L, cutoff=C6, skin=cfg.skin,
+                    sigma_max=float(sig.max()), max_neighbors=width)
+    (rp, cols), sysf, _ = gpu_list(sysd, x, sig)
+    g = np.random.default_rng(1)
+    for i in g.choice(cfg.n, 24, replace=False):
+        ref = orc.nlist_row(x, sig, L, C6, cfg.skin, int(i))
+        assert np.array_equal(cols[rp[i]:rp[i + 1]], ref), i
+    rows = np.repeat(np.arange(cfg.n), np.diff(rp))
+    fwd = rows.astype(np.int64) * cfg.n + cols
+    bwd = cols.astype(np.int64) * cfg.n + rows
+    assert np.array_equal(np.sort(fwd), np.sort(bwd))

@@ -1,0 +1,87 @@
+"""GPU velocity Verlet against the oracle over short horizons, determinism,
+and energy conservation."""
+import numpy as np
+import pytest
+
+from paper_2112_12271_amd import hdmd as H
+from paper_2112_12271_amd import inputs
+from tests.gpu_util import dev
+
+pytestmark = pytest.mark.gpu
+C6 = inputs.WCA_CUT
+
+
+def _state(d, m, a, seed, T=1.0):
+    x, L = inputs.jittered_lattice(d, m, a, 0.12 * a, seed)
+    n = len(x)
+    sig = inputs.bidisperse(n, 1.0, 1.2, seed)
+    v = inputs.gaussian_velocities(n, d, T, seed + 1)
+    return x, v, sig, L
+
+
+def _run_gpu(sysd, x, v, sig, nsteps, dt, every=1):
+    X, V = dev(x), dev(v)
+    _, st, th = H.step_auto(sysd, X, V, dev(sig), nsteps, dt, every)
+    return X.cpu().numpy(), V.cpu().numpy(), th.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("d,m,a,skin", [(3, 8, 1.12, 0.3), (4, 5, 1.1, 0.3), (6, 4, 1.05, 0.25),
+                                        (8, 3, 1.0, 0.25)])
+def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
+    x, v, sig, L = _state(d, m, a, 3 * d)
+    nsteps, dt = 100, 0.004
+    xo, vo, tho, bo = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt)
+    sysd = H.System(d=d, n=len(x), box_l=L, cutoff=C6, skin=skin, sigma_max=1.2)
+    xg, vg, thg, st = _run_gpu(sysd, x, v, sig, nsteps, dt)
+    dx = xg - xo
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-8
+    assert np.allclose(thg[:, 1], tho[:, 0], rtol=1e-10, atol=1e-12)
+    assert np.allclose(thg[:, 2], tho[:, 1], rtol=1e-10, atol=1e-12)
+    assert st.steps_done == nsteps
+    assert st.builds + 1 == bo          # the oracle counts the initial build too
+
+
+def test_mixed_precision_short_trajectory(orc):
+    x, v, sig, L = _state(3, 8, 1.12, 5)
+    nsteps, dt = 100, 0.004
+    xo, vo, tho, _ = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, nsteps, dt)
+    sysd = H.System(d=3, n=len(x), box_l=L, cutoff=C6, skin=0.3, sigma_max=1.2,
+                    precision=H.HDMD_MIXED)
+    xg, vg, thg, _ = _run_gpu(sysd, x, v, sig, nsteps, dt)
+    dx = xg - xo
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < 1e-4
+    etot_o = tho.sum(axis=1)
+    assert np.abs(thg[:, 3] - etot_o).max() < 1e-4 * abs(etot_o[0])
+
+
+def test_deterministic():
+    x, v, sig, L = _state(6, 4, 1.05, 9)
+    sysd = H.System(d=6, n=len(x), box_l=L, cutoff=C6, skin=0.25, sigma_max=1.2)
+    a = _run_gpu(sysd, x, v, sig, 120, 0.003)
+    b = _run_gpu(sysd, x, v, sig, 120, 0.003)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+
+
+def test_c1_energy_conservation():
+    """C1 shape (d=3, N=1000, rho=0.8, 1000 steps of dt=0.005) from a relaxed
+    start: the total energy stays within 1e-3 of its magnitude per atom."""
+    cfg = inputs.C1
+    sig = cfg.diameters()
+    L = cfg.box(sig)
+    x0 = cfg.positions(L)
+    sysh = H.System(d=3, n=cfg.n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0, skin=cfg.skin,
+                    sigma_max=1.4)
+    sysh, ws = H.build_with_width(sysh, dev(x0), dev(sig))
+    X = dev(x0)
+    H.hdmd_fire_minimize(sysh, X, dev(sig), ws, H.hdmd_fire_defaults(0.05, 1e-6, 20000))
+    v = cfg.velocities()
+    sysd = H.System(d=3, n=cfg.n, box_l=L, cutoff=C6, skin=cfg.skin, sigma_max=1.4)
+    xg, vg, th, st = _run_gpu(sysd, X.cpu().numpy(), v, sig, cfg.steps, cfg.dt, every=10)
+    e = th[:, 3] / cfg.n
+    assert np.isfinite(e).all()
+    assert np.abs(e - e[0]).max() < 1e-3 * max(1.0, abs(e[0]))
+    assert st.builds >= 1
