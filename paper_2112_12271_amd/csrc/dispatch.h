@@ -12,9 +12,11 @@ struct DKernels {
                  double* force);
   void (*bin)(const KArgs& a, int grid, hipStream_t st);
   void (*cellsort)(bool mix, const KArgs& a, int grid, hipStream_t st);
+  // blk: workgroup size of the home-atom-lane build (64/128/256), or 1 for the
+  // candidate-lane build (n_cell >= 3 only)
   void (*build)(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st);
-  void (*force)(bool mix, const KArgs& a, int grid, int fire, hipStream_t st);
-  void (*step)(bool mix, const KArgs& a, int grid, hipStream_t st);
+  void (*force)(bool mix, int lpa, const KArgs& a, int grid, int fire, hipStream_t st);
+  void (*step)(bool mix, int lpa, const KArgs& a, int grid, hipStream_t st);
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
 };
 

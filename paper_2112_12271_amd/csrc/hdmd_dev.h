@@ -1,16 +1,23 @@
 // hdmd_dev.h -- device-side data structures and helpers of the HIP hot path.
 //
 // Internal layout of one system (all in the caller's workspace):
-//   x[2]      positions, atom-major (AoS) [npad][DP] FP64, DP = d rounded up to
-//             even so an atom is whole 16-byte loads; double-buffered
-//             (a step reads x[cur] and writes x[cur^1]).
+//   x[2]      atom records [npad][DR] FP64: the d coordinates, the diameter,
+//             zero padding; DR = 4, 8 or 16 doubles so that a record is whole
+//             16-byte loads and never straddles more cache lines than needed
+//             (one 64-byte half line for 4 <= d <= 7).  Double-buffered: a
+//             step reads x[cur] and writes x[cur^1].
+//   q[2]      (mixed precision only) the same records as 32-bit fixed-point
+//             coordinates u = (x + L/2) 2^32 / L and the FP32 diameter,
+//             [npad][DQ] int32; u_j - u_i in two's complement is the
+//             minimum-image displacement, so gathers carry half the bytes.
 //   v[2]      velocities, axis-major (SoA) [d][npad], FP64 or FP32.
-//   sig[2], oid[2]  diameter and caller id of each slot; the [2] buffers are
-//             the source and destination of the permutation at a rebuild.
+//   oid[2]    caller id of each slot; the [2] buffers of v and oid are the
+//             source and destination of the permutation at a rebuild.
 //   f         forces [d][npad] (FP64 or FP32), written by the force kernels.
 //   xref      positions at the last build [d][npad] FP64 (rebuild trigger).
-//   ycell     FP32 offsets of each atom from its subcell centre [npad][DY],
-//             DY = d rounded up to a multiple of 4 (prefilter of the build).
+//   qc        offsets from the subcell centre quantised to int8 in units of
+//             L_sc/250, packed four per int32 (prefilter of the list build
+//             when n_cell >= 3); ycell the same offsets in FP32 (n_cell <= 2).
 //   nl, nlen  Verlet rows in ELL form, column-major nl[k*npad + i], i.e. entry
 //             k of every row is contiguous so a wave reads it coalesced.
 // Atoms are stored in subcell order (canonical: by subcell, then caller id),
@@ -25,13 +32,14 @@ namespace hdmd {
 
 constexpr int kMaxD = 10;
 constexpr int kMinD = 2;
-constexpr int kTile = 256;      // atoms per atom tile = threads per workgroup
+constexpr int kTile = 64;       // atoms per atom tile (one wave at one lane per atom)
 constexpr int kWave = 64;
 constexpr int kChunk = 1024;    // subcells per scan chunk
 constexpr int kSortCap = 4096;  // subcell occupancy sorted in LDS (larger: in global memory)
 constexpr int kPart = 8;        // doubles per wave in the partial-sum array
 constexpr int kMaxSlots = 1024;
 constexpr int kQCap = 16;       // per-lane prefilter queue of the build
+constexpr int kQScale = 250;    // int8 quantisation: subcell side = 250 units
 
 enum Mode : int32_t { MODE_NONE = 0, MODE_FIRE = 1, MODE_MD = 2, MODE_STATIC = 3 };
 enum Slot : int32_t { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };
@@ -57,17 +65,22 @@ struct SysDev {
   int32_t mode, wrap, nwaves, pad0;
   double L, hL, cutoff, skin, eps, sigma_max;
   double rlmax, lsc, inv_lsc, halfskin2;
-  float rl2f, lscf, Lf, pad1;
+  double fxscale, qinv;  // 2^32 / L; 250 / L_sc
+  float rl2f, lscf, Lf, fxinv;  // fxinv = L / 2^32
+  int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
+                         // (squared quantised units)
   double* x[2];
+  int32_t* q[2];
   void* v[2];
-  double* sig[2];
   int32_t* oid[2];
   void* f;
   double* xref;
   float* ycell;
+  int32_t* qc;
   int32_t* cell_of;
   int32_t* rank;
   int32_t* cell_count;
+  int32_t* cell_flat;  // start of every subcell, [ncells + 1], written at each rebuild
   int32_t* cell_local;
   int32_t* chunk_sum;
   int32_t* chunk_off;
@@ -197,33 +210,80 @@ __device__ inline double min_image(double dx, double L, double h) {
 
 template <int D>
 struct Dims {
-  static constexpr int DP = (D + 1) & ~1;  // FP64 AoS stride
-  static constexpr int DY = (D + 3) & ~3;  // FP32 AoS stride
+  static constexpr int DR = D <= 3 ? 4 : (D <= 7 ? 8 : 16);  // FP64 record stride (doubles)
+  static constexpr int NR = (D + 2) / 2;                      // double2 loads per record
+  static constexpr int DQ = D <= 3 ? 4 : (D <= 7 ? 8 : 16);  // fixed-point record stride (ints)
+  static constexpr int NQ = (D + 4) / 4;                      // int4 loads per record
+  static constexpr int DY = (D + 3) & ~3;                     // FP32 offset stride
+  static constexpr int QW = (D + 3) / 4;                      // int8x4 words of the offsets
 };
 
+// record = (x_0 .. x_{D-1}, sigma, 0 ...)
 template <int D>
-__device__ inline void load_x(const double* __restrict__ xb, int i, double (&x)[D]) {
-  constexpr int DP = Dims<D>::DP;
-  const double2* p = reinterpret_cast<const double2*>(xb + (size_t)i * DP);
+__device__ inline void load_rec(const double* __restrict__ xb, int i, double (&x)[D], double& sg) {
+  const double2* p = reinterpret_cast<const double2*>(xb + (size_t)i * Dims<D>::DR);
 #pragma unroll
-  for (int k = 0; k < DP / 2; k++) {
+  for (int k = 0; k < Dims<D>::NR; k++) {
     double2 t = p[k];
-    x[2 * k] = t.x;
+    if (2 * k < D) x[2 * k] = t.x;
+    else sg = t.x;
     if (2 * k + 1 < D) x[2 * k + 1] = t.y;
+    else if (2 * k + 1 == D) sg = t.y;
   }
 }
 
 template <int D>
-__device__ inline void store_x(double* __restrict__ xb, int i, const double (&x)[D]) {
-  constexpr int DP = Dims<D>::DP;
-  double2* p = reinterpret_cast<double2*>(xb + (size_t)i * DP);
+__device__ inline void load_x(const double* __restrict__ xb, int i, double (&x)[D]) {
+  double sg;
+  load_rec<D>(xb, i, x, sg);
+}
+
+template <int D>
+__device__ inline void store_rec(double* __restrict__ xb, int i, const double (&x)[D], double sg) {
+  double2* p = reinterpret_cast<double2*>(xb + (size_t)i * Dims<D>::DR);
 #pragma unroll
-  for (int k = 0; k < DP / 2; k++) {
+  for (int k = 0; k < Dims<D>::NR; k++) {
     double2 t;
-    t.x = x[2 * k];
-    t.y = (2 * k + 1 < D) ? x[2 * k + 1] : 0.0;
+    t.x = 2 * k < D ? x[2 * k] : (2 * k == D ? sg : 0.0);
+    t.y = 2 * k + 1 < D ? x[2 * k + 1] : (2 * k + 1 == D ? sg : 0.0);
     p[k] = t;
   }
+}
+
+// fixed-point record = (u_0 .. u_{D-1}, float bits of sigma, 0 ...)
+__device__ inline int32_t to_fixed(double x, double hL, double scale) {
+  return (int32_t)(uint32_t)(long long)rint((x + hL) * scale);
+}
+
+template <int D>
+__device__ inline void store_q(int32_t* __restrict__ qb, int i, const double (&x)[D], double sg,
+                               double hL, double scale) {
+  int v[4 * Dims<D>::NQ];
+#pragma unroll
+  for (int k = 0; k < 4 * Dims<D>::NQ; k++) v[k] = 0;
+#pragma unroll
+  for (int k = 0; k < D; k++) v[k] = to_fixed(x[k], hL, scale);
+  v[D] = __float_as_int((float)sg);
+  int4* p = reinterpret_cast<int4*>(qb + (size_t)i * Dims<D>::DQ);
+#pragma unroll
+  for (int k = 0; k < Dims<D>::NQ; k++) p[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+
+template <int D>
+__device__ inline void load_q(const int32_t* __restrict__ qb, int i, int (&u)[D], float& sg) {
+  const int4* p = reinterpret_cast<const int4*>(qb + (size_t)i * Dims<D>::DQ);
+  int v[4 * Dims<D>::NQ];
+#pragma unroll
+  for (int k = 0; k < Dims<D>::NQ; k++) {
+    int4 t = p[k];
+    v[4 * k] = t.x;
+    v[4 * k + 1] = t.y;
+    v[4 * k + 2] = t.z;
+    v[4 * k + 3] = t.w;
+  }
+#pragma unroll
+  for (int k = 0; k < D; k++) u[k] = v[k];
+  sg = __int_as_float(v[D]);
 }
 
 // Squared minimum-image distance accumulated axis by axis with a fused

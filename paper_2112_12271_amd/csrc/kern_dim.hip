@@ -23,8 +23,8 @@ void l_unload(bool mix, const SysDev* s, int grid, hipStream_t st, double* pos, 
 }
 void l_bin(const KArgs& a, int grid, hipStream_t st) { k_bin<D><<<grid, kTile, 0, st>>>(a); }
 void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
-  if (mix) k_cellsort<D, float><<<grid, kTile, 0, st>>>(a);
-  else k_cellsort<D, double><<<grid, kTile, 0, st>>>(a);
+  if (mix) k_cellsort<D, float><<<grid, 256, 0, st>>>(a);
+  else k_cellsort<D, double><<<grid, 256, 0, st>>>(a);
 }
 void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
   if (wrap) {
@@ -32,18 +32,41 @@ void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
     else if (blk <= 128) k_build<D, true, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, true, 256><<<grid, 256, 0, st>>>(a);
   } else {
-    if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
+    if (blk == 1) k_build_t<D><<<grid, 64, 0, st>>>(a);
+    else if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);
   }
 }
-void l_force(bool mix, const KArgs& a, int grid, int fire, hipStream_t st) {
-  if (mix) k_force<D, true><<<grid, kTile, 0, st>>>(a, fire);
-  else k_force<D, false><<<grid, kTile, 0, st>>>(a, fire);
+template <bool MIX, int LPA>
+void force_lpa(const KArgs& a, int grid, int fire, hipStream_t st) {
+  k_force<D, MIX, LPA><<<grid, kTile * LPA, 0, st>>>(a, fire);
 }
-void l_step(bool mix, const KArgs& a, int grid, hipStream_t st) {
-  if (mix) k_step<D, true><<<grid, kTile, 0, st>>>(a);
-  else k_step<D, false><<<grid, kTile, 0, st>>>(a);
+template <bool MIX, int LPA>
+void step_lpa(const KArgs& a, int grid, hipStream_t st) {
+  k_step<D, MIX, LPA><<<grid, kTile * LPA, 0, st>>>(a);
+}
+void l_force(bool mix, int lpa, const KArgs& a, int grid, int fire, hipStream_t st) {
+  if (mix) {
+    if (lpa >= 4) force_lpa<true, 4>(a, grid, fire, st);
+    else if (lpa == 2) force_lpa<true, 2>(a, grid, fire, st);
+    else force_lpa<true, 1>(a, grid, fire, st);
+  } else {
+    if (lpa >= 4) force_lpa<false, 4>(a, grid, fire, st);
+    else if (lpa == 2) force_lpa<false, 2>(a, grid, fire, st);
+    else force_lpa<false, 1>(a, grid, fire, st);
+  }
+}
+void l_step(bool mix, int lpa, const KArgs& a, int grid, hipStream_t st) {
+  if (mix) {
+    if (lpa >= 4) step_lpa<true, 4>(a, grid, st);
+    else if (lpa == 2) step_lpa<true, 2>(a, grid, st);
+    else step_lpa<true, 1>(a, grid, st);
+  } else {
+    if (lpa >= 4) step_lpa<false, 4>(a, grid, st);
+    else if (lpa == 2) step_lpa<false, 2>(a, grid, st);
+    else step_lpa<false, 1>(a, grid, st);
+  }
 }
 void l_fire_update(bool mix, const KArgs& a, int grid, hipStream_t st) {
   if (mix) k_fire_update<D, true><<<grid, kTile, 0, st>>>(a);

@@ -2,16 +2,14 @@
 //
 //  k_load        caller [n][d] arrays -> internal buffers (wrap, validate)
 //  k_bin         subcell of every atom + occupancy counts      (Sec. II.C)
-//  k_scatter     counting-sort placement by subcell
+//  k_scatter     counting-sort placement by subcell            (common.hip)
 //  k_cellsort    per-subcell sort by caller id, permutation of every per-atom
-//                array, reference positions, FP32 subcell offsets
+//                array, reference positions, prefilter offsets
 //  k_build       Verlet rows over the 3^d linked subcells      (Sec. II.C, Fig. 1)
-//  k_force       pair forces and energy                        (Sec. II.B)
+//  k_force       pair forces and energy (+ FIRE reductions)    (Sec. II.B)
 //  k_step        fused velocity-Verlet step + rebuild trigger (Sec. II.B/II.C)
-//  k_fire_force  forces + FIRE reductions                      (Sec. II.B, FIRE 2.0)
 //  k_fire_update semi-implicit Euler FIRE update
 //  k_unload      internal -> caller order
-//  k_export_*    canonical CSR export of the list
 #pragma once
 #include "hdmd_dev.h"
 
@@ -36,8 +34,7 @@ __global__ __launch_bounds__(kTile) void k_load(SysDev* s, const double* __restr
       x[k] = 0.0;
       vo[(size_t)k * npad + i] = VT(0);
     }
-    store_x<D>(xo, i, x);
-    s->sig[pc][i] = 0.0;
+    store_rec<D>(xo, i, x, 0.0);
     s->oid[pc][i] = -1;
     return;
   }
@@ -61,11 +58,14 @@ __global__ __launch_bounds__(kTile) void k_load(SysDev* s, const double* __restr
     }
     vo[(size_t)k * npad + i] = VT(u);
   }
-  store_x<D>(xo, i, x);
   double sg = diam[i];
-  if (!isfinite(sg)) err |= ERR_NONFINITE;
-  else if (!(sg > 0.0) || sg > s->sigma_max) err |= ERR_ARG;
-  s->sig[pc][i] = sg;
+  if (!isfinite(sg)) {
+    err |= ERR_NONFINITE;
+    sg = 0.0;
+  } else if (!(sg > 0.0) || sg > s->sigma_max) {
+    err |= ERR_ARG;
+  }
+  store_rec<D>(xo, i, x, sg);
   s->oid[pc][i] = i;
   if (err) atomicOr(&s->err, err);
 }
@@ -164,9 +164,17 @@ __device__ inline void bitonic_sort(int* keys, int* vals, int cnt) {
   }
 }
 
+// int8 offset from the subcell centre in units of L_sc / 250; |y| <= L_sc/2
+// up to binning rounding, so |q| <= 125 and the clamp never bites.
+__device__ inline int quant8(double y, double qinv) {
+  int q = (int)rint(y * qinv);
+  return q < -127 ? -127 : (q > 127 ? 127 : q);
+}
+
 template <int D, typename VT>
-__global__ __launch_bounds__(kTile) void k_cellsort(KArgs a) {
-  constexpr int DY = Dims<D>::DY;
+__global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
+  constexpr int DY = Dims<D>::DY, QW = Dims<D>::QW;
+  constexpr bool MIX = sizeof(VT) == 4;
   __shared__ int sk[kSortCap];
   __shared__ int sv[kSortCap];
   for (int t = blockIdx.x;; t += gridDim.x) {
@@ -175,7 +183,11 @@ __global__ __launch_bounds__(kTile) void k_cellsort(KArgs a) {
     if (!fetch_cell_tile(a, t, s, c)) break;
     if (!running(s) || !need_rebuild(s)) continue;
     const int s0 = cell_start(s, c), cnt = cell_start(s, c + 1) - s0;
-    if (threadIdx.x == 0) s->cell_count[c] = 0;  // ready for the next build
+    if (threadIdx.x == 0) {
+      s->cell_count[c] = 0;  // ready for the next build
+      s->cell_flat[c] = s0;
+      if (c == s->ncells - 1) s->cell_flat[s->ncells] = s->n;
+    }
     if (cnt == 0) continue;
     int* keys;
     int* vals;
@@ -204,26 +216,37 @@ __global__ __launch_bounds__(kTile) void k_cellsort(KArgs a) {
       }
     }
     const int cur = s->xcur, pc = s->pcur, pn = pc ^ 1, npad = s->npad;
+    const bool wrap = s->wrap != 0;
     const VT* vin = reinterpret_cast<const VT*>(s->v[pc]);
     VT* vout = reinterpret_cast<VT*>(s->v[pn]);
     for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
       const int src = vals[q], dst = s0 + q;
-      double x[D];
-      load_x<D>(s->x[cur ^ 1], src, x);
-      store_x<D>(s->x[cur], dst, x);
-      float y[DY];
-#pragma unroll
-      for (int k = 0; k < DY; k++) y[k] = 0.0f;
+      double x[D], sg;
+      load_rec<D>(s->x[cur ^ 1], src, x, sg);
+      store_rec<D>(s->x[cur], dst, x, sg);
+      if (MIX) store_q<D>(s->q[cur], dst, x, sg, s->hL, s->fxscale);
 #pragma unroll
       for (int k = 0; k < D; k++) {
         s->xref[(size_t)k * npad + dst] = x[k];
-        y[k] = (float)(x[k] - cen[k]);
         vout[(size_t)k * npad + dst] = vin[(size_t)k * npad + src];
       }
-      float4* yp = reinterpret_cast<float4*>(s->ycell + (size_t)dst * DY);
+      if (wrap) {
+        float y[DY];
 #pragma unroll
-      for (int k = 0; k < DY / 4; k++) yp[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
-      s->sig[pn][dst] = s->sig[pc][src];
+        for (int k = 0; k < DY; k++) y[k] = k < D ? (float)(x[k] - cen[k]) : 0.0f;
+        float4* yp = reinterpret_cast<float4*>(s->ycell + (size_t)dst * DY);
+#pragma unroll
+        for (int k = 0; k < DY / 4; k++) yp[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
+      } else {
+        int w[QW];
+#pragma unroll
+        for (int k = 0; k < QW; k++) w[k] = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++)
+          w[k / 4] |= (quant8(x[k] - cen[k], s->qinv) & 0xff) << (8 * (k % 4));
+#pragma unroll
+        for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
+      }
       s->oid[pn][dst] = keys[q];
     }
     __syncthreads();
@@ -233,24 +256,50 @@ __global__ __launch_bounds__(kTile) void k_cellsort(KArgs a) {
 // ---------------------------------------------------------------------------
 // Verlet-list build over the linked subcells (Sec. II.C, Fig. 1)
 //
-// One workgroup per home subcell; its atoms are the lanes.  The linked
-// subcells are decoded on the fly from a mixed-radix counter (offsets -1/0/+1
-// per axis, or the deduplicated {0,+1} / {0} when n_cell is 2 / 1).  Each
-// linked subcell's FP32 offsets-from-centre are staged in LDS and every lane
-// tests every staged atom with a conservative FP32 prefilter (r^2 against the
-// largest list radius, enlarged far beyond FP32 rounding).  Survivors go to a
-// per-lane LDS queue and are re-tested exactly in FP64 with the per-pair
-// radius -- the same operation sequence as the list definition -- before
-// being appended to the row.  Row order: linked-subcell order, then slot
-// order, which makes the list deterministic.
-// With n_cell >= 3 the image shift of a linked subcell is its offset times the
-// subcell side (exact for every pair within the list radius); with n_cell <= 2
-// the per-axis minimum image is taken in the prefilter instead (WRAP).
+// One workgroup per home subcell; its atoms are the lanes (in chunks of BLK).
+// The linked subcells are decoded on the fly from a mixed-radix counter
+// (offsets -1/0/+1 per axis, or the deduplicated {0,+1} / {0} when n_cell is 2
+// / 1).  Each linked subcell's atoms are staged in LDS and every lane tests
+// every staged atom with a conservative prefilter; survivors go to a per-lane
+// LDS queue and are re-tested exactly in FP64 with the per-pair radius -- the
+// operation sequence of the list definition -- before being appended to the
+// row.  Row order: linked-subcell order, then slot order (deterministic).
+//
+// Prefilter, n_cell >= 3: the image shift of a linked subcell is its offset
+// times the subcell side for every pair within the list radius, so with
+// offsets y from the subcell centres quantised to q = y/Delta (Delta =
+// L_sc/250, shift D = 250 o exactly), |r - Delta |q_j + D - q_i|| <= Delta
+// sqrt(d) and
+//   |q_j + D - q_i|^2 = A_j + C_i - 2 q_i.q_j,  A_j = |q_j + D|^2,
+//   C_i = |q_i|^2 - 2 q_i.D,
+// where q_i.q_j is two or three packed int8 dot products (v_dot4_i32_i8);
+// a pair survives when that is below ((r_l,max + Delta sqrt(d)) / Delta)^2.
+// Prefilter, n_cell <= 2: FP32 offsets with the per-axis minimum image
+// min(|u|, L - |u|), against the largest list radius enlarged by 1e-4.
 // ---------------------------------------------------------------------------
+template <int D>
+__device__ inline void decode_linked(int q, int radix, int nc, const int (&ci)[D], int (&o)[D],
+                                     int (&cj)[D]) {
+#pragma unroll
+  for (int k = D - 1; k >= 0; k--) {
+    int dig = q % radix;
+    q /= radix;
+    int oo = (radix == 3) ? dig - 1 : dig;
+    int c2 = ci[k] + oo;
+    c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
+    cj[k] = c2;
+    o[k] = (radix == 3) ? oo : c2 - ci[k];
+  }
+}
+
+__device__ inline int sext8(int w, int k) { return (int)(signed char)((w >> (8 * k)) & 0xff); }
+
 template <int D, bool WRAP, int BLK>
 __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
-  constexpr int DY = Dims<D>::DY;
-  __shared__ float ys[BLK * DY];
+  constexpr int DY = Dims<D>::DY, QW = Dims<D>::QW;
+  constexpr int SW = WRAP ? DY : 4;  // staged words per candidate
+  constexpr int UNR = WRAP ? 4 : 8;  // candidates tested per batch of LDS reads
+  __shared__ float stage[BLK * SW];
   __shared__ int qbuf[kQCap * BLK];
   const int tid = threadIdx.x;
   for (int t = blockIdx.x;; t += gridDim.x) {
@@ -262,13 +311,11 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
     if (h0 == h1) continue;
     const int nc = s->ncell, radix = s->radix, nst = s->nstencil, npad = s->npad;
     const int W = s->width;
-    const int pn = s->pcur ^ 1;
     const double* __restrict__ xb = s->x[s->xcur];
-    const double* __restrict__ sg = s->sig[pn];
-    const float* __restrict__ yc = s->ycell;
     int* __restrict__ nl = s->nl;
     const double L = s->L, hL = s->hL, cut = s->cutoff, skin = s->skin;
     const float lscf = s->lscf, Lf = s->Lf, rl2f = s->rl2f;
+    const int tq = s->tq;
     int ci[D];
     {
       int u = hc;
@@ -283,21 +330,31 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
       const int i = hb + tid;
       const bool vi = i < h1;
       const int ii = vi ? i : h0;
-      double xi[D];
-      load_x<D>(xb, ii, xi);
+      double xi[D], si;
+      load_rec<D>(xb, ii, xi, si);
       float yi[D];
+      int qi[QW], qik[D], qn2 = 0;
+      if (WRAP) {
 #pragma unroll
-      for (int k = 0; k < D; k++) yi[k] = yc[(size_t)ii * DY + k];
-      const double si = sg[ii];
+        for (int k = 0; k < D; k++) yi[k] = s->ycell[(size_t)ii * DY + k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < QW; k++) qi[k] = s->qc[(size_t)ii * 4 + k];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          qik[k] = sext8(qi[k / 4], k % 4);
+          qn2 += qik[k] * qik[k];
+        }
+      }
       int len = 0, qn = 0;
 
       auto flush = [&]() {
         for (int m = 0; m < qn; m++) {
           const int j = qbuf[m * BLK + tid];
-          double xj[D];
-          load_x<D>(xb, j, xj);
+          double xj[D], sj;
+          load_rec<D>(xb, j, xj, sj);
           const double r2 = dist2_exact<D>(xi, xj, L, hL);
-          if (r2 < list_r2(si, sg[j], cut, skin)) {
+          if (r2 < list_r2(si, sj, cut, skin)) {
             if (len < W) nl[(size_t)len * npad + i] = j;
             len++;
           }
@@ -306,61 +363,106 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
       };
 
       for (int q = 0; q < nst; q++) {
-        // decode the linked subcell (axis 0 most significant)
-        float tk[D];
+        int o[D], cj[D];
+        decode_linked<D>(q, radix, nc, ci, o, cj);
         int J = 0;
-        {
-          int u = q;
-          int cj[D];
 #pragma unroll
-          for (int k = D - 1; k >= 0; k--) {
-            int dig = u % radix;
-            u /= radix;
-            int o = (radix == 3) ? dig - 1 : dig;
-            int c2 = ci[k] + o;
-            c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
-            cj[k] = c2;
-            if (WRAP) tk[k] = (float)(c2 - ci[k]) * lscf - yi[k];
-            else tk[k] = (float)o * lscf - yi[k];
-          }
+        for (int k = 0; k < D; k++) J = J * nc + cj[k];
+        float tk[D];
+        int Ci = 0;
+        if (WRAP) {
 #pragma unroll
-          for (int k = 0; k < D; k++) J = J * nc + cj[k];
+          for (int k = 0; k < D; k++) tk[k] = (float)o[k] * lscf - yi[k];
+        } else {
+          Ci = qn2;
+#pragma unroll
+          for (int k = 0; k < D; k++) Ci -= 2 * kQScale * o[k] * qik[k];
         }
-        const int j0 = cell_start(s, J), j1 = cell_start(s, J + 1);
+        const int j0 = __builtin_amdgcn_readfirstlane(cell_start(s, J));
+        const int j1 = __builtin_amdgcn_readfirstlane(cell_start(s, J + 1));
         for (int jb = j0; jb < j1; jb += BLK) {
           const int m = min(BLK, j1 - jb);
+          const int mp = (m + UNR - 1) / UNR * UNR;  // staged entries padded with sentinels
           __syncthreads();
-          if (tid < m) {
-            const float4* src = reinterpret_cast<const float4*>(yc + (size_t)(jb + tid) * DY);
-            float4* dst = reinterpret_cast<float4*>(ys + tid * DY);
+          if (tid < mp) {
+            if (WRAP) {
+              float4* dst = reinterpret_cast<float4*>(stage + tid * SW);
+              if (tid < m) {
+                const float4* src = reinterpret_cast<const float4*>(s->ycell + (size_t)(jb + tid) * DY);
 #pragma unroll
-            for (int k = 0; k < DY / 4; k++) dst[k] = src[k];
+                for (int k = 0; k < DY / 4; k++) dst[k] = src[k];
+              } else {
+#pragma unroll
+                for (int k = 0; k < DY / 4; k++) dst[k] = make_float4(1e30f, 1e30f, 1e30f, 1e30f);
+              }
+            } else {
+              int w[4] = {0, 0, 0, 0x3fffffff};  // sentinel: A_j far above any threshold
+              if (tid < m) {
+#pragma unroll
+                for (int k = 0; k < QW; k++) w[k] = s->qc[(size_t)(jb + tid) * 4 + k];
+                int A = 0;
+#pragma unroll
+                for (int k = 0; k < D; k++) {
+                  const int c = sext8(w[k / 4], k % 4) + kQScale * o[k];
+                  A += c * c;
+                }
+                w[3] = A;  // QW <= 3 words of coordinates, then A_j
+              }
+              reinterpret_cast<int4*>(stage)[tid] = make_int4(w[0], w[1], w[2], w[3]);
+            }
           }
           __syncthreads();
-          for (int u0 = 0; u0 < m; u0 += 8) {
+          for (int u0 = 0; u0 < mp; u0 += UNR) {
+            unsigned mask = 0;
+            if (WRAP) {
+              float yj[UNR][DY];
 #pragma unroll
-            for (int uu = 0; uu < 8; uu++) {
-              const int idx = u0 + uu;
-              if (idx < m) {
-                const float* yj = ys + idx * DY;
+              for (int uu = 0; uu < UNR; uu++) {
+                const float4* src = reinterpret_cast<const float4*>(stage + (u0 + uu) * SW);
+#pragma unroll
+                for (int k = 0; k < DY / 4; k++) {
+                  const float4 v = src[k];
+                  yj[uu][4 * k] = v.x;
+                  yj[uu][4 * k + 1] = v.y;
+                  yj[uu][4 * k + 2] = v.z;
+                  yj[uu][4 * k + 3] = v.w;
+                }
+              }
+#pragma unroll
+              for (int uu = 0; uu < UNR; uu++) {
                 float r2 = 0.0f;
 #pragma unroll
                 for (int k = 0; k < D; k++) {
-                  float dx = yj[k] + tk[k];
-                  if (WRAP) {
-                    dx = fabsf(dx);
-                    dx = fminf(dx, Lf - dx);
-                  }
+                  float dx = fabsf(yj[uu][k] + tk[k]);
+                  dx = fminf(dx, Lf - dx);
                   r2 = __builtin_fmaf(dx, dx, r2);
                 }
-                const int j = jb + idx;
-                if (vi && r2 < rl2f && j != i) {
+                mask |= (r2 < rl2f ? 1u : 0u) << uu;
+              }
+            } else {
+              int4 w[UNR];
+#pragma unroll
+              for (int uu = 0; uu < UNR; uu++) w[uu] = reinterpret_cast<const int4*>(stage)[u0 + uu];
+#pragma unroll
+              for (int uu = 0; uu < UNR; uu++) {
+                int dot = __builtin_amdgcn_sdot4(qi[0], w[uu].x, 0, false);
+                if (QW > 1) dot = __builtin_amdgcn_sdot4(qi[QW > 1 ? 1 : 0], w[uu].y, dot, false);
+                if (QW > 2) dot = __builtin_amdgcn_sdot4(qi[QW > 2 ? 2 : 0], w[uu].z, dot, false);
+                mask |= (w[uu].w + Ci - 2 * dot < tq ? 1u : 0u) << uu;
+              }
+            }
+            if (vi && mask) {
+              while (mask) {
+                const int b = __builtin_ctz(mask);
+                mask &= mask - 1;
+                const int j = jb + u0 + b;
+                if (j != i) {
                   qbuf[qn * BLK + tid] = j;
                   qn++;
                 }
               }
             }
-            if (__any(qn > kQCap - 8)) flush();
+            if (__any(qn > kQCap - UNR)) flush();
           }
         }
       }
@@ -379,13 +481,248 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Verlet-list build, candidate-lane form (n_cell >= 3)
+//
+// Same list, same row order and the same exact FP64 test as k_build; the
+// work is laid out the other way round.  The linked subcells come in rows of
+// three along the last axis (offsets -1, 0, +1), whose atoms are packed into
+// 64-lane chunks: every lane takes one candidate j, shifts its int8 offsets by
+// the subcell offset into int16 (q'_j = q_j + 250 o, |q'| <= 375) and forms
+// A_j = |q'_j|^2.  The home atoms i of the subcell are then walked uniformly
+// from LDS, each test being
+//   |q'_j - q_i|^2 = A_j + |q_i|^2 - 2 q_i.q'_j  (v_dot2_i32_i16 on int16 pairs)
+// against the same threshold as k_build.  The ballot of each test is filed
+// under its home atom (lane i keeps the ballot of home atom i), so after a
+// chunk lane i holds the
+// 64-bit mask of its surviving candidates.  Every NB chunks the lanes turn
+// back into home atoms and run the exact test on their survivors in chunk
+// and lane order, appending to their own rows.  Lanes are idle only in the
+// ragged last chunk of a row.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(64) void k_build_t(KArgs a) {
+  constexpr int QW = Dims<D>::QW;
+  constexpr int HW = (D + 1) / 2;  // int16 pair words
+  constexpr int NB = 8;            // chunks per exact pass
+  __shared__ int hrec[65 * 8];     // home atoms (+ a never-passing sentinel at 64):
+                                   // HW int16 pair words of 2 q_i, then |q_i|^2
+  __shared__ unsigned long long msk[NB * 64];
+  __shared__ int cand[NB * 64];
+  const int lane = threadIdx.x;
+  for (int t = blockIdx.x;; t += gridDim.x) {
+    SysDev* s;
+    int hc;
+    if (!fetch_cell_tile(a, t, s, hc)) break;
+    if (!running(s) || !need_rebuild(s)) continue;
+    const int* __restrict__ flat = s->cell_flat;
+    const int h0 = __builtin_amdgcn_readfirstlane(flat[hc]);
+    const int h1 = __builtin_amdgcn_readfirstlane(flat[hc + 1]);
+    if (h0 == h1) continue;
+    const int nc = s->ncell, npad = s->npad, W = s->width, tq = s->tq;
+    const double* __restrict__ xb = s->x[s->xcur];
+    const int* __restrict__ qc = s->qc;
+    int* __restrict__ nl = s->nl;
+    const double L = s->L, hL = s->hL, cut = s->cutoff, skin = s->skin;
+    int ci[D], stride[D];
+    {
+      int u = hc, st = 1;
+#pragma unroll
+      for (int k = D - 1; k >= 0; k--) {
+        ci[k] = u % nc;
+        u /= nc;
+        stride[k] = st;
+        st *= nc;
+      }
+    }
+    int nrow = 1;
+#pragma unroll
+    for (int k = 0; k < D - 1; k++) nrow *= 3;
+    const int cl = ci[D - 1];
+    const int lm = cl == 0 ? nc - 1 : cl - 1, lp = cl == nc - 1 ? 0 : cl + 1;
+    int rowmax = 0;
+    for (int hb = h0; hb < h1; hb += 64) {
+      const int hcnt = __builtin_amdgcn_readfirstlane(min(64, h1 - hb));
+      const int i = hb + lane;
+      const bool vi = lane < hcnt;
+      const int ii = vi ? i : hb;
+      double xi[D], si;
+      load_rec<D>(xb, ii, xi, si);
+      int qh[D];
+      {
+        int w[QW];
+#pragma unroll
+        for (int k = 0; k < QW; k++) w[k] = qc[(size_t)ii * 4 + k];
+        int q[2 * HW], B = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * HW; k++) q[k] = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          q[k] = sext8(w[k / 4], k % 4);
+          B += q[k] * q[k];
+          qh[k] = q[k];
+        }
+        __syncthreads();  // previous home chunk done with hrec
+#pragma unroll
+        for (int k = 0; k < HW; k++)
+          hrec[lane * 8 + k] = ((2 * q[2 * k]) & 0xffff) | ((2 * q[2 * k + 1]) << 16);
+        hrec[lane * 8 + 7] = vi ? B : 0x7fffffff;
+        if (lane == 0) hrec[64 * 8 + 7] = 0x7fffffff;
+      }
+      int len = 0, nb = 0;
+
+      auto exact_pass = [&]() {
+        __syncthreads();
+        for (int b = 0; b < nb; b++) {
+          unsigned long long m = msk[b * 64 + lane];
+          while (m) {
+            const int bit = __builtin_ctzll(m);
+            m &= m - 1;
+            const int j = cand[b * 64 + bit];
+            if (vi && j != i) {
+              double xj[D], sj;
+              load_rec<D>(xb, j, xj, sj);
+              const double r2 = dist2_exact<D>(xi, xj, L, hL);
+              if (r2 < list_r2(si, sj, cut, skin)) {
+                if (len < W) nl[(size_t)len * npad + i] = j;
+                len++;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        nb = 0;
+      };
+
+      __syncthreads();
+      int dg[D];
+#pragma unroll
+      for (int k = 0; k < D; k++) dg[k] = 0;
+      for (int row = 0; row < nrow; row++) {
+        int P = 0, Dq[D];
+#pragma unroll
+        for (int k = 0; k < D - 1; k++) {
+          const int o = dg[k] - 1;
+          int c2 = ci[k] + o;
+          c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
+          P += c2 * stride[k];
+          Dq[k] = kQScale * o;
+        }
+        const int st0 = __builtin_amdgcn_readfirstlane(flat[P + lm]);
+        const int c0 = __builtin_amdgcn_readfirstlane(flat[P + lm + 1]) - st0;
+        const int st1 = __builtin_amdgcn_readfirstlane(flat[P + cl]);
+        const int c1 = __builtin_amdgcn_readfirstlane(flat[P + cl + 1]) - st1;
+        const int st2 = __builtin_amdgcn_readfirstlane(flat[P + lp]);
+        const int c2n = __builtin_amdgcn_readfirstlane(flat[P + lp + 1]) - st2;
+        const int T = c0 + c1 + c2n;
+        // home atoms that can reach this row: gap to the neighbouring faces
+        // along the first d-1 axes, one quantisation unit short per axis
+        unsigned long long keep;
+        {
+          int S = 0;
+#pragma unroll
+          for (int k = 0; k < D - 1; k++) {
+            const int o = dg[k] - 1;
+            int g = (kQScale / 2) - o * qh[k] - 1;
+            g = (o == 0 || g < 0) ? 0 : g;
+            S += g * g;
+          }
+          keep = __ballot(vi && S < s->tcull);
+        }
+        for (int k0 = 0; keep != 0 && k0 < T; k0 += 64) {
+          const int tt = k0 + lane;
+          const bool valid = tt < T;
+          const int seg = tt < c0 ? 0 : (tt < c0 + c1 ? 1 : 2);
+          const int j = seg == 0 ? st0 + tt : (seg == 1 ? st1 + tt - c0 : st2 + tt - c0 - c1);
+          int cw[HW], A = 0x3fffffff;
+#pragma unroll
+          for (int k = 0; k < HW; k++) cw[k] = 0;
+          int tA = -0x3fffffff;  // tq - A_j; never passes for an empty lane
+          if (valid) {
+            int w[QW];
+#pragma unroll
+            for (int k = 0; k < QW; k++) w[k] = qc[(size_t)j * 4 + k];
+            int qq[2 * HW];
+#pragma unroll
+            for (int k = 0; k < 2 * HW; k++) qq[k] = 0;
+            A = 0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+              const int off = k < D - 1 ? Dq[k] : kQScale * (seg - 1);
+              qq[k] = sext8(w[k / 4], k % 4) + off;
+              A += qq[k] * qq[k];
+            }
+#pragma unroll
+            for (int k = 0; k < HW; k++) cw[k] = (qq[2 * k] & 0xffff) | (qq[2 * k + 1] << 16);
+            tA = tq - A;
+          }
+          cand[nb * 64 + lane] = valid ? j : -1;
+          msk[nb * 64 + lane] = 0ull;
+          // tq - A_j + (2 q_i).q'_j > |q_i|^2  <=>  |q'_j - q_i|^2 < tq,
+          // for the home atoms kept for this row, four at a time
+          unsigned long long km = keep;
+          while (km) {
+            int hh[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              hh[u] = km ? __builtin_ctzll(km) : 64;  // 64: sentinel record
+              km &= km - 1;
+            }
+            int hr[4][8];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+#pragma unroll
+              for (int k = 0; k < HW; k++) hr[u][k] = hrec[hh[u] * 8 + k];
+              hr[u][7] = hrec[hh[u] * 8 + 7];
+            }
+            unsigned long long m[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              typedef short short2v __attribute__((ext_vector_type(2)));
+              int acc = tA;
+#pragma unroll
+              for (int k = 0; k < HW; k++)
+                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, hr[u][k]),
+                                             __builtin_bit_cast(short2v, cw[k]), acc, false);
+              m[u] = __ballot(acc > hr[u][7]);
+            }
+            // file the ballots under their home atoms (one lane writes them)
+            if (lane == 0) {
+#pragma unroll
+              for (int u = 0; u < 4; u++)
+                if (hh[u] < 64) msk[nb * 64 + hh[u]] = m[u];
+            }
+          }
+          nb++;
+          if (nb == NB) exact_pass();
+        }
+        // next row: odometer over the first D-1 axes, last digit fastest
+#pragma unroll
+        for (int k = D - 2; k >= 0; k--) {
+          if (++dg[k] < 3) break;
+          dg[k] = 0;
+        }
+      }
+      exact_pass();
+      if (vi) {
+        s->nlen[i] = len;
+        rowmax = max(rowmax, len);
+      }
+    }
+    rowmax = wave_max_i(rowmax);
+    if (lane == 0 && rowmax > 0) {
+      atomicMax(&s->max_row, rowmax);
+      if (rowmax > W) atomicOr(&s->err, ERR_OVERFLOW);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pair forces over one Verlet row (Sec. II.B getforce)
 // ---------------------------------------------------------------------------
 // F_i = sum_j fc (x_i - x_j) with fc = -U'(r)/r for r < c sigma_ij;
-// e_i = 1/2 sum_j U(r).  FP64 path.
-template <int D>
-__device__ inline void pair_f64(int pot, double eps, double c, double r2, double sij,
-                                double& fc, double& u) {
+// e_i = 1/2 sum_j U(r).
+__device__ inline void pair_f64(int pot, double eps, double r2, double sij, double& fc,
+                                double& u) {
   if (pot == 0) {  // WCA
     const double inv = 1.0 / r2;
     const double s2 = sij * sij * inv;
@@ -415,69 +752,112 @@ __device__ inline void pair_f32(int pot, float eps, float r2, float sij, float& 
   }
 }
 
-// Accumulates the force on slot i (F as FT = double or float) and its energy.
-template <int D, bool MIX, typename FT>
-__device__ inline void force_row(const SysDev* s, const double* __restrict__ xb,
-                                 const double* __restrict__ sg, int i, const double (&xi)[D],
-                                 double si, FT (&F)[D], double& e) {
+// Own atom's data as the force loop needs it.
+template <int D, bool MIX>
+struct Own {
+  double x[D];  // FP64 coordinates
+  double sg;
+  int u[D];     // fixed-point coordinates (mixed)
+};
+
+// Partial force of lane `sub` of the LPA lanes that share slot i: entries
+// k = sub, sub + LPA, ...; the next group's row indices are fetched before
+// the current group's records are used.  The LPA partial sums are combined
+// with the same butterfly on every lane of the group.
+template <int D, bool MIX, int LPA, typename FT>
+__device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, MIX>& me,
+                                  FT (&F)[D], double& e) {
+  constexpr int U = MIX ? 4 : 2;
   const int npad = s->npad;
   const int len = min(s->nlen[i], s->width);
   const int* __restrict__ nl = s->nl;
   const double L = s->L, h = s->hL, c = s->cutoff, eps = s->eps;
   const int pot = s->potential;
+  const double* __restrict__ xb = s->x[s->xcur];
+  const int32_t* __restrict__ qb = MIX ? s->q[s->xcur] : nullptr;
+  const float fxinv = s->fxinv, cf = (float)c, epsf = (float)eps;
 #pragma unroll
   for (int k = 0; k < D; k++) F[k] = FT(0);
   e = 0.0;
-  constexpr int U = 4;
-  for (int k0 = 0; k0 < len; k0 += U) {
+  int jn[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int kk = sub + u * LPA;
+    jn[u] = kk < len ? nl[(size_t)kk * npad + i] : -1;
+  }
+  for (int k0 = sub; k0 < len; k0 += U * LPA) {
     int jj[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) jj[u] = (k0 + u < len) ? nl[(size_t)(k0 + u) * npad + i] : i;
-    double xj[U][D];
-    double sj[U];
-#pragma unroll
     for (int u = 0; u < U; u++) {
-      load_x<D>(xb, jj[u], xj[u]);
-      sj[u] = sg[jj[u]];
+      jj[u] = jn[u];
+      const int kk = k0 + (U + u) * LPA;
+      jn[u] = kk < len ? nl[(size_t)kk * npad + i] : -1;
     }
+    if (!MIX) {
+      double xj[U][D], sj[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-      if (jj[u] == i) continue;
-      const double sij = 0.5 * (si + sj[u]);
-      const double rc = c * sij;
-      if (!MIX) {
+      for (int u = 0; u < U; u++) load_rec<D>(xb, jj[u] >= 0 ? jj[u] : i, xj[u], sj[u]);
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (jj[u] < 0) continue;
+        const double sij = 0.5 * (me.sg + sj[u]);
+        const double rc = c * sij;
         double dx[D];
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          dx[k] = min_image(xj[u][k] - xi[k], L, h);
+          dx[k] = min_image(xj[u][k] - me.x[k], L, h);
           r2 = __builtin_fma(dx[k], dx[k], r2);
         }
         if (r2 < rc * rc) {
           double fc, uu;
-          pair_f64<D>(pot, eps, c, r2, sij, fc, uu);
+          pair_f64(pot, eps, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) F[k] -= FT(fc * dx[k]);
           e += 0.5 * uu;
         }
-      } else {
+      }
+    } else {
+      int uj[U][D];
+      float sj[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) load_q<D>(qb, jj[u] >= 0 ? jj[u] : i, uj[u], sj[u]);
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (jj[u] < 0) continue;
+        const float sij = 0.5f * ((float)me.sg + sj[u]);
+        const float rc = cf * sij;
         float dx[D];
         float r2 = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          dx[k] = (float)min_image(xj[u][k] - xi[k], L, h);
+          dx[k] = (float)(int)(uj[u][k] - me.u[k]) * fxinv;  // two's complement = minimum image
           r2 = __builtin_fmaf(dx[k], dx[k], r2);
         }
-        const float rcf = (float)rc;
-        if (r2 < rcf * rcf) {
+        if (r2 < rc * rc) {
           float fc, uu;
-          pair_f32(pot, (float)eps, r2, (float)sij, fc, uu);
+          pair_f32(pot, epsf, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) F[k] -= FT(fc * dx[k]);
           e += 0.5 * (double)uu;
         }
       }
     }
+  }
+#pragma unroll
+  for (int o = 1; o < LPA; o <<= 1) {
+#pragma unroll
+    for (int k = 0; k < D; k++) F[k] += (FT)__shfl_xor((FT)F[k], o, 64);
+    e += __shfl_xor(e, o, 64);
+  }
+}
+
+template <int D, bool MIX>
+__device__ inline void load_own(const SysDev* s, int i, Own<D, MIX>& me) {
+  load_rec<D>(s->x[s->xcur], i, me.x, me.sg);
+  if (MIX) {
+    float sgf;
+    load_q<D>(s->q[s->xcur], i, me.u, sgf);
   }
 }
 
@@ -490,31 +870,67 @@ struct VType<true> {
   typedef float T;
 };
 
-// Forces (stored in s->f) with per-wave energy and, for FIRE, the power
+// Per-tile partial sums: each wave reduces its lanes, then (LPA > 1) thread
+// 0 adds the waves of the tile in order (deterministic for a given LPA).
+template <int LPA>
+__device__ inline void tile_partials(double* dst, double (&vals)[kPart], double& maxv,
+                                     double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < kPart; p++) vals[p] = wave_sum(vals[p]);
+  maxv = wave_max(maxv);
+  if (LPA == 1) {
+    if (lane == 0) {
+#pragma unroll
+      for (int p = 0; p < kPart; p++) dst[p] = p == P_FMAX2 ? maxv : vals[p];
+    }
+    return;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < kPart; p++) sh[w * kPart + p] = p == P_FMAX2 ? maxv : vals[p];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int p = 0; p < kPart; p++) {
+      double acc = sh[p];
+      for (int ww = 1; ww < LPA; ww++)
+        acc = p == P_FMAX2 ? fmax(acc, sh[ww * kPart + p]) : acc + sh[ww * kPart + p];
+      dst[p] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Forces (stored in s->f) with the tile's energy and, for FIRE, the power
 // P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
-template <int D, bool MIX>
-__global__ __launch_bounds__(kTile) void k_force(KArgs a, int fire) {
+template <int D, bool MIX, int LPA>
+__global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
   typedef typename VType<MIX>::T FT;
+  __shared__ double sh[LPA * kPart];
+  const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s)) continue;
     if (fire && s->mode != MODE_FIRE) continue;
-    const int i = tile * kTile + threadIdx.x;
+    const int i = tile * kTile + slot;
     const int n = s->n, npad = s->npad, pc = s->pcur;
     const bool vi = i < n;
     const int ii = vi ? i : 0;
-    const double* xb = s->x[s->xcur];
-    double xi[D];
-    load_x<D>(xb, ii, xi);
+    Own<D, MIX> me;
+    load_own<D, MIX>(s, ii, me);
     FT F[D];
     double e;
-    force_row<D, MIX, FT>(s, xb, s->sig[pc], ii, xi, s->sig[pc][ii], F, e);
-    FT* fo = reinterpret_cast<FT*>(s->f);
-    double fv = 0.0, ff = 0.0, vv = 0.0;
-    const FT* v = reinterpret_cast<const FT*>(s->v[pc]);
-    if (vi) {
+    force_part<D, MIX, LPA, FT>(s, ii, sub, me, F, e);
+    double vals[kPart], mx = 0.0;
+#pragma unroll
+    for (int p = 0; p < kPart; p++) vals[p] = 0.0;
+    if (vi && sub == 0) {
+      FT* fo = reinterpret_cast<FT*>(s->f);
+      const FT* v = reinterpret_cast<const FT*>(s->v[pc]);
+      double fv = 0.0, ff = 0.0, vv = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         fo[(size_t)k * npad + i] = F[k];
@@ -525,97 +941,81 @@ __global__ __launch_bounds__(kTile) void k_force(KArgs a, int fire) {
           vv += vk * vk;
         }
       }
-    } else {
-      e = 0.0;
+      vals[P_PE] = e;
+      vals[P_FV] = fv;
+      vals[P_FF] = ff;
+      vals[P_VV] = vv;
+      mx = ff;
     }
-    const double pe = wave_sum(e);
-    double r_fv = 0, r_ff = 0, r_vv = 0, r_fm = 0;
-    if (fire) {
-      r_fv = wave_sum(fv);
-      r_ff = wave_sum(ff);
-      r_vv = wave_sum(vv);
-      r_fm = wave_max(ff);
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-      double* p = s->part + (size_t)(i / kWave) * kPart;
-      p[P_PE] = pe;
-      p[P_FV] = r_fv;
-      p[P_FF] = r_ff;
-      p[P_VV] = r_vv;
-      p[P_FMAX2] = r_fm;
-    }
+    tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh);
   }
 }
 
 // Fused velocity-Verlet step (kick-drift-kick leapfrog, Sec. II.B):
 //   F = F(x^n); v^n = v^(n-1/2) + dt/2 F (skipped at step 0, where v is the
 //   full-step velocity); record KE(v^n), PE(x^n); v^(n+1/2) = v^n + dt/2 F;
-//   x^(n+1) = wrap(x^n + dt v^(n+1/2)) into the other position buffer;
+//   x^(n+1) = wrap(x^n + dt v^(n+1/2)) into the other record buffer;
 //   max_i |x^(n+1)_i - x_ref,i|^2 for the rebuild trigger (skin/2).
 // At the closing step (n == nsteps) only the second kick is applied.
-template <int D, bool MIX>
-__global__ __launch_bounds__(kTile) void k_step(KArgs a) {
+template <int D, bool MIX, int LPA>
+__global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
   typedef typename VType<MIX>::T VT;
+  __shared__ double sh[LPA * kPart];
+  const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s) || s->mode != MODE_MD) continue;
-    const int i = tile * kTile + threadIdx.x;
+    const int i = tile * kTile + slot;
     const int n = s->n, npad = s->npad, pc = s->pcur, cur = s->xcur;
     const bool vi = i < n;
     const int ii = vi ? i : 0;
     const bool first = s->step == 0, close = s->step >= s->nsteps;
     const double dt = s->dt, hdt = 0.5 * dt;
-    const double* xb = s->x[cur];
-    double xi[D];
-    load_x<D>(xb, ii, xi);
+    Own<D, MIX> me;
+    load_own<D, MIX>(s, ii, me);
     VT F[D];
     double e;
-    force_row<D, MIX, VT>(s, xb, s->sig[pc], ii, xi, s->sig[pc][ii], F, e);
-    VT* v = reinterpret_cast<VT*>(s->v[pc]);
-    double ke = 0.0, disp2 = 0.0;
-    if (vi) {
+    force_part<D, MIX, LPA, VT>(s, ii, sub, me, F, e);
+    double vals[kPart], mx = 0.0;
+#pragma unroll
+    for (int p = 0; p < kPart; p++) vals[p] = 0.0;
+    if (vi && sub == 0) {
+      VT* v = reinterpret_cast<VT*>(s->v[pc]);
       VT vk[D];
-      double xn[D];
+      double xn[D], ke = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         vk[k] = v[(size_t)k * npad + i];
         if (!first) vk[k] += VT(hdt) * F[k];
         ke += (double)vk[k] * (double)vk[k];
       }
-      ke *= 0.5;
       const double L = s->L, h = s->hL;
+      double r2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         if (!close) {
           vk[k] += VT(hdt) * F[k];
-          xn[k] = wrap1(xi[k] + dt * (double)vk[k], L, h);
+          xn[k] = wrap1(me.x[k] + dt * (double)vk[k], L, h);
         } else {
-          xn[k] = xi[k];
+          xn[k] = me.x[k];
         }
         v[(size_t)k * npad + i] = vk[k];
-      }
-      store_x<D>(s->x[cur ^ 1], i, xn);
-      double r2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; k++) {
-        double dx = min_image(xn[k] - s->xref[(size_t)k * npad + i], L, h);
+        const double dx = min_image(xn[k] - s->xref[(size_t)k * npad + i], L, h);
         r2 = __builtin_fma(dx, dx, r2);
       }
-      disp2 = r2;
-    } else {
-      e = 0.0;
+      store_rec<D>(s->x[cur ^ 1], i, xn, me.sg);
+      if (MIX) store_q<D>(s->q[cur ^ 1], i, xn, me.sg, h, s->fxscale);
+      vals[P_PE] = e;
+      vals[P_KE] = 0.5 * ke;
+      mx = r2;
     }
-    const double pe = wave_sum(e);
-    const double kes = wave_sum(ke);
-    const double dm = wave_max(disp2);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-      double* p = s->part + (size_t)(i / kWave) * kPart;
-      p[P_PE] = pe;
-      p[P_KE] = kes;
-      if (dm > 0.0) atomicMax(&s->maxdisp2, (unsigned long long)__double_as_longlong(dm));
-    }
+    // the displacement maximum of the tile is reduced like the partial sums
+    double* pt = s->part + (size_t)tile * kPart;
+    tile_partials<LPA>(pt, vals, mx, sh);
+    if (threadIdx.x == 0 && pt[P_FMAX2] > 0.0)
+      atomicMax(&s->maxdisp2, (unsigned long long)__double_as_longlong(pt[P_FMAX2]));
   }
 }
 
@@ -638,8 +1038,8 @@ __global__ __launch_bounds__(kTile) void k_fire_update(KArgs a) {
       const double dt = s->c_dt, keep = s->c_keep, mix = s->c_mix;
       const bool zero = s->c_zero != 0;
       const double L = s->L, h = s->hL;
-      double x[D];
-      load_x<D>(s->x[cur], i, x);
+      double x[D], sg;
+      load_rec<D>(s->x[cur], i, x, sg);
       VT* v = reinterpret_cast<VT*>(s->v[pc]);
       const VT* f = reinterpret_cast<const VT*>(s->f);
       double r2 = 0.0;
@@ -659,7 +1059,8 @@ __global__ __launch_bounds__(kTile) void k_fire_update(KArgs a) {
         double dx = min_image(x[k] - s->xref[(size_t)k * npad + i], L, h);
         r2 = __builtin_fma(dx, dx, r2);
       }
-      store_x<D>(s->x[cur ^ 1], i, x);
+      store_rec<D>(s->x[cur ^ 1], i, x, sg);
+      if (MIX) store_q<D>(s->q[cur ^ 1], i, x, sg, h, s->fxscale);
       disp2 = r2;
     }
     const double dm = wave_max(disp2);

@@ -39,14 +39,14 @@ static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // geometry and workspace plan
 // ---------------------------------------------------------------------------
 struct Plan {
-  int d = 0, dp = 0, dy = 0;
+  int d = 0, dr = 0, dq = 0, dy = 0;
   int n = 0, npad = 0, ncell = 0, radix = 0, ncells = 0, nstencil = 0, nchunks = 0;
   int ntiles = 0, nwaves = 0, width = 0;
   bool wrap = false, mix = false;
   double rlmax = 0;
-  size_t off_desc = 0, off_x[2] = {0, 0}, off_v[2] = {0, 0}, off_sig[2] = {0, 0},
-         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_cell_of = 0,
-         off_rank = 0, off_cell_count = 0, off_cell_local = 0, off_chunk_sum = 0,
+  size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
+         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_qc = 0, off_cell_of = 0,
+         off_rank = 0, off_cell_count = 0, off_cell_flat = 0, off_cell_local = 0, off_chunk_sum = 0,
          off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0;
   size_t bytes = 0;
 };
@@ -89,10 +89,11 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   if (s->box_l < 2.0 * s->cutoff * s->sigma_max)
     return fail(HDMD_ERR_BOX, "box_l < 2 * cutoff * sigma_max: minimum image is ambiguous");
   p.d = s->d;
-  p.dp = (s->d + 1) & ~1;
+  p.dr = s->d <= 3 ? 4 : (s->d <= 7 ? 8 : 16);
+  p.dq = p.dr;
   p.dy = (s->d + 3) & ~3;
   p.n = (int)s->n;
-  p.npad = (int)((s->n + kTile - 1) / kTile * kTile);
+  p.npad = (int)((s->n + kTile - 1) / kTile * kTile);  // whole 64-atom tiles
   p.rlmax = s->cutoff * s->sigma_max + s->skin;
   p.ncell = choose_ncell(*s, p.rlmax);
   p.radix = p.ncell < 3 ? p.ncell : 3;
@@ -112,16 +113,18 @@ static int make_plan(const hdmd_system* s, Plan& p) {
     return r;
   };
   p.off_desc = take(sizeof(SysDev));
-  for (int b = 0; b < 2; b++) p.off_x[b] = take(np * p.dp * 8);
+  for (int b = 0; b < 2; b++) p.off_x[b] = take(np * p.dr * 8);
+  for (int b = 0; b < 2; b++) p.off_q[b] = take(p.mix ? np * p.dq * 4 : 0);
   for (int b = 0; b < 2; b++) p.off_v[b] = take(np * p.d * vsz);
-  for (int b = 0; b < 2; b++) p.off_sig[b] = take(np * 8);
   for (int b = 0; b < 2; b++) p.off_oid[b] = take(np * 4);
   p.off_f = take(np * p.d * vsz);
   p.off_xref = take(np * p.d * 8);
-  p.off_ycell = take(np * p.dy * 4);
+  p.off_ycell = take(p.wrap ? np * p.dy * 4 : 0);
+  p.off_qc = take(p.wrap ? 0 : np * 16);
   p.off_cell_of = take(np * 4);
   p.off_rank = take(np * 4);
   p.off_cell_count = take((size_t)p.ncells * 4);
+  p.off_cell_flat = take((size_t)(p.ncells + 1) * 4);
   p.off_cell_local = take((size_t)p.ncells * 4);
   p.off_chunk_sum = take((size_t)p.nchunks * 4);
   p.off_chunk_off = take((size_t)p.nchunks * 4);
@@ -167,6 +170,20 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.lsc = s->box_l / (double)p.ncell;
   h.inv_lsc = (double)p.ncell / s->box_l;
   h.halfskin2 = 0.25 * s->skin * s->skin;
+  h.fxscale = 4294967296.0 / s->box_l;
+  h.fxinv = (float)(s->box_l / 4294967296.0);
+  h.qinv = (double)kQScale / h.lsc;
+  {
+    // int8 prefilter threshold: ((r_l,max + Delta sqrt(d)) / Delta)^2, Delta =
+    // L_sc / 250, rounded down and made strict (+1), with slack on sqrt(d)
+    const double delta = h.lsc / (double)kQScale;
+    const double thr = (p.rlmax + delta * std::sqrt((double)p.d) * (1.0 + 1e-6)) / delta;
+    h.tq = (int32_t)std::floor(thr * thr) + 1;
+    // a home atom skips a row of linked subcells when its gap to the row,
+    // taken one unit short per axis, is at least r_l,max: S >= (r_l,max/Delta)^2
+    const double rc = p.rlmax / delta;
+    h.tcull = (int32_t)std::ceil(rc * rc);
+  }
   // FP32 prefilter radius: the largest list radius enlarged by a relative
   // 1e-4 plus 1e-5 L, far above the FP32 rounding of offsets from subcell
   // centres (|y| <= L_sc) and of the box length.
@@ -176,16 +193,18 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.Lf = (float)s->box_l;
   for (int b = 0; b < 2; b++) {
     h.x[b] = at<double>(ws, p.off_x[b]);
+    h.q[b] = p.mix ? at<int32_t>(ws, p.off_q[b]) : nullptr;
     h.v[b] = at<void>(ws, p.off_v[b]);
-    h.sig[b] = at<double>(ws, p.off_sig[b]);
     h.oid[b] = at<int32_t>(ws, p.off_oid[b]);
   }
   h.f = at<void>(ws, p.off_f);
   h.xref = at<double>(ws, p.off_xref);
-  h.ycell = at<float>(ws, p.off_ycell);
+  h.ycell = p.wrap ? at<float>(ws, p.off_ycell) : nullptr;
+  h.qc = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc);
   h.cell_of = at<int32_t>(ws, p.off_cell_of);
   h.rank = at<int32_t>(ws, p.off_rank);
   h.cell_count = at<int32_t>(ws, p.off_cell_count);
+  h.cell_flat = at<int32_t>(ws, p.off_cell_flat);
   h.cell_local = at<int32_t>(ws, p.off_cell_local);
   h.chunk_sum = at<int32_t>(ws, p.off_chunk_sum);
   h.chunk_off = at<int32_t>(ws, p.off_chunk_off);
@@ -225,6 +244,7 @@ static int occ_bucket(const Plan& p) {
 static int default_blk(const Plan& p) {
   const char* e = std::getenv("HDMD_BUILD_BLK");
   if (e) return std::atoi(e);
+  if (!p.wrap) return 1;
   double occ = (double)p.n / (double)p.ncells;
   return occ > 160 ? 256 : (occ > 80 ? 128 : 64);
 }
@@ -244,6 +264,19 @@ extern "C" int hdmd_tuned_blk(int d, int wrap, int bucket) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tune.find({d, wrap, bucket});
   return it == g_tune.end() ? 0 : it->second;
+}
+
+// Lanes per atom of the force kernels: fixed per (d, precision) so that a
+// system gives the same bits alone and in a batch (the LPA partial sums are
+// combined in a tree that depends on LPA).  HDMD_LPA overrides it.
+static int lpa_for(int d, bool mix) {
+  const char* e = std::getenv("HDMD_LPA");
+  if (e) {
+    int v = std::atoi(e);
+    return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
+  }
+  (void)mix;
+  return 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -303,6 +336,7 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
   K->load(p.mix, dev, p.ntiles, st, pos, diam, vel);
   bool known = false;
   int blk = lookup_blk(p, &known);
+  if (std::getenv("HDMD_BUILD_BLK")) known = true;
   if (!known && tuning_enabled()) {
     // run the chain up to the build, then time each build variant
     KArgs a = single_args(dev, p.d);
@@ -316,7 +350,8 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_blk = blk;
-    for (int cand : {64, 128, 256}) {
+    for (int cand : {1, 64, 128, 256}) {
+      if (cand == 1 && p.wrap) continue;
       K->build(p.wrap, cand, a, p.ncells, st);  // warm-up
       HIPCHK(hipEventRecord(e0, st));
       K->build(p.wrap, cand, a, p.ncells, st);
@@ -372,7 +407,7 @@ typedef void (*EnqueueFn)(const Plan& p, SysDev* dev, hipStream_t st, int blk);
 static void enqueue_md_step(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
   const DKernels* K = dkernels(p.d);
   KArgs a = single_args(dev, p.d);
-  K->step(p.mix, a, p.ntiles, st);
+  K->step(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
 }
@@ -384,7 +419,7 @@ static void enqueue_fire_iter(const Plan& p, SysDev* dev, hipStream_t st, int bl
   K->fire_update(p.mix, a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
-  K->force(p.mix, a, p.ntiles, 1, st);
+  K->force(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, 1, st);
 }
 
 static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p, SysDev* dev,
@@ -510,7 +545,7 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
   if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   const DKernels* K = dkernels(p.d);
-  K->force(p.mix, single_args(dev, p.d), p.ntiles, 0, st);
+  K->force(p.mix, lpa_for(p.d, p.mix), single_args(dev, p.d), p.ntiles, 0, st);
   launch_reduce_pe(dev, energy, st);
   K->unload(p.mix, dev, p.ntiles, st, nullptr, nullptr, force);
   HIPCHK(hipGetLastError());
@@ -568,7 +603,7 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     for (int64_t k = 0; k <= nsteps; k++) {
       HIPCHK(hipEventRecord(ev[4 * k], st));
-      K->step(p.mix, a, p.ntiles, st);
+      K->step(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, st);
       HIPCHK(hipEventRecord(ev[4 * k + 1], st));
       K->bin(a, p.ntiles, st);
       launch_scan1(a, p.nchunks, st);
@@ -677,7 +712,7 @@ static int fire_start(const hdmd_system* sys, const Plan& p, const double* pos, 
   if (rc) return rc;
   set_fire(h, fp);
   launch_setdesc(dev, h, st);
-  dkernels(p.d)->force(p.mix, single_args(dev, p.d), p.ntiles, 1, st);
+  dkernels(p.d)->force(p.mix, lpa_for(p.d, p.mix), single_args(dev, p.d), p.ntiles, 1, st);
   HIPCHK(hipGetLastError());
   return HDMD_OK;
 }
@@ -750,7 +785,7 @@ struct HostBatch {
   bool dirty = true;
   // current composition
   int n_atom[kMaxD + 1] = {0}, n_cell[kMaxD + 1] = {0}, n_nowrap[kMaxD + 1] = {0};
-  int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};
+  int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};  // wrap-variant build tile per d
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
        has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
@@ -903,7 +938,7 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   }
   if (B->has_md)
     for (int d = kMinD; d <= kMaxD; d++)
-      if (B->n_atom[d]) dkernels(d)->step(B->mix[d], batch_args(B, d), ga(d), st);
+      if (B->n_atom[d]) dkernels(d)->step(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), st);
   for (int d = kMinD; d <= kMaxD; d++)
     if (B->n_atom[d]) dkernels(d)->bin(batch_args(B, d), ga(d), st);
   launch_scan1(a0, gchunk, st);
@@ -913,13 +948,13 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   for (int d = kMinD; d <= kMaxD; d++)
     if (B->n_cell[d]) dkernels(d)->cellsort(B->mix[d], batch_args(B, d), gc(d), st);
   for (int d = kMinD; d <= kMaxD; d++) {
-    if (B->has_nowrap[d]) dkernels(d)->build(false, B->blk[d], batch_args(B, d, 1), gc(d), st);
+    if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
     if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
   }
   launch_finalize(a0, gsys, st);
   if (B->has_fire)
     for (int d = kMinD; d <= kMaxD; d++)
-      if (B->n_atom[d]) dkernels(d)->force(B->mix[d], batch_args(B, d), ga(d), 1, st);
+      if (B->n_atom[d]) dkernels(d)->force(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), 1, st);
 }
 
 }  // namespace hdmd
