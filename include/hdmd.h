@@ -54,9 +54,12 @@ typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
  *   potential  HDMD_WCA: U = 4 eps [(sigma/r)^12 - (sigma/r)^6] + eps (the
  *              paper's Mie n=6 form, Sec. II.A, with cutoff 2^(1/6));
  *              HDMD_HARMONIC: U = eps/2 (1 - r/sigma)^2 (cutoff 1).
- *   precision  HDMD_FP64: everything in FP64.  HDMD_MIXED: distances, forces
- *              and velocities in FP32; positions, energy sums and FIRE's
- *              reductions in FP64.  Verlet lists are FP64-exact in both.
+ *   precision  HDMD_FP64: everything in FP64.  HDMD_MIXED: neighbour
+ *              positions are gathered as 32-bit fixed-point coordinates whose
+ *              integer difference is the exact minimum-image displacement;
+ *              the pair distance and force coefficient are FP64, the force
+ *              vector and the velocities FP32; positions, energy sums and
+ *              FIRE's reductions FP64.  Verlet lists are FP64-exact in both.
  *   sigma_max  largest diameter present; it sizes the subcells (eq. setnc).
  *   max_neighbors  Verlet row capacity W of the workspace. */
 typedef struct {

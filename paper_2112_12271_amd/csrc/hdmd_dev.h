@@ -7,8 +7,8 @@
 //             (one 64-byte half line for 4 <= d <= 7).  Double-buffered: a
 //             step reads x[cur] and writes x[cur^1].
 //   q[2]      (mixed precision only) the same records as 32-bit fixed-point
-//             coordinates u = (x + L/2) 2^32 / L and the FP32 diameter,
-//             [npad][DQ] int32; u_j - u_i in two's complement is the
+//             coordinates u = (x + L/2) 2^32 / L and the FP64 diameter,
+//             [npad][DQ] int32; u_j - u_i in two's complement is the exact
 //             minimum-image displacement, so gathers carry half the bytes.
 //   v[2]      velocities, axis-major (SoA) [d][npad], FP64 or FP32.
 //   oid[2]    caller id of each slot; the [2] buffers of v and oid are the
@@ -17,7 +17,8 @@
 //   xref      positions at the last build [d][npad] FP64 (rebuild trigger).
 //   qc        offsets from the subcell centre quantised to int8 in units of
 //             L_sc/250, packed four per int32 (prefilter of the list build
-//             when n_cell >= 3); ycell the same offsets in FP32 (n_cell <= 2).
+//             when n_cell >= 3); qc16 the same as int16 pairs; ycell the
+//             offsets in FP32 (prefilter when n_cell <= 2).
 //   nl, nlen  Verlet rows in ELL form, column-major nl[k*npad + i], i.e. entry
 //             k of every row is contiguous so a wave reads it coalesced.
 // Atoms are stored in subcell order (canonical: by subcell, then caller id),
@@ -66,7 +67,8 @@ struct SysDev {
   double L, hL, cutoff, skin, eps, sigma_max;
   double rlmax, lsc, inv_lsc, halfskin2;
   double fxscale, qinv;  // 2^32 / L; 250 / L_sc
-  float rl2f, lscf, Lf, fxinv;  // fxinv = L / 2^32
+  double fxinv;          // L / 2^32
+  float rl2f, lscf, Lf, pad3;
   int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
                          // (squared quantised units)
   double* x[2];
@@ -77,6 +79,7 @@ struct SysDev {
   double* xref;
   float* ycell;
   int32_t* qc;
+  int32_t* qc16;  // the same offsets as int16 pairs, [npad][8]
   int32_t* cell_of;
   int32_t* rank;
   int32_t* cell_count;
@@ -212,8 +215,9 @@ template <int D>
 struct Dims {
   static constexpr int DR = D <= 3 ? 4 : (D <= 7 ? 8 : 16);  // FP64 record stride (doubles)
   static constexpr int NR = (D + 2) / 2;                      // double2 loads per record
-  static constexpr int DQ = D <= 3 ? 4 : (D <= 7 ? 8 : 16);  // fixed-point record stride (ints)
-  static constexpr int NQ = (D + 4) / 4;                      // int4 loads per record
+  static constexpr int SQ = (D + 1) & ~1;                     // FP64 sigma slot (in ints)
+  static constexpr int DQ = D <= 2 ? 4 : (D <= 6 ? 8 : 16);  // fixed-point record stride (ints)
+  static constexpr int NQ = (SQ + 2 + 3) / 4;                 // int4 loads per record
   static constexpr int DY = (D + 3) & ~3;                     // FP32 offset stride
   static constexpr int QW = (D + 3) / 4;                      // int8x4 words of the offsets
 };
@@ -250,7 +254,7 @@ __device__ inline void store_rec(double* __restrict__ xb, int i, const double (&
   }
 }
 
-// fixed-point record = (u_0 .. u_{D-1}, float bits of sigma, 0 ...)
+// fixed-point record = (u_0 .. u_{D-1}, [0], sigma as FP64 at int slot SQ, 0 ...)
 __device__ inline int32_t to_fixed(double x, double hL, double scale) {
   return (int32_t)(uint32_t)(long long)rint((x + hL) * scale);
 }
@@ -258,19 +262,23 @@ __device__ inline int32_t to_fixed(double x, double hL, double scale) {
 template <int D>
 __device__ inline void store_q(int32_t* __restrict__ qb, int i, const double (&x)[D], double sg,
                                double hL, double scale) {
+  constexpr int SQ = Dims<D>::SQ;
   int v[4 * Dims<D>::NQ];
 #pragma unroll
   for (int k = 0; k < 4 * Dims<D>::NQ; k++) v[k] = 0;
 #pragma unroll
   for (int k = 0; k < D; k++) v[k] = to_fixed(x[k], hL, scale);
-  v[D] = __float_as_int((float)sg);
+  const long long sb = __double_as_longlong(sg);
+  v[SQ] = (int)(unsigned)(sb & 0xffffffffll);
+  v[SQ + 1] = (int)(unsigned)((unsigned long long)sb >> 32);
   int4* p = reinterpret_cast<int4*>(qb + (size_t)i * Dims<D>::DQ);
 #pragma unroll
   for (int k = 0; k < Dims<D>::NQ; k++) p[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 
 template <int D>
-__device__ inline void load_q(const int32_t* __restrict__ qb, int i, int (&u)[D], float& sg) {
+__device__ inline void load_q(const int32_t* __restrict__ qb, int i, int (&u)[D], double& sg) {
+  constexpr int SQ = Dims<D>::SQ;
   const int4* p = reinterpret_cast<const int4*>(qb + (size_t)i * Dims<D>::DQ);
   int v[4 * Dims<D>::NQ];
 #pragma unroll
@@ -283,7 +291,8 @@ __device__ inline void load_q(const int32_t* __restrict__ qb, int i, int (&u)[D]
   }
 #pragma unroll
   for (int k = 0; k < D; k++) u[k] = v[k];
-  sg = __int_as_float(v[D]);
+  sg = __longlong_as_double((long long)(((unsigned long long)(unsigned)v[SQ + 1] << 32) |
+                                        (unsigned)v[SQ]));
 }
 
 // Squared minimum-image distance accumulated axis by axis with a fused

@@ -164,6 +164,8 @@ __device__ inline void bitonic_sort(int* keys, int* vals, int cnt) {
   }
 }
 
+__device__ inline int sext8(int w, int k) { return (int)(signed char)((w >> (8 * k)) & 0xff); }
+
 // int8 offset from the subcell centre in units of L_sc / 250; |y| <= L_sc/2
 // up to binning rounding, so |q| <= 125 and the clamp never bites.
 __device__ inline int quant8(double y, double qinv) {
@@ -246,6 +248,18 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
           w[k / 4] |= (quant8(x[k] - cen[k], s->qinv) & 0xff) << (8 * (k % 4));
 #pragma unroll
         for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
+        // the same offsets as int16 pairs for the candidate-lane build
+        int p16[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) p16[k] = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          const int qv = sext8(w[k / 4], k % 4);
+          p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
+        }
+        int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
+        pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
+        if (D > 8) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
       }
       s->oid[pn][dst] = keys[q];
     }
@@ -291,8 +305,6 @@ __device__ inline void decode_linked(int q, int radix, int nc, const int (&ci)[D
     o[k] = (radix == 3) ? oo : c2 - ci[k];
   }
 }
-
-__device__ inline int sext8(int w, int k) { return (int)(signed char)((w >> (8 * k)) & 0xff); }
 
 template <int D, bool WRAP, int BLK>
 __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
@@ -598,15 +610,20 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
 #pragma unroll
       for (int k = 0; k < D; k++) dg[k] = 0;
       for (int row = 0; row < nrow; row++) {
-        int P = 0, Dq[D];
+        int P = 0, Dp[HW];
+#pragma unroll
+        for (int k = 0; k < HW; k++) Dp[k] = 0;
 #pragma unroll
         for (int k = 0; k < D - 1; k++) {
           const int o = dg[k] - 1;
           int c2 = ci[k] + o;
           c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
           P += c2 * stride[k];
-          Dq[k] = kQScale * o;
+          Dp[k / 2] |= ((kQScale * o) & 0xffff) << (16 * (k % 2));
         }
+        // offset of the last axis (-1, 0, +1 subcells) in its int16 half
+        const int lsh = 16 * ((D - 1) % 2);
+        const int lastp[3] = {(-kQScale & 0xffff) << lsh, 0, (kQScale & 0xffff) << lsh};
         const int st0 = __builtin_amdgcn_readfirstlane(flat[P + lm]);
         const int c0 = __builtin_amdgcn_readfirstlane(flat[P + lm + 1]) - st0;
         const int st1 = __builtin_amdgcn_readfirstlane(flat[P + cl]);
@@ -633,26 +650,23 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
           const bool valid = tt < T;
           const int seg = tt < c0 ? 0 : (tt < c0 + c1 ? 1 : 2);
           const int j = seg == 0 ? st0 + tt : (seg == 1 ? st1 + tt - c0 : st2 + tt - c0 - c1);
-          int cw[HW], A = 0x3fffffff;
+          typedef short short2v __attribute__((ext_vector_type(2)));
+          int cw[HW];
 #pragma unroll
           for (int k = 0; k < HW; k++) cw[k] = 0;
           int tA = -0x3fffffff;  // tq - A_j; never passes for an empty lane
           if (valid) {
-            int w[QW];
+            const int* src = s->qc16 + (size_t)j * 8;
+            int A = 0;
 #pragma unroll
-            for (int k = 0; k < QW; k++) w[k] = qc[(size_t)j * 4 + k];
-            int qq[2 * HW];
-#pragma unroll
-            for (int k = 0; k < 2 * HW; k++) qq[k] = 0;
-            A = 0;
-#pragma unroll
-            for (int k = 0; k < D; k++) {
-              const int off = k < D - 1 ? Dq[k] : kQScale * (seg - 1);
-              qq[k] = sext8(w[k / 4], k % 4) + off;
-              A += qq[k] * qq[k];
+            for (int k = 0; k < HW; k++) {
+              // shift by the subcell offset as packed int16 adds, then A_j += |pair|^2
+              const short2v q2 = __builtin_bit_cast(short2v, src[k]);
+              const short2v o2 = __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastp[seg] : 0));
+              const short2v r2 = q2 + o2;
+              cw[k] = __builtin_bit_cast(int, r2);
+              A = __builtin_amdgcn_sdot2(r2, r2, A, false);
             }
-#pragma unroll
-            for (int k = 0; k < HW; k++) cw[k] = (qq[2 * k] & 0xffff) | (qq[2 * k + 1] << 16);
             tA = tq - A;
           }
           cand[nb * 64 + lane] = valid ? j : -1;
@@ -737,21 +751,6 @@ __device__ inline void pair_f64(int pot, double eps, double r2, double sij, doub
   }
 }
 
-__device__ inline void pair_f32(int pot, float eps, float r2, float sij, float& fc, float& u) {
-  if (pot == 0) {
-    const float inv = 1.0f / r2;
-    const float s2 = sij * sij * inv;
-    const float s6 = s2 * s2 * s2;
-    fc = 24.0f * eps * (2.0f * s6 * s6 - s6) * inv;
-    u = 4.0f * eps * (s6 * s6 - s6) + eps;
-  } else {
-    const float r = sqrtf(r2);
-    const float g = 1.0f - r / sij;
-    fc = eps * g / (sij * r);
-    u = 0.5f * eps * g * g;
-  }
-}
-
 // Own atom's data as the force loop needs it.
 template <int D, bool MIX>
 struct Own {
@@ -775,7 +774,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
   const int pot = s->potential;
   const double* __restrict__ xb = s->x[s->xcur];
   const int32_t* __restrict__ qb = MIX ? s->q[s->xcur] : nullptr;
-  const float fxinv = s->fxinv, cf = (float)c, epsf = (float)eps;
+  const double fxinv = s->fxinv;
 #pragma unroll
   for (int k = 0; k < D; k++) F[k] = FT(0);
   e = 0.0;
@@ -818,28 +817,30 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         }
       }
     } else {
+      // mixed: exact integer displacements; distance and pair coefficient in
+      // FP64, force vector accumulated in FP32
       int uj[U][D];
-      float sj[U];
+      double sj[U];
 #pragma unroll
       for (int u = 0; u < U; u++) load_q<D>(qb, jj[u] >= 0 ? jj[u] : i, uj[u], sj[u]);
 #pragma unroll
       for (int u = 0; u < U; u++) {
         if (jj[u] < 0) continue;
-        const float sij = 0.5f * ((float)me.sg + sj[u]);
-        const float rc = cf * sij;
-        float dx[D];
-        float r2 = 0.0f;
+        const double sij = 0.5 * (me.sg + sj[u]);
+        const double rc = c * sij;
+        double dx[D];
+        double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          dx[k] = (float)(int)(uj[u][k] - me.u[k]) * fxinv;  // two's complement = minimum image
-          r2 = __builtin_fmaf(dx[k], dx[k], r2);
+          dx[k] = (double)(int)(uj[u][k] - me.u[k]) * fxinv;  // two's complement = minimum image
+          r2 = __builtin_fma(dx[k], dx[k], r2);
         }
         if (r2 < rc * rc) {
-          float fc, uu;
-          pair_f32(pot, epsf, r2, sij, fc, uu);
+          double fc, uu;
+          pair_f64(pot, eps, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) F[k] -= FT(fc * dx[k]);
-          e += 0.5 * (double)uu;
+          e += 0.5 * uu;
         }
       }
     }
@@ -856,8 +857,8 @@ template <int D, bool MIX>
 __device__ inline void load_own(const SysDev* s, int i, Own<D, MIX>& me) {
   load_rec<D>(s->x[s->xcur], i, me.x, me.sg);
   if (MIX) {
-    float sgf;
-    load_q<D>(s->q[s->xcur], i, me.u, sgf);
+    double sgq;
+    load_q<D>(s->q[s->xcur], i, me.u, sgq);
   }
 }
 

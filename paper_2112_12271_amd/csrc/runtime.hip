@@ -45,7 +45,8 @@ struct Plan {
   bool wrap = false, mix = false;
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
-         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_qc = 0, off_cell_of = 0,
+         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_qc = 0, off_qc16 = 0,
+         off_cell_of = 0,
          off_rank = 0, off_cell_count = 0, off_cell_flat = 0, off_cell_local = 0, off_chunk_sum = 0,
          off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0;
   size_t bytes = 0;
@@ -90,7 +91,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
     return fail(HDMD_ERR_BOX, "box_l < 2 * cutoff * sigma_max: minimum image is ambiguous");
   p.d = s->d;
   p.dr = s->d <= 3 ? 4 : (s->d <= 7 ? 8 : 16);
-  p.dq = p.dr;
+  p.dq = s->d <= 2 ? 4 : (s->d <= 6 ? 8 : 16);
   p.dy = (s->d + 3) & ~3;
   p.n = (int)s->n;
   p.npad = (int)((s->n + kTile - 1) / kTile * kTile);  // whole 64-atom tiles
@@ -121,6 +122,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.off_xref = take(np * p.d * 8);
   p.off_ycell = take(p.wrap ? np * p.dy * 4 : 0);
   p.off_qc = take(p.wrap ? 0 : np * 16);
+  p.off_qc16 = take(p.wrap ? 0 : np * 32);
   p.off_cell_of = take(np * 4);
   p.off_rank = take(np * 4);
   p.off_cell_count = take((size_t)p.ncells * 4);
@@ -171,7 +173,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.inv_lsc = (double)p.ncell / s->box_l;
   h.halfskin2 = 0.25 * s->skin * s->skin;
   h.fxscale = 4294967296.0 / s->box_l;
-  h.fxinv = (float)(s->box_l / 4294967296.0);
+  h.fxinv = s->box_l / 4294967296.0;
   h.qinv = (double)kQScale / h.lsc;
   {
     // int8 prefilter threshold: ((r_l,max + Delta sqrt(d)) / Delta)^2, Delta =
@@ -201,6 +203,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.xref = at<double>(ws, p.off_xref);
   h.ycell = p.wrap ? at<float>(ws, p.off_ycell) : nullptr;
   h.qc = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc);
+  h.qc16 = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc16);
   h.cell_of = at<int32_t>(ws, p.off_cell_of);
   h.rank = at<int32_t>(ws, p.off_rank);
   h.cell_count = at<int32_t>(ws, p.off_cell_count);
@@ -600,7 +603,7 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
     const DKernels* K = dkernels(p.d);
     KArgs a = single_args(dev, p.d);
     ev.resize(4 * (size_t)(nsteps + 1));
-    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     for (int64_t k = 0; k <= nsteps; k++) {
       HIPCHK(hipEventRecord(ev[4 * k], st));
       K->step(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, st);

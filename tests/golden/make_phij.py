@@ -1,0 +1,66 @@
+"""Writes tests/golden/phij.json: the jamming packing fraction phi_J per d
+estimated with the CPU oracle (test infrastructure; calls only oracle/ and the
+seeded input generators).
+
+Recipe: 50:50 harmonic soft spheres of diameters 1.0/1.4, N = 1024, seeded
+uniform positions; for each d bisect phi over [phi_d, 1.5 phi_d], with phi_d
+the hard-sphere dynamical-transition packing fraction of Table III (Sec.
+III.A); a state is jammed iff FIRE (to |F|max < 1e-10 or 20000 iterations)
+leaves E/N > 1e-16.  phi_J per d is the median over three seeds after eight
+bisections.  The paper itself gives no phi_J; these values only set the
+density window of the batched FIRE workload.
+"""
+import json
+import multiprocessing as mp
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2112_12271_amd import inputs  # noqa: E402
+
+PHI_D = {3: 0.5770, 4: 0.4036, 5: 0.2683, 6: 0.1723}   # Table III
+N = 1024
+SEEDS = (0, 1, 2)
+BISECT = 8
+
+
+def jammed(d, phi, seed):
+    sig = inputs.bidisperse(N, 1.0, 1.4, 100 * d + seed)
+    L = inputs.box_for_packing(d, sig, phi)
+    x = inputs.uniform_positions(N, d, L, 1000 * d + seed)
+    p = O.fire_params(dt0=0.05, ftol=1e-10, maxiter=20000)
+    _, res = O.fire(x, sig, L, O.HARMONIC, 1.0, 0.25, 1.0, p)
+    return res.energy / N > 1e-16
+
+
+def one(args):
+    d, seed = args
+    lo, hi = PHI_D[d], 1.5 * PHI_D[d]
+    for _ in range(BISECT):
+        mid = 0.5 * (lo + hi)
+        if jammed(d, mid, seed):
+            hi = mid
+        else:
+            lo = mid
+    return d, seed, 0.5 * (lo + hi)
+
+
+def main():
+    O.build(force=False)
+    jobs = [(d, s) for d in PHI_D for s in SEEDS]
+    with mp.Pool(min(8, len(jobs))) as pool:
+        res = pool.map(one, jobs)
+    out = {}
+    for d in PHI_D:
+        v = sorted(r[2] for r in res if r[0] == d)
+        out[str(d)] = v[len(v) // 2]
+    out["recipe"] = __doc__.strip().splitlines()[2:]
+    json.dump(out, open(os.path.join(HERE, "phij.json"), "w"), indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

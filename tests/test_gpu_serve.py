@@ -1,0 +1,70 @@
+"""Serving on the GPU: a seeded stream of FIRE minimisations and short MD runs
+of mixed d and N, admitted by HBM budget while others run; every result equals
+the same request run alone (bit for bit)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_12271_amd import hdmd as H
+from paper_2112_12271_amd import inputs
+from paper_2112_12271_amd import serve as S
+from tests.gpu_util import dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(count):
+    phij = {3: 0.65, 4: 0.47, 5: 0.32, 6: 0.21}
+    reqs = inputs.fire_requests(count, phij, rate=400.0, seed=4100, n_lo=256, n_hi=1500)
+    out = []
+    for r in reqs:
+        if r.rid % 4 == 3:    # every fourth request is a short MD run (WCA, jittered start)
+            x, L = inputs.jittered_lattice(r.d, {3: 7, 4: 5, 5: 4, 6: 3}[r.d], 1.1, 0.1, r.rid)
+            n = len(x)
+            sig = inputs.bidisperse(n, 1.0, 1.2, r.rid)
+            v = inputs.gaussian_velocities(n, r.d, 1.0, r.rid + 1)
+            out.append(S.Request(r.rid, "md", r.d, n, L, x, sig, r.arrival, potential=0,
+                                 cutoff=inputs.WCA_CUT, skin=0.3, v=v, nsteps=150, dt=0.003))
+        else:
+            out.append(S.Request(r.rid, "fire", r.d, r.n, r.L, r.positions(), r.sig, r.arrival))
+    return out
+
+
+def _alone(req, width, params, prec):
+    sysd = H.System(d=req.d, n=req.n, box_l=req.box_l, potential=req.potential,
+                    cutoff=req.cutoff, skin=req.skin, sigma_max=float(req.sig.max()),
+                    precision=prec, max_neighbors=width)
+    ws = H.workspace(sysd)
+    X = dev(req.x)
+    if req.kind == "fire":
+        res = H.hdmd_fire_minimize(sysd, X, dev(req.sig), ws, params)
+        return X.cpu().numpy(), res.iterations
+    V = dev(req.v)
+    st, _ = H.hdmd_step(sysd, X, V, dev(req.sig), ws, req.nsteps, req.dt)
+    return X.cpu().numpy(), st.steps_done
+
+
+@pytest.mark.parametrize("prec", [H.HDMD_MIXED])
+def test_mix_equals_alone(prec):
+    params = H.hdmd_fire_defaults(0.05, 1e-5, 20000)
+    reqs = _stream(24)
+    ex = S.GpuExecutor(max_slots=8, max_atoms=40000, max_cells=400000, precision=prec,
+                       fire_params=params)
+    budget = 6 * max(ex.workspace_bytes(r, S.estimate_width(r.d, r.n, r.box_l, 1.75))
+                     for r in reqs)
+    srv = S.Server(ex, max_slots=8, hbm_budget=budget, chunk=40, keep_positions=True)
+    res = srv.serve(reqs, time_limit=300)
+    assert sorted(r.rid for r in res) == [r.rid for r in reqs]
+    assert srv.max_in_use <= budget
+    assert srv.max_active >= 2          # work overlapped on the device
+    byid = {r.rid: r for r in reqs}
+    for r in res:
+        req = byid[r.rid]
+        width = S.estimate_width(req.d, req.n, req.box_l,
+                                 req.cutoff * float(req.sig.max()) + req.skin)
+        for _ in range(r.retries):      # the server widens a row capacity per retry
+            width = int(width * 1.5) + 16
+        xa, it = _alone(req, width, params, prec)
+        assert r.status == 0
+        assert r.iterations == it, r.rid
+        assert np.array_equal(r.x, xa), r.rid
