@@ -115,30 +115,153 @@ def run_md(H, torch, cfg, x0, v0, sig, L, prec, steps, warmup, every, profile):
                 width=sysd.max_neighbors)
 
 
-def cpu_baseline(cfg, steps: int = 10):
-    """Oracle (single thread) on a bounded sample of the same workload: d=6,
-    phi=0.42, 50:50 sigma 1.0/1.2, dt, skin, T as the GPU run, but 6^6 = 46656
-    atoms in a box of exactly 3 subcells per axis, so that every atom meets the
-    same number of candidates (its 3^6 linked subcells at the same density)
-    and has the same list length as in the 262144-atom box; one list build and
-    `steps` velocity-Verlet steps from a jittered lattice."""
+def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5):
+    """The oracle (single thread, as it stands) on a bounded sample of the same
+    workload: `n` atoms at the same density and diameters, in a box of 3
+    subcells per axis, so that the subcell path links every subcell and each
+    atom meets n - 1 candidates.  Timed: one list build by the oracle's subcell
+    path and `reps` force evaluations over that list.  The build time per atom
+    is scaled to the candidates per atom of the full box (3^d of its
+    n_cell^d subcells: 46656 atoms for N = 262144 with n_cell = 4) -- the build is one plain loop per candidate --
+    and per step the oracle costs N * (force time per atom) + N * (build time
+    per atom) / steps_per_build, with the rebuild interval the GPU run
+    measured."""
     from oracle import oracle as O
     from paper_2112_12271_amd import inputs
-    m = 6
-    n = m ** cfg.d
     sig = inputs.bidisperse(n, cfg.sig_a, cfg.sig_b, 77)
     L = inputs.box_for_packing(cfg.d, sig, cfg.phi)
-    x, Lq = inputs.jittered_lattice(cfg.d, m, L / m, 0.15 * L / m, 78)
-    v = inputs.gaussian_velocities(n, cfg.d, cfg.T, 79)
+    x = inputs.uniform_positions(n, cfg.d, L, 78)
+    rlmax = cfg.cutoff * float(sig.max()) + cfg.skin
     O.lib()
+    assert O.ncell(L, rlmax) == 3
     t0 = time.perf_counter()
-    _, _, th, builds = O.vv(x, v, sig, Lq, O.WCA, cfg.cutoff, cfg.skin, 1.0, steps, cfg.dt)
-    t1 = time.perf_counter()
-    return dict(value=n * steps / (t1 - t0), unit="atom-steps/s", cores=1, kind="oracle",
-                sample="oracle FP64, 1 thread: %d atoms, d=%d, phi=%.2f, box of 3 subcells per axis "
-                       "(same candidates per atom as N=%d), %d list build(s) + %d VV steps in %.1f s"
-                       % (n, cfg.d, cfg.phi, cfg.n, builds, steps, t1 - t0),
-                steps_per_build=steps / max(builds, 1))
+    rp, cols = O.nlist_cells(x, sig, L, cfg.cutoff, cfg.skin)
+    t_build = time.perf_counter() - t0
+    log("cpu baseline: oracle list build of %d atoms in %.1f s" % (n, t_build))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.forces(x, sig, L, O.WCA, cfg.cutoff, 1.0, rp, cols)
+    t_f = (time.perf_counter() - t0) / reps
+    nc_full = O.ncell(cfg.box(cfg.diameters()), rlmax)
+    cand_full = cfg.n * (3.0 / nc_full) ** cfg.d
+    build_per_atom = t_build / n * (cand_full / (n - 1))
+    step_s = cfg.n * (t_f / n) + cfg.n * build_per_atom / steps_per_build
+    return dict(value=cfg.n / step_s, unit="atom-steps/s", cores=1, kind="oracle",
+                sample="oracle FP64, 1 thread, %d atoms (d=%d, phi=%.2f, 3 subcells per axis): "
+                       "one subcell-path list build in %.1f s (%d candidates per atom, scaled to "
+                       "the %.0f of N=%d) and %d force passes over it (mean row %.1f) in %.2f s, "
+                       "combined at %.2f steps per build"
+                       % (n, cfg.d, cfg.phi, t_build, n - 1, cand_full, cfg.n, reps,
+                          len(cols) / n, t_f * reps, steps_per_build),
+                build_s_full=cfg.n * build_per_atom, force_s_full=cfg.n * t_f / n)
+
+
+def fire_stream(count: int, rate: float, seed: int = 4000):
+    """The batched FIRE workload: harmonic soft spheres, 50:50 diameters
+    1.0/1.4, d uniform in {3,4,5,6}, N log-uniform in [256, 8192], packing
+    fraction uniform in [phi_J - 0.02, phi_J + 0.05] with phi_J per d from the
+    committed oracle pilot, Poisson arrivals at `rate` per second."""
+    from paper_2112_12271_amd import inputs
+    from paper_2112_12271_amd import serve as S
+    pj = json.load(open(os.path.join(ROOT, "tests", "golden", "phij.json")))
+    phij = {d: float(pj[str(d)]) for d in (3, 4, 5, 6)}
+    return [S.Request(r.rid, "fire", r.d, r.n, r.L, r.positions(), r.sig, r.arrival)
+            for r in inputs.fire_requests(count, phij, rate, seed=seed)]
+
+
+def per_instance(H, torch, reqs, prec, f_tol, max_iter):
+    """Plain per-instance solves: one hdmd_fire_minimize at a time, in arrival
+    order, each with its own workspace (same row-capacity policy as the server:
+    estimated, widened by 1.5x + 16 and re-run from the input on overflow)."""
+    from paper_2112_12271_amd import serve as S
+    params = H.hdmd_fire_defaults(0.05, f_tol, max_iter)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    out = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in sorted(reqs, key=lambda q: q.arrival):
+        wait = r.arrival - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        width = S.estimate_width(r.d, r.n, r.box_l, r.cutoff * float(r.sig.max()) + r.skin)
+        sig = dev(r.sig)
+        while True:
+            sysd = H.System(d=r.d, n=r.n, box_l=r.box_l, potential=H.HDMD_HARMONIC,
+                            cutoff=1.0, skin=r.skin, sigma_max=float(r.sig.max()),
+                            precision=prec, max_neighbors=width)
+            ws = H.workspace(sysd)
+            X = dev(r.x)
+            try:
+                res = H.hdmd_fire_minimize(sysd, X, sig, ws, params)
+                break
+            except H.HdmdError as e:
+                if e.status != H.HDMD_ERR_NLIST_OVERFLOW:
+                    raise
+                width = int(width * 1.5) + 16
+        now = time.perf_counter() - t0
+        out.append(S.Result(r.rid, "fire", r.d, r.n, r.arrival, now, now, res.iterations,
+                            res.fmax, res.energy, res.status, 0))
+    return out, time.perf_counter() - t0
+
+
+def batched(H, torch, reqs, prec, f_tol, max_iter, slots, budget_gb, chunk):
+    from paper_2112_12271_amd import serve as S
+    params = H.hdmd_fire_defaults(0.05, f_tol, max_iter)
+    ex = S.GpuExecutor(max_slots=slots, max_atoms=slots * 8192, max_cells=slots * 32768,
+                       precision=prec, fire_params=params)
+    srv = S.Server(ex, max_slots=slots, hbm_budget=int(budget_gb * (1 << 30)), chunk=chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = srv.serve(reqs, time_limit=900)
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0, srv
+
+
+def fire_record(res, wall):
+    from paper_2112_12271_amd import serve as S
+    rec = S.summarize(res, wall)
+    f = np.array([r.fmax for r in res])
+    rec.update(converged=int(sum(r.status == 0 for r in res)),
+               fmax_final_max=float(f.max()) if len(f) else None,
+               iterations_total=int(sum(r.iterations for r in res)),
+               atoms_total=int(sum(r.n for r in res)))
+    return rec
+
+
+def fire_serving(H, torch, args):
+    """Batched mixed-precision FIRE over the whole request stream through the
+    continuous-batching server, then the comparison at equal final |F|max on a
+    bounded prefix of the same stream: batched mixed vs plain per-instance FP64
+    (one minimisation at a time, the only way to serve without batching)."""
+    reqs = fire_stream(args.fire_requests, args.fire_rate)
+    log("fire stream: %d requests, %d atoms, arrivals over %.2f s"
+        % (len(reqs), sum(r.n for r in reqs), reqs[-1].arrival if reqs else 0))
+    out = {"f_tol": args.fire_tol, "requests": len(reqs), "arrival_rate_per_s": args.fire_rate}
+
+    def run_batched(rs):
+        res, wall, srv = batched(H, torch, rs, H.HDMD_MIXED, args.fire_tol, args.fire_max_iter,
+                                 args.fire_slots, args.fire_budget_gb, args.fire_chunk)
+        rec = fire_record(res, wall)
+        rec.update(precision="mixed", slots=args.fire_slots, max_active=srv.max_active,
+                   peak_workspace_gb=srv.max_in_use / (1 << 30), budget_gb=args.fire_budget_gb,
+                   retries=int(sum(r.retries for r in res)))
+        return rec
+
+    out["batched_mixed"] = run_batched(reqs)
+    log("batched mixed", json.dumps(out["batched_mixed"]))
+    k = min(args.fire_compare, len(reqs))
+    if k > 0:
+        pre = reqs[:k]
+        a = run_batched(pre)
+        res, wall = per_instance(H, torch, pre, H.HDMD_FP64, args.fire_tol, args.fire_max_iter)
+        b = fire_record(res, wall)
+        b.update(precision="fp64")
+        out["compare"] = {"requests": k, "batched_mixed": a, "per_instance_fp64": b,
+                          "speedup_solves_per_s": a["solves_per_s"] / b["solves_per_s"],
+                          "p99_ratio_per_instance_over_batched":
+                              b["latency_p99"] / a["latency_p99"]}
+        log("compare", json.dumps(out["compare"]))
+    return out
 
 
 def main():
@@ -152,7 +275,32 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time with captured graphs and without per-kernel events")
+    ap.add_argument("--no-fire", action="store_true", help="skip the batched FIRE serving leg")
+    ap.add_argument("--fire-compare", type=int, default=64,
+                    help="prefix of the stream run both batched and per instance (0: skip)")
+    ap.add_argument("--fire-requests", type=int, default=512)
+    ap.add_argument("--fire-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    ap.add_argument("--fire-tol", type=float, default=1e-5, help="|F|max target of both legs")
+    ap.add_argument("--fire-max-iter", type=int, default=100000)
+    ap.add_argument("--fire-slots", type=int, default=512)
+    ap.add_argument("--fire-budget-gb", type=float, default=64.0)
+    ap.add_argument("--fire-chunk", type=int, default=50)
+    ap.add_argument("--no-md", action="store_true", help="skip the MD legs (FIRE serving only)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES three times (scales the HBM "
+                         "byte counters of a profiler to bytes)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                          "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
@@ -170,42 +318,45 @@ def main():
     x0 = cfg.positions(L)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
-    # untimed set-up: FIRE pushoff of the overlaps on harmonic soft spheres
-    t = time.perf_counter()
-    sysh = H.System(d=cfg.d, n=cfg.n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0,
-                    skin=cfg.skin, sigma_max=float(sig.max()), max_neighbors=64)
-    X = dev(x0)
-    sysh, res = H.fire_auto(sysh, X, dev(sig),
-                            H.hdmd_fire_defaults(0.05, 1e-6, args.pushoff_iters))
-    xr = X.cpu().numpy()
-    log("pushoff: %d FIRE iterations, %d builds, E/N=%.4g, |F|max=%.3g, %.1fs"
-        % (res.iterations, res.builds, res.energy / cfg.n, res.fmax, time.perf_counter() - t))
-    v0 = cfg.velocities()
-
     out = {}
-    for prec in ([H.HDMD_FP64] + ([] if args.no_mixed else [H.HDMD_MIXED])):
-        name = "fp64" if prec == H.HDMD_FP64 else "mixed"
-        r = run_md(H, torch, cfg, xr, v0, sig, L, prec, args.steps, args.warmup, 10,
-                   not args.no_profile)
-        st = r["stats"]
-        sl, fl = drift(r["thermo"], cfg.n, cfg.dt)
-        rate = cfg.n * args.steps / r["seconds"]
-        rec = dict(value=rate, ms_per_step=1e3 * r["seconds"] / args.steps, builds=int(st.builds),
-                   steps_per_build=args.steps / max(st.builds, 1), mean_row=r["mean_row"],
-                   max_row=int(st.max_row), width=r["width"], drift_per_tau=sl, rms_fluct=fl,
-                   T_end=2 * st.ke / (cfg.d * (cfg.n - 1)))
-        if st.step_kernels > 0:
-            avg_ms = st.step_kernel_ms / st.step_kernels
-            bpa = step_bytes_per_atom(cfg.d, r["mean_row"], prec == H.HDMD_MIXED)
-            ach = cfg.n * bpa / (avg_ms * 1e-3) / 1e9
-            rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
-                       build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
-                       share_step_kernel=st.step_kernel_ms / (1e3 * r["seconds"]),
-                       share_build_kernel=st.build_kernel_ms / (1e3 * r["seconds"]))
-        out[name] = rec
-        log(name, json.dumps(rec))
+    if not args.no_md:
+        # untimed set-up: FIRE pushoff of the overlaps on harmonic soft spheres
+        t = time.perf_counter()
+        sysh = H.System(d=cfg.d, n=cfg.n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0,
+                        skin=cfg.skin, sigma_max=float(sig.max()), max_neighbors=64)
+        X = dev(x0)
+        sysh, res = H.fire_auto(sysh, X, dev(sig),
+                                H.hdmd_fire_defaults(0.05, 1e-6, args.pushoff_iters))
+        xr = X.cpu().numpy()
+        log("pushoff: %d FIRE iterations, %d builds, E/N=%.4g, |F|max=%.3g, %.1fs"
+            % (res.iterations, res.builds, res.energy / cfg.n, res.fmax, time.perf_counter() - t))
+        v0 = cfg.velocities()
 
-    f = out["fp64"]
+        for prec in ([H.HDMD_FP64] + ([] if args.no_mixed else [H.HDMD_MIXED])):
+            name = "fp64" if prec == H.HDMD_FP64 else "mixed"
+            r = run_md(H, torch, cfg, xr, v0, sig, L, prec, args.steps, args.warmup, 10,
+                       not args.no_profile)
+            st = r["stats"]
+            sl, fl = drift(r["thermo"], cfg.n, cfg.dt)
+            rate = cfg.n * args.steps / r["seconds"]
+            rec = dict(value=rate, ms_per_step=1e3 * r["seconds"] / args.steps, builds=int(st.builds),
+                       steps_per_build=args.steps / max(st.builds, 1), mean_row=r["mean_row"],
+                       max_row=int(st.max_row), width=r["width"], drift_per_tau=sl, rms_fluct=fl,
+                       T_end=2 * st.ke / (cfg.d * (cfg.n - 1)))
+            if st.step_kernels > 0:
+                avg_ms = st.step_kernel_ms / st.step_kernels
+                bpa = step_bytes_per_atom(cfg.d, r["mean_row"], prec == H.HDMD_MIXED)
+                ach = cfg.n * bpa / (avg_ms * 1e-3) / 1e9
+                rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
+                           build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
+                           share_step_kernel=st.step_kernel_ms / (1e3 * r["seconds"]),
+                           share_build_kernel=st.build_kernel_ms / (1e3 * r["seconds"]))
+            out[name] = rec
+            log(name, json.dumps(rec))
+    fire = None
+    if not args.no_fire:
+        fire = fire_serving(H, torch, args)
+    f = out.get("fp64", {})
     roof = None
     if "step_kernel_ms" in f:
         roof = {"bound": "hbm", "achieved": f["step_kernel_gbs"], "peak": HBM_PEAK_GBS,
@@ -214,17 +365,17 @@ def main():
                 "kernel": "k_step<6,fp64>", "bytes_per_launch": cfg.n * f["step_bytes_per_atom"],
                 "launch_ms": f["step_kernel_ms"]}
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg)
+    if not args.no_cpu_baseline and not args.no_md:
+        cpu = cpu_baseline(cfg, f["steps_per_build"])
         log("cpu baseline", json.dumps(cpu))
     line = {
-        "metric": "atom-steps/s at d=6,N=262144",
-        "value": f["value"],
+        "metric": "atom-steps/s at d=6,N=262144; batched FIRE solves/s + p50/p99 latency",
+        "value": f.get("value"),
         "unit": "atom-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f["ms_per_step"],
+        "ms_per_step": f.get("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -239,7 +390,8 @@ def main():
         "fp64": out.get("fp64"),
         "mixed": out.get("mixed"),
         "drift_difference_mixed_minus_fp64": (out["mixed"]["drift_per_tau"] - f["drift_per_tau"])
-        if "mixed" in out else None,
+        if "mixed" in out and f else None,
+        "fire_serving": fire,
     }
     print(json.dumps(line), flush=True)
 

@@ -57,7 +57,7 @@ def main():
     for d in PHI_D:
         v = sorted(r[2] for r in res if r[0] == d)
         out[str(d)] = v[len(v) // 2]
-    out["recipe"] = __doc__.strip().splitlines()[2:]
+    out["recipe"] = " ".join(__doc__.split("Recipe:")[1].split())
     json.dump(out, open(os.path.join(HERE, "phij.json"), "w"), indent=1)
     print(json.dumps(out))
 
