@@ -205,10 +205,19 @@ __device__ inline double wrap1(double x, double L, double h) {
   return x;
 }
 
+// Nearest image for the pair forces: dx - L k with k = rint(dx / L), one
+// rounding (for k = +-1 the same value as dx -+ L).  It can pick the other
+// image only for |dx| within rounding of L/2, far beyond any cutoff, so the
+// force sums are those of the definition; the list test keeps min_image.
+__device__ inline double near_image(double dx, double L, double invL) {
+  return __builtin_fma(-L, rint(dx * invL), dx);
+}
+
+// dx - L when dx > L/2, dx + L (= dx - (-L)) when dx < -L/2, else dx - 0 = dx:
+// one subtraction after selecting the shift (no branches, same values).
 __device__ inline double min_image(double dx, double L, double h) {
-  if (dx > h) dx = dx - L;
-  else if (dx < -h) dx = dx + L;
-  return dx;
+  const double sh = dx > h ? L : (dx < -h ? -L : 0.0);
+  return dx - sh;
 }
 
 template <int D>
@@ -222,13 +231,28 @@ struct Dims {
   static constexpr int QW = (D + 3) / 4;                      // int8x4 words of the offsets
 };
 
+// Device arrays are global memory: accessing them through the global
+// address space gives global_load/store instead of flat ones.
+#define HDMD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const HDMD_GLOBAL T* gbl(const T* p) {
+  return (const HDMD_GLOBAL T*)p;
+}
+template <typename T>
+__device__ inline HDMD_GLOBAL T* gbl(T* p) {
+  return (HDMD_GLOBAL T*)p;
+}
+// plain vector types for loads and stores through those pointers
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef int vi4 __attribute__((ext_vector_type(4)));
+
 // record = (x_0 .. x_{D-1}, sigma, 0 ...)
 template <int D>
 __device__ inline void load_rec(const double* __restrict__ xb, int i, double (&x)[D], double& sg) {
-  const double2* p = reinterpret_cast<const double2*>(xb + (size_t)i * Dims<D>::DR);
+  const HDMD_GLOBAL vd2* p = gbl(reinterpret_cast<const vd2*>(xb + (size_t)i * Dims<D>::DR));
 #pragma unroll
   for (int k = 0; k < Dims<D>::NR; k++) {
-    double2 t = p[k];
+    const vd2 t = p[k];
     if (2 * k < D) x[2 * k] = t.x;
     else sg = t.x;
     if (2 * k + 1 < D) x[2 * k + 1] = t.y;
@@ -244,10 +268,10 @@ __device__ inline void load_x(const double* __restrict__ xb, int i, double (&x)[
 
 template <int D>
 __device__ inline void store_rec(double* __restrict__ xb, int i, const double (&x)[D], double sg) {
-  double2* p = reinterpret_cast<double2*>(xb + (size_t)i * Dims<D>::DR);
+  HDMD_GLOBAL vd2* p = gbl(reinterpret_cast<vd2*>(xb + (size_t)i * Dims<D>::DR));
 #pragma unroll
   for (int k = 0; k < Dims<D>::NR; k++) {
-    double2 t;
+    vd2 t;
     t.x = 2 * k < D ? x[2 * k] : (2 * k == D ? sg : 0.0);
     t.y = 2 * k + 1 < D ? x[2 * k + 1] : (2 * k + 1 == D ? sg : 0.0);
     p[k] = t;
@@ -271,19 +295,26 @@ __device__ inline void store_q(int32_t* __restrict__ qb, int i, const double (&x
   const long long sb = __double_as_longlong(sg);
   v[SQ] = (int)(unsigned)(sb & 0xffffffffll);
   v[SQ + 1] = (int)(unsigned)((unsigned long long)sb >> 32);
-  int4* p = reinterpret_cast<int4*>(qb + (size_t)i * Dims<D>::DQ);
+  HDMD_GLOBAL vi4* p = gbl(reinterpret_cast<vi4*>(qb + (size_t)i * Dims<D>::DQ));
 #pragma unroll
-  for (int k = 0; k < Dims<D>::NQ; k++) p[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  for (int k = 0; k < Dims<D>::NQ; k++) {
+    vi4 t;
+    t.x = v[4 * k];
+    t.y = v[4 * k + 1];
+    t.z = v[4 * k + 2];
+    t.w = v[4 * k + 3];
+    p[k] = t;
+  }
 }
 
 template <int D>
 __device__ inline void load_q(const int32_t* __restrict__ qb, int i, int (&u)[D], double& sg) {
   constexpr int SQ = Dims<D>::SQ;
-  const int4* p = reinterpret_cast<const int4*>(qb + (size_t)i * Dims<D>::DQ);
+  const HDMD_GLOBAL vi4* p = gbl(reinterpret_cast<const vi4*>(qb + (size_t)i * Dims<D>::DQ));
   int v[4 * Dims<D>::NQ];
 #pragma unroll
   for (int k = 0; k < Dims<D>::NQ; k++) {
-    int4 t = p[k];
+    const vi4 t = p[k];
     v[4 * k] = t.x;
     v[4 * k + 1] = t.y;
     v[4 * k + 2] = t.z;

@@ -11,6 +11,8 @@
 //  k_fire_update semi-implicit Euler FIRE update
 //  k_unload      internal -> caller order
 #pragma once
+#include <type_traits>
+
 #include "hdmd_dev.h"
 
 namespace hdmd {
@@ -249,17 +251,20 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
 #pragma unroll
         for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
         // the same offsets as int16 pairs for the candidate-lane build
-        int p16[8];
+        // and |q|^2 in the last word read by the home-atom loads
+        int p16[8], B = 0;
 #pragma unroll
         for (int k = 0; k < 8; k++) p16[k] = 0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
           const int qv = sext8(w[k / 4], k % 4);
           p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
+          B += qv * qv;
         }
+        p16[(D + 1) / 2 < 4 ? 3 : 7] = B;
         int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
         pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
-        if (D > 8) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
+        if (D > 6) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
       }
       s->oid[pn][dst] = keys[q];
     }
@@ -498,43 +503,98 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 // Same list, same row order and the same exact FP64 test as k_build; the
 // work is laid out the other way round.  The linked subcells come in rows of
 // three along the last axis (offsets -1, 0, +1), whose atoms are packed into
-// 64-lane chunks: every lane takes one candidate j, shifts its int8 offsets by
-// the subcell offset into int16 (q'_j = q_j + 250 o, |q'| <= 375) and forms
-// A_j = |q'_j|^2.  The home atoms i of the subcell are then walked uniformly
-// from LDS, each test being
-//   |q'_j - q_i|^2 = A_j + |q_i|^2 - 2 q_i.q'_j  (v_dot2_i32_i16 on int16 pairs)
-// against the same threshold as k_build.  The ballot of each test is filed
-// under its home atom (lane i keeps the ballot of home atom i), so after a
-// chunk lane i holds the
-// 64-bit mask of its surviving candidates.  Every NB chunks the lanes turn
-// back into home atoms and run the exact test on their survivors in chunk
-// and lane order, appending to their own rows.  Lanes are idle only in the
-// ragged last chunk of a row.
+// 64-lane chunks: every lane takes one candidate j, shifts its quantised
+// offsets by the subcell offset (q'_j = q_j + 250 o as int16, |q'| <= 375)
+// and forms A_j = |q'_j|^2.  The home atoms i kept for the row are then
+// walked uniformly, their records (q_i as int16 pairs and B_i = |q_i|^2)
+// coming through the scalar cache, each test being
+//   |q'_j - q_i|^2 < tq  <=>  (tq - A_j) + q_i.(2 q'_j) > B_i
+// (v_dot2_i32_i16 on int16 pairs) against the same threshold as k_build.
+// The ballot of each test is written into lane i of a mask register, so
+// after a chunk lane i holds the 64-bit mask of its surviving candidates.
+// Every NB chunks the lanes turn back into home atoms and run the exact
+// test on their survivors in chunk and lane order, appending to their own
+// rows.
+//
+// A workgroup of G waves takes one home subcell; wave w takes the w-th of G
+// contiguous shares of its atoms (more waves in flight per subcell at the
+// price of repeating the candidate set-up), with no barrier between waves.
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(64) void k_build_t(KArgs a) {
-  constexpr int QW = Dims<D>::QW;
-  constexpr int HW = (D + 1) / 2;  // int16 pair words
-  constexpr int NB = 8;            // chunks per exact pass
-  __shared__ int hrec[65 * 8];     // home atoms (+ a never-passing sentinel at 64):
-                                   // HW int16 pair words of 2 q_i, then |q_i|^2
-  __shared__ unsigned long long msk[NB * 64];
-  __shared__ int cand[NB * 64];
-  const int lane = threadIdx.x;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+// Uniform loads of the home records go through the scalar cache: read
+// through the constant address space, which tells the compiler that the
+// kernel does not write them (they come from an earlier kernel).
+typedef __attribute__((address_space(4))) const v4i cv4i;
+typedef __attribute__((address_space(4))) const v8i cv8i;
+
+// A pointer that is the same in every lane, moved into scalar registers (a
+// pointer read from device memory lands in vector registers otherwise).
+template <typename T>
+__device__ inline T* uniform_ptr(T* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline double uniform_dbl(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The lane-write intrinsic (v_writelane_b32): returns `old` with lane `ln`
+// replaced by the uniform `val`.
+__device__ int amdgcn_writelane(int val, int ln, int old) __asm("llvm.amdgcn.writelane");
+
+// Orders this wave's LDS writes before its later LDS reads (other lanes).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int D, int G>
+__global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
+  constexpr int HW = (D + 1) / 2;        // int16 pair words of q
+  constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
+  constexpr int BW = RW - 1;             // word of B = |q|^2
+  constexpr int NB = 8;                  // chunks per exact pass
+  typedef typename std::conditional<RW == 4, v4i, v8i>::type Rec;
+  typedef typename std::conditional<RW == 4, cv4i, cv8i>::type CRec;
+  typedef short short2v __attribute__((ext_vector_type(2)));
+  __shared__ unsigned long long msk_all[G][NB * 64];
+  __shared__ int cand_all[G][NB * 64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned long long* msk = msk_all[wv];
+  int* cand = cand_all[wv];
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int hc;
     if (!fetch_cell_tile(a, t, s, hc)) break;
+    s = uniform_ptr(s);
+    hc = uniform_int(hc);
     if (!running(s) || !need_rebuild(s)) continue;
-    const int* __restrict__ flat = s->cell_flat;
-    const int h0 = __builtin_amdgcn_readfirstlane(flat[hc]);
-    const int h1 = __builtin_amdgcn_readfirstlane(flat[hc + 1]);
-    if (h0 == h1) continue;
-    const int nc = s->ncell, npad = s->npad, W = s->width, tq = s->tq;
-    const double* __restrict__ xb = s->x[s->xcur];
-    const int* __restrict__ qc = s->qc;
-    int* __restrict__ nl = s->nl;
-    const double L = s->L, hL = s->hL, cut = s->cutoff, skin = s->skin;
+    const int* __restrict__ flat = uniform_ptr(s->cell_flat);
+    const int c0h = uniform_int(flat[hc]);
+    const int c1h = uniform_int(flat[hc + 1]);
+    // this wave's share of the home atoms
+    const int per = (c1h - c0h + G - 1) / G;
+    const int h0 = c0h + wv * per;
+    const int h1 = min(c1h, h0 + per);
+    if (h0 >= h1) continue;
+    const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
+    const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
+    const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
+    const int* __restrict__ qc16 = uniform_ptr(s->qc16);
+    HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
+    const double L = uniform_dbl(s->L), hL = uniform_dbl(s->hL);
+    const double cut = uniform_dbl(s->cutoff), skin = uniform_dbl(s->skin);
     int ci[D], stride[D];
     {
       int u = hc, st = 1;
@@ -557,55 +617,64 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
       const int i = hb + lane;
       const bool vi = lane < hcnt;
       const int ii = vi ? i : hb;
-      double xi[D], si;
-      load_rec<D>(xb, ii, xi, si);
       int qh[D];
       {
-        int w[QW];
-#pragma unroll
-        for (int k = 0; k < QW; k++) w[k] = qc[(size_t)ii * 4 + k];
-        int q[2 * HW], B = 0;
-#pragma unroll
-        for (int k = 0; k < 2 * HW; k++) q[k] = 0;
+        const v4i w0 = *reinterpret_cast<const v4i*>(qc16 + (size_t)ii * 8);
+        int w[4] = {w0.x, w0.y, w0.z, w0.w};
+        int w1[4] = {0, 0, 0, 0};
+        if (HW > 4) {
+          const v4i u1 = *reinterpret_cast<const v4i*>(qc16 + (size_t)ii * 8 + 4);
+          w1[0] = u1.x;
+        }
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          q[k] = sext8(w[k / 4], k % 4);
-          B += q[k] * q[k];
-          qh[k] = q[k];
+          const int word = k / 2 < 4 ? w[k / 2] : w1[k / 2 - 4];
+          qh[k] = (k % 2) ? (word >> 16) : (int)(short)(word & 0xffff);
         }
-        __syncthreads();  // previous home chunk done with hrec
-#pragma unroll
-        for (int k = 0; k < HW; k++)
-          hrec[lane * 8 + k] = ((2 * q[2 * k]) & 0xffff) | ((2 * q[2 * k + 1]) << 16);
-        hrec[lane * 8 + 7] = vi ? B : 0x7fffffff;
-        if (lane == 0) hrec[64 * 8 + 7] = 0x7fffffff;
       }
       int len = 0, nb = 0;
 
       auto exact_pass = [&]() {
-        __syncthreads();
-        for (int b = 0; b < nb; b++) {
-          unsigned long long m = msk[b * 64 + lane];
-          while (m) {
-            const int bit = __builtin_ctzll(m);
-            m &= m - 1;
-            const int j = cand[b * 64 + bit];
-            if (vi && j != i) {
-              double xj[D], sj;
-              load_rec<D>(xb, j, xj, sj);
-              const double r2 = dist2_exact<D>(xi, xj, L, hL);
-              if (r2 < list_r2(si, sj, cut, skin)) {
-                if (len < W) nl[(size_t)len * npad + i] = j;
-                len++;
-              }
+        wave_lds_sync();
+        double xi[D], si;  // own record, reloaded (cache hit) to keep registers free
+        load_rec<D>(xb, ii, xi, si);
+        int base = -64;
+        unsigned long long m = 0;
+        auto pop = [&](int& j) -> bool {
+          while (m == 0) {
+            base += 64;
+            if (base >= nb * 64) return false;
+            m = msk[base + lane];
+          }
+          const int bit = __builtin_ctzll(m);
+          m &= m - 1;
+          j = cand[base + bit];
+          return true;
+        };
+        int j = 0;
+        while (pop(j)) {
+          double xj[D], sj;
+          load_rec<D>(xb, j, xj, sj);
+          if (j != i) {
+            // the list definition's distance, one axis after the other (keeps
+            // few registers live)
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+              const double dx = min_image(xj[k] - xi[k], L, hL);
+              r2 = __builtin_fma(dx, dx, r2);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            if (r2 < list_r2(si, sj, cut, skin)) {
+              if (len < W) nl[(size_t)len * npad + i] = j;
+              len++;
             }
           }
         }
-        __syncthreads();
+        wave_lds_sync();
         nb = 0;
       };
 
-      __syncthreads();
       int dg[D];
 #pragma unroll
       for (int k = 0; k < D; k++) dg[k] = 0;
@@ -621,16 +690,6 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
           P += c2 * stride[k];
           Dp[k / 2] |= ((kQScale * o) & 0xffff) << (16 * (k % 2));
         }
-        // offset of the last axis (-1, 0, +1 subcells) in its int16 half
-        const int lsh = 16 * ((D - 1) % 2);
-        const int lastp[3] = {(-kQScale & 0xffff) << lsh, 0, (kQScale & 0xffff) << lsh};
-        const int st0 = __builtin_amdgcn_readfirstlane(flat[P + lm]);
-        const int c0 = __builtin_amdgcn_readfirstlane(flat[P + lm + 1]) - st0;
-        const int st1 = __builtin_amdgcn_readfirstlane(flat[P + cl]);
-        const int c1 = __builtin_amdgcn_readfirstlane(flat[P + cl + 1]) - st1;
-        const int st2 = __builtin_amdgcn_readfirstlane(flat[P + lp]);
-        const int c2n = __builtin_amdgcn_readfirstlane(flat[P + lp + 1]) - st2;
-        const int T = c0 + c1 + c2n;
         // home atoms that can reach this row: gap to the neighbouring faces
         // along the first d-1 axes, one quantisation unit short per axis
         unsigned long long keep;
@@ -643,77 +702,86 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
             g = (o == 0 || g < 0) ? 0 : g;
             S += g * g;
           }
-          keep = __ballot(vi && S < s->tcull);
+          keep = __ballot(vi && S < tcull);
         }
-        for (int k0 = 0; keep != 0 && k0 < T; k0 += 64) {
+        // next row: odometer over the first D-1 axes, last digit fastest
+        int dgn[D];
+#pragma unroll
+        for (int k = 0; k < D; k++) dgn[k] = dg[k];
+#pragma unroll
+        for (int k = D - 2; k >= 0; k--) {
+          if (++dgn[k] < 3) break;
+          dgn[k] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < D; k++) dg[k] = dgn[k];
+        if (keep == 0) continue;
+        // offset of the last axis (-1, 0, +1 subcells) in its int16 half
+        const int lsh = 16 * ((D - 1) % 2);
+        const int lastp[3] = {(-kQScale & 0xffff) << lsh, 0, (kQScale & 0xffff) << lsh};
+        const int st0 = __builtin_amdgcn_readfirstlane(flat[P + lm]);
+        const int n0 = __builtin_amdgcn_readfirstlane(flat[P + lm + 1]) - st0;
+        const int st1 = __builtin_amdgcn_readfirstlane(flat[P + cl]);
+        const int n1 = __builtin_amdgcn_readfirstlane(flat[P + cl + 1]) - st1;
+        const int st2 = __builtin_amdgcn_readfirstlane(flat[P + lp]);
+        const int n2 = __builtin_amdgcn_readfirstlane(flat[P + lp + 1]) - st2;
+        const int T = n0 + n1 + n2;
+        for (int k0 = 0; k0 < T; k0 += 64) {
           const int tt = k0 + lane;
           const bool valid = tt < T;
-          const int seg = tt < c0 ? 0 : (tt < c0 + c1 ? 1 : 2);
-          const int j = seg == 0 ? st0 + tt : (seg == 1 ? st1 + tt - c0 : st2 + tt - c0 - c1);
-          typedef short short2v __attribute__((ext_vector_type(2)));
+          const int seg = tt < n0 ? 0 : (tt < n0 + n1 ? 1 : 2);
+          const int j = seg == 0 ? st0 + tt : (seg == 1 ? st1 + tt - n0 : st2 + tt - n0 - n1);
           int cw[HW];
 #pragma unroll
           for (int k = 0; k < HW; k++) cw[k] = 0;
           int tA = -0x3fffffff;  // tq - A_j; never passes for an empty lane
           if (valid) {
-            const int* src = s->qc16 + (size_t)j * 8;
+            const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)j * 8);
             int A = 0;
 #pragma unroll
             for (int k = 0; k < HW; k++) {
               // shift by the subcell offset as packed int16 adds, then A_j += |pair|^2
               const short2v q2 = __builtin_bit_cast(short2v, src[k]);
-              const short2v o2 = __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastp[seg] : 0));
+              const short2v o2 =
+                  __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastp[seg] : 0));
               const short2v r2 = q2 + o2;
-              cw[k] = __builtin_bit_cast(int, r2);
               A = __builtin_amdgcn_sdot2(r2, r2, A, false);
+              cw[k] = __builtin_bit_cast(int, r2 + r2);
             }
             tA = tq - A;
           }
           cand[nb * 64 + lane] = valid ? j : -1;
-          msk[nb * 64 + lane] = 0ull;
-          // tq - A_j + (2 q_i).q'_j > |q_i|^2  <=>  |q'_j - q_i|^2 < tq,
-          // for the home atoms kept for this row, four at a time
+          // (tq - A_j) + q_i.(2 q'_j) > B_i for the home atoms kept for this
+          // row, four at a time (a short last group repeats its last atom)
+          unsigned mlo = 0u, mhi = 0u;
           unsigned long long km = keep;
           while (km) {
             int hh[4];
+            hh[0] = __builtin_ctzll(km);
+            km &= km - 1;
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-              hh[u] = km ? __builtin_ctzll(km) : 64;  // 64: sentinel record
+            for (int u = 1; u < 4; u++) {
+              hh[u] = km ? __builtin_ctzll(km) : hh[u - 1];
               km &= km - 1;
             }
-            int hr[4][8];
+            Rec r[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) r[u] = *(CRec*)(qc16 + (size_t)(hb + hh[u]) * 8);
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-#pragma unroll
-              for (int k = 0; k < HW; k++) hr[u][k] = hrec[hh[u] * 8 + k];
-              hr[u][7] = hrec[hh[u] * 8 + 7];
-            }
-            unsigned long long m[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              typedef short short2v __attribute__((ext_vector_type(2)));
               int acc = tA;
 #pragma unroll
               for (int k = 0; k < HW; k++)
-                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, hr[u][k]),
+                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
                                              __builtin_bit_cast(short2v, cw[k]), acc, false);
-              m[u] = __ballot(acc > hr[u][7]);
-            }
-            // file the ballots under their home atoms (one lane writes them)
-            if (lane == 0) {
-#pragma unroll
-              for (int u = 0; u < 4; u++)
-                if (hh[u] < 64) msk[nb * 64 + hh[u]] = m[u];
+              const unsigned long long m = __ballot(acc > r[u][BW]);
+              mlo = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo);
+              mhi = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi);
             }
           }
+          msk[nb * 64 + lane] = ((unsigned long long)mhi << 32) | mlo;
           nb++;
           if (nb == NB) exact_pass();
-        }
-        // next row: odometer over the first D-1 axes, last digit fastest
-#pragma unroll
-        for (int k = D - 2; k >= 0; k--) {
-          if (++dg[k] < 3) break;
-          dg[k] = 0;
         }
       }
       exact_pass();
@@ -735,18 +803,38 @@ __global__ __launch_bounds__(64) void k_build_t(KArgs a) {
 // ---------------------------------------------------------------------------
 // F_i = sum_j fc (x_i - x_j) with fc = -U'(r)/r for r < c sigma_ij;
 // e_i = 1/2 sum_j U(r).
+// 1/x from the hardware reciprocal estimate and two Newton-Raphson steps
+// (each squares the relative error): within an ulp or two of 1/x.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
+}
+
+// 1/sqrt(x) from the hardware estimate and two Newton-Raphson steps
+// y <- y (3/2 - x y^2 / 2).
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = __builtin_fma(y, __builtin_fma(-hx * y, y, 0.5), y);
+  y = __builtin_fma(y, __builtin_fma(-hx * y, y, 0.5), y);
+  return y;
+}
+
 __device__ inline void pair_f64(int pot, double eps, double r2, double sij, double& fc,
                                 double& u) {
   if (pot == 0) {  // WCA
-    const double inv = 1.0 / r2;
+    const double inv = recip(r2);
     const double s2 = sij * sij * inv;
     const double s6 = s2 * s2 * s2;
     fc = 24.0 * eps * (2.0 * s6 * s6 - s6) * inv;
     u = 4.0 * eps * (s6 * s6 - s6) + eps;
   } else {         // harmonic soft spheres
-    const double r = sqrt(r2);
-    const double g = 1.0 - r / sij;
-    fc = eps * g / (sij * r);
+    const double ir = rsqrt_nr(r2);  // 1/r
+    const double is = recip(sij);
+    const double g = 1.0 - (r2 * ir) * is;
+    fc = eps * g * is * ir;
     u = 0.5 * eps * g * g;
   }
 }
@@ -768,9 +856,9 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
                                   FT (&F)[D], double& e) {
   constexpr int U = MIX ? 4 : 2;
   const int npad = s->npad;
-  const int len = min(s->nlen[i], s->width);
-  const int* __restrict__ nl = s->nl;
-  const double L = s->L, h = s->hL, c = s->cutoff, eps = s->eps;
+  const int len = min(gbl(s->nlen)[i], s->width);
+  const HDMD_GLOBAL int* __restrict__ nl = gbl(s->nl);
+  const double L = s->L, c = s->cutoff, eps = s->eps, invL = 1.0 / L;
   const int pot = s->potential;
   const double* __restrict__ xb = s->x[s->xcur];
   const int32_t* __restrict__ qb = MIX ? s->q[s->xcur] : nullptr;
@@ -778,11 +866,16 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
   for (int k = 0; k < D; k++) F[k] = FT(0);
   e = 0.0;
+  // row entries are read unconditionally from a clamped (in-bounds) slot and
+  // masked afterwards, so the loads issue without branches and the wait for
+  // the current group does not also wait for the prefetched one
+  const int wm1 = s->width - 1;
   int jn[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
     const int kk = sub + u * LPA;
-    jn[u] = kk < len ? nl[(size_t)kk * npad + i] : -1;
+    const int raw = nl[(size_t)min(kk, wm1) * npad + i];
+    jn[u] = kk < len ? raw : -1;
   }
   for (int k0 = sub; k0 < len; k0 += U * LPA) {
     int jj[U];
@@ -790,7 +883,8 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
     for (int u = 0; u < U; u++) {
       jj[u] = jn[u];
       const int kk = k0 + (U + u) * LPA;
-      jn[u] = kk < len ? nl[(size_t)kk * npad + i] : -1;
+      const int raw = nl[(size_t)min(kk, wm1) * npad + i];
+      jn[u] = kk < len ? raw : -1;
     }
     if (!MIX) {
       double xj[U][D], sj[U];
@@ -805,7 +899,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          dx[k] = min_image(xj[u][k] - me.x[k], L, h);
+          dx[k] = near_image(xj[u][k] - me.x[k], L, invL);
           r2 = __builtin_fma(dx[k], dx[k], r2);
         }
         if (r2 < rc * rc) {

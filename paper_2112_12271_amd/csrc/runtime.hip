@@ -353,8 +353,8 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_blk = blk;
-    for (int cand : {1, 64, 128, 256}) {
-      if (cand == 1 && p.wrap) continue;
+    for (int cand : {1, 2, 4, 64, 128, 256}) {
+      if (cand < 64 && p.wrap) continue;
       K->build(p.wrap, cand, a, p.ncells, st);  // warm-up
       HIPCHK(hipEventRecord(e0, st));
       K->build(p.wrap, cand, a, p.ncells, st);

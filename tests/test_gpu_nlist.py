@@ -136,3 +136,32 @@ def test_full_size_sampled_rows(orc, name):
     fwd = rows.astype(np.int64) * cfg.n + cols
     bwd = cols.astype(np.int64) * cfg.n + rows
     assert np.array_equal(np.sort(fwd), np.sort(bwd))
+
+
+@pytest.mark.parametrize("d,nc,per_cell", [(3, 3, 150), (4, 3, 140), (6, 3, 10), (8, 3, 1)])
+def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
+    """Each list-build variant (candidate-lane with 1, 2 or 4 waves per subcell,
+    home-lane with 64/128/256 lanes), forced in turn, gives the definition's
+    list; crowded subcells (more than 64 and 128 atoms) take several home passes."""
+    import os
+    c, s = C6, 0.3
+    rlmax = c * 1.4 + s
+    L = nc * rlmax * 1.02
+    n = per_cell * nc ** d
+    x, sig = partnered(d, n, L, 77 * d + nc, rlmax)
+    ref = orc.nlist_brute(x, sig, L, c, s)
+    old = os.environ.get("HDMD_BUILD_BLK")
+    try:
+        for blk in (1, 2, 4, 64, 128, 256):
+            os.environ["HDMD_BUILD_BLK"] = str(blk)
+            for prec in (H.HDMD_FP64, H.HDMD_MIXED):
+                sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4,
+                                precision=prec, max_neighbors=16)
+                assert H.hdmd_cells_per_axis(sysd) == nc
+                got, _, _ = gpu_list(sysd, x, sig)
+                assert csr_equal(got, ref), (d, blk, prec)
+    finally:
+        if old is None:
+            os.environ.pop("HDMD_BUILD_BLK", None)
+        else:
+            os.environ["HDMD_BUILD_BLK"] = old

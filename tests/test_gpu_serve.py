@@ -38,10 +38,10 @@ def _alone(req, width, params, prec):
     X = dev(req.x)
     if req.kind == "fire":
         res = H.hdmd_fire_minimize(sysd, X, dev(req.sig), ws, params)
-        return X.cpu().numpy(), res.iterations
+        return X.cpu().numpy(), res.iterations, res.status
     V = dev(req.v)
     st, _ = H.hdmd_step(sysd, X, V, dev(req.sig), ws, req.nsteps, req.dt)
-    return X.cpu().numpy(), st.steps_done
+    return X.cpu().numpy(), st.steps_done, 0
 
 
 @pytest.mark.parametrize("prec", [H.HDMD_MIXED])
@@ -64,7 +64,9 @@ def test_mix_equals_alone(prec):
                                  req.cutoff * float(req.sig.max()) + req.skin)
         for _ in range(r.retries):      # the server widens a row capacity per retry
             width = int(width * 1.5) + 16
-        xa, it = _alone(req, width, params, prec)
-        assert r.status == 0
+        xa, it, st = _alone(req, width, params, prec)
+        # a minimisation may stop at the iteration cap (status 1); either way
+        # the mix must reproduce the lone run
+        assert r.status in (0, 1) and r.status == st, r.rid
         assert r.iterations == it, r.rid
         assert np.array_equal(r.x, xa), r.rid
