@@ -672,34 +672,25 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
       auto exact_one = [&](int set, int ii, int i, int& len) {
         double xi[D], si;  // own record, reloaded (cache hit) to keep registers free
         load_rec<D>(xb, ii, xi, si);
-        int base = -128;
-        unsigned long long m = 0;
-        auto pop = [&](int& j) -> bool {
-          while (m == 0) {
-            base += 128;
-            if (base >= nb * 128) return false;
-            m = msk[base + set * 64 + lane];
-          }
-          const int bit = __builtin_ctzll(m);
-          m &= m - 1;
-          j = cand[(base >> 1) + bit];
-          return true;
-        };
-        int j = 0;
-        while (pop(j)) {
-          double xj[D], sj;
-          load_rec<D>(xb, j, xj, sj);
-          if (j != i) {
-            double r2 = 0.0;
+        for (int b = 0; b < nb; b++) {
+          unsigned long long m = msk[b * 128 + set * 64 + lane];
+          while (m) {
+            const int j = cand[b * 64 + __builtin_ctzll(m)];
+            m &= m - 1;
+            double xj[D], sj;
+            load_rec<D>(xb, j, xj, sj);
+            if (j != i) {
+              double r2 = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; k++) {
-              const double dx = near_image(xj[k] - xi[k], L, invL);
-              r2 = __builtin_fma(dx, dx, r2);
-              __builtin_amdgcn_sched_barrier(0);
-            }
-            if (r2 < list_r2(si, sj, cut, skin)) {
-              if (len < W) nl[(size_t)len * npad + i] = j;
-              len++;
+              for (int k = 0; k < D; k++) {
+                const double dx = near_image(xj[k] - xi[k], L, invL);
+                r2 = __builtin_fma(dx, dx, r2);
+                __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
+              }
+              if (r2 < list_r2(si, sj, cut, skin)) {
+                if (len < W) nl[(size_t)len * npad + i] = j;
+                len++;
+              }
             }
           }
         }
@@ -784,6 +775,7 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
           int cw[CB][HW], tA[CB];
 #pragma unroll
           for (int c = 0; c < CB; c++) {
+            if (c >= nch) continue;
             const int tt = k0 + c * 64 + lane;
             const bool valid = c < nch && tt < T;
             const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
@@ -801,7 +793,7 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
               cw[c][k] = __builtin_bit_cast(int, r2 + r2);
             }
             tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
-            if (c < nch) cand[(nb + c) * 64 + lane] = valid ? j : -1;
+            cand[(nb + c) * 64 + lane] = valid ? j : -1;
           }
           // (tq - A_j) + q_i.(2 q'_j) > B_i  <=>  |q'_j - q_i|^2 < tq
           unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
