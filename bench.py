@@ -200,7 +200,7 @@ def per_instance(H, torch, reqs, prec, f_tol, max_iter):
                 width = int(width * 1.5) + 16
         now = time.perf_counter() - t0
         out.append(S.Result(r.rid, "fire", r.d, r.n, r.arrival, now, now, res.iterations,
-                            res.fmax, res.energy, res.status, 0))
+                            res.fmax, res.energy, res.status, 0, None, res.builds))
     return out, time.perf_counter() - t0
 
 
@@ -224,6 +224,8 @@ def fire_record(res, wall):
     rec.update(converged=int(sum(r.status == 0 for r in res)),
                fmax_final_max=float(f.max()) if len(f) else None,
                iterations_total=int(sum(r.iterations for r in res)),
+               iterations_max=int(max((r.iterations for r in res), default=0)),
+               builds_total=int(sum(r.builds for r in res)),
                atoms_total=int(sum(r.n for r in res)))
     return rec
 

@@ -17,8 +17,10 @@
 //   xref      positions at the last build [d][npad] FP64 (rebuild trigger).
 //   qc        offsets from the subcell centre quantised to int8 in units of
 //             L_sc/250, packed four per int32 (prefilter of the list build
-//             when n_cell >= 3); qc16 the same as int16 pairs; ycell the
-//             offsets in FP32 (prefilter when n_cell <= 2).
+//             when n_cell >= 3); qc16 the same as int16 pairs with |q|^2 in
+//             the last word read, or, when n_cell <= 2, 16-bit coordinates
+//             wrapping at L; ycell the offsets in FP32 (home-lane build when
+//             n_cell <= 2).
 //   nl, nlen  Verlet rows in ELL form, column-major nl[k*npad + i], i.e. entry
 //             k of every row is contiguous so a wave reads it coalesced.
 // Atoms are stored in subcell order (canonical: by subcell, then caller id),
@@ -79,7 +81,7 @@ struct SysDev {
   double* xref;
   float* ycell;
   int32_t* qc;
-  int32_t* qc16;  // the same offsets as int16 pairs, [npad][8]
+  int32_t* qc16;  // int16 offsets or wrapped 16-bit coordinates, [npad][8]
   int32_t* cell_of;
   int32_t* rank;
   int32_t* cell_count;

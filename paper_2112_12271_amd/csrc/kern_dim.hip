@@ -28,13 +28,16 @@ void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
 }
 void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
   if (wrap) {
-    if (blk <= 64) k_build<D, true, 64><<<grid, 64, 0, st>>>(a);
+    if (blk == 1) k_build_t<D, 1, true><<<grid, 64, 0, st>>>(a);
+    else if (blk == 2) k_build_t<D, 2, true><<<grid, 128, 0, st>>>(a);
+    else if (blk == 4) k_build_t<D, 4, true><<<grid, 256, 0, st>>>(a);
+    else if (blk <= 64) k_build<D, true, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, true, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, true, 256><<<grid, 256, 0, st>>>(a);
   } else {
-    if (blk == 1) k_build_t<D, 1><<<grid, 64, 0, st>>>(a);
-    else if (blk == 2) k_build_t<D, 2><<<grid, 128, 0, st>>>(a);
-    else if (blk == 4) k_build_t<D, 4><<<grid, 256, 0, st>>>(a);
+    if (blk == 1) k_build_t<D, 1, false><<<grid, 64, 0, st>>>(a);
+    else if (blk == 2) k_build_t<D, 2, false><<<grid, 128, 0, st>>>(a);
+    else if (blk == 4) k_build_t<D, 4, false><<<grid, 256, 0, st>>>(a);
     else if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);

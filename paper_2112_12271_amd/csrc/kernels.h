@@ -241,6 +241,21 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
         float4* yp = reinterpret_cast<float4*>(s->ycell + (size_t)dst * DY);
 #pragma unroll
         for (int k = 0; k < DY / 4; k++) yp[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
+        // 16-bit coordinates u = (x + L/2) 2^16 / L, wrapping at L: the 16-bit
+        // difference u_j - u_i is the minimum-image displacement in L/2^16
+        // units (candidate-lane build with n_cell <= 2)
+        const double ws16 = 65536.0 / s->L;
+        int p16[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) p16[k] = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          const int u = (int)((long long)rint((x[k] + s->hL) * ws16) & 0xffff);
+          p16[k / 2] |= u << (16 * (k % 2));
+        }
+        int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
+        pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
+        pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
       } else {
         int w[QW];
 #pragma unroll
@@ -558,7 +573,7 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <int D, int G>
+template <int D, int G, bool WR>
 __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
   constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
@@ -597,7 +612,7 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
     const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
     const int* __restrict__ qc16 = uniform_ptr(s->qc16);
     HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
-    const double L = uniform_dbl(s->L), invL = 1.0 / L;
+    const double L = uniform_dbl(s->L), invL = 1.0 / L, hL = uniform_dbl(s->hL);
     const double cut = uniform_dbl(s->cutoff), skin = uniform_dbl(s->skin);
     int ci[D - 1], stride[D - 1];
     int cl;
@@ -614,10 +629,14 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
         st *= nc;
       }
     }
+    // rows of linked subcells: radix 3 (offsets -1, 0, +1) or, for n_cell <= 2,
+    // radix n_cell (offsets 0, +1: the deduplicated stencil)
+    const int R = WR ? nc : 3;
     int nrow = 1;
 #pragma unroll
-    for (int k = 0; k < D - 1; k++) nrow *= 3;
-    const int lm = cl == 0 ? nc - 1 : cl - 1, lp = cl == nc - 1 ? 0 : cl + 1;
+    for (int k = 0; k < D - 1; k++) nrow *= R;
+    const int lm = WR ? cl : (cl == 0 ? nc - 1 : cl - 1);
+    const int lp = cl == nc - 1 ? 0 : cl + 1;
     // offsets of the last axis (-1, 0, +1 subcells) in their int16 half
     constexpr int lsh = 16 * ((D - 1) % 2);
     const int lastm = (int)((unsigned)(-kQScale & 0xffff) << lsh);
@@ -630,8 +649,8 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
       for (int k = 0; k < HW; k++) Dp[k] = 0;
 #pragma unroll
       for (int k = D - 2; k >= 0; k--) {
-        const int o = r % 3 - 1;
-        r /= 3;
+        const int o = WR ? r % R : r % 3 - 1;
+        r /= R;
         og[k] = o;
         int c2 = ci[k] + o;
         c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
@@ -656,7 +675,16 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
 #pragma unroll
         for (int k = 0; k < D; k++) {
           const int word = w[k / 2];
-          qh[k] = (k % 2) ? (word >> 16) : (int)(short)(word & 0xffff);
+          if (WR) {
+            // gap to the other subcell along axis k (n_cell = 2: it touches both
+            // faces), one unit short: L_sc/2 - |u - centre| - 1 in 2^16/L units
+            const int u = (k % 2) ? ((word >> 16) & 0xffff) : (word & 0xffff);
+            const int cc = (k < D - 1 ? ci[k < D - 1 ? k : 0] : cl) * 32768 + 16384;
+            const int y = (int)(short)((u - cc) & 0xffff);
+            qh[k] = max(16384 - abs(y) - 1, 0);
+          } else {
+            qh[k] = (k % 2) ? (word >> 16) : (int)(short)(word & 0xffff);
+          }
         }
       };
       own_q(ii0, qh0);
@@ -683,7 +711,8 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
               double r2 = 0.0;
 #pragma unroll
               for (int k = 0; k < D; k++) {
-                const double dx = near_image(xj[k] - xi[k], L, invL);
+                const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
+                                     : near_image(xj[k] - xi[k], L, invL);
                 r2 = __builtin_fma(dx, dx, r2);
                 __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
               }
@@ -725,12 +754,26 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
             if (c >= nch) break;
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-              int acc = tA[c];
+              unsigned long long m;
+              if (WR) {
+                // |u_j - u_i|^2 over 16-bit wrapped differences (saturating: far
+                // pairs clamp at INT_MAX) against the lane's threshold
+                int acc = 0;
 #pragma unroll
-              for (int k = 0; k < HW; k++)
-                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
-                                             __builtin_bit_cast(short2v, cw[c][k]), acc, false);
-              const unsigned long long m = __ballot(acc > r[u][BW]);
+                for (int k = 0; k < HW; k++) {
+                  const short2v dq = __builtin_bit_cast(short2v, cw[c][k]) -
+                                     __builtin_bit_cast(short2v, (int)r[u][k]);
+                  acc = __builtin_amdgcn_sdot2(dq, dq, acc, true);
+                }
+                m = __ballot(acc < tA[c]);
+              } else {
+                int acc = tA[c];
+#pragma unroll
+                for (int k = 0; k < HW; k++)
+                  acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
+                                               __builtin_bit_cast(short2v, cw[c][k]), acc, false);
+                m = __ballot(acc > r[u][BW]);
+              }
               mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo[c]);
               mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi[c]);
             }
@@ -749,10 +792,16 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
 #pragma unroll
           for (int k = 0; k < D - 1; k++) {
             const int o = og[k];
-            int g0 = (kQScale / 2) - o * qh0[k] - 1;
-            int g1 = (kQScale / 2) - o * qh1[k] - 1;
-            g0 = (o == 0 || g0 < 0) ? 0 : g0;
-            g1 = (o == 0 || g1 < 0) ? 0 : g1;
+            int g0, g1;
+            if (WR) {
+              g0 = o ? qh0[k] : 0;
+              g1 = o ? qh1[k] : 0;
+            } else {
+              g0 = (kQScale / 2) - o * qh0[k] - 1;
+              g1 = (kQScale / 2) - o * qh1[k] - 1;
+              g0 = (o == 0 || g0 < 0) ? 0 : g0;
+              g1 = (o == 0 || g1 < 0) ? 0 : g1;
+            }
             S0 += g0 * g0;
             S1 += g1 * g1;
           }
@@ -760,12 +809,14 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
           keep1 = __ballot(v1 && S1 < tcull);
         }
         if ((keep0 | keep1) == 0) continue;
+        // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
         const int st0 = flat[P + lm];
         const int n0 = flat[P + lm + 1] - st0;
-        const int st1 = flat[P + cl];
-        const int n1 = flat[P + cl + 1] - st1;
-        const int st2 = flat[P + lp];
-        const int n2 = flat[P + lp + 1] - st2;
+        const int c1 = WR ? lp : cl;
+        const int st1 = (WR && R < 2) ? 0 : flat[P + c1];
+        const int n1 = (WR && R < 2) ? 0 : flat[P + c1 + 1] - st1;
+        const int st2 = WR ? 0 : flat[P + lp];
+        const int n2 = WR ? 0 : flat[P + lp + 1] - st2;
         const int T = n0 + n1 + n2;
         for (int k0 = 0; k0 < T; k0 += CB * 64) {
           const int nch = min(CB, (T - k0 + 63) / 64);
@@ -782,17 +833,23 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
             const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
             const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
             const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
-            int A = 0;
+            if (WR) {
 #pragma unroll
-            for (int k = 0; k < HW; k++) {
-              const short2v q2 = __builtin_bit_cast(short2v, src[k]);
-              const short2v o2 =
-                  __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
-              const short2v r2 = q2 + o2;
-              A = __builtin_amdgcn_sdot2(r2, r2, A, false);
-              cw[c][k] = __builtin_bit_cast(int, r2 + r2);
+              for (int k = 0; k < HW; k++) cw[c][k] = src[k];
+              tA[c] = valid ? tq : -1;  // the lane's threshold; none for an empty lane
+            } else {
+              int A = 0;
+#pragma unroll
+              for (int k = 0; k < HW; k++) {
+                const short2v q2 = __builtin_bit_cast(short2v, src[k]);
+                const short2v o2 =
+                    __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
+                const short2v r2 = q2 + o2;
+                A = __builtin_amdgcn_sdot2(r2, r2, A, false);
+                cw[c][k] = __builtin_bit_cast(int, r2 + r2);
+              }
+              tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
             }
-            tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
             cand[(nb + c) * 64 + lane] = valid ? j : -1;
           }
           // (tq - A_j) + q_i.(2 q'_j) > B_i  <=>  |q'_j - q_i|^2 < tq

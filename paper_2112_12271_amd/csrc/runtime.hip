@@ -122,7 +122,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.off_xref = take(np * p.d * 8);
   p.off_ycell = take(p.wrap ? np * p.dy * 4 : 0);
   p.off_qc = take(p.wrap ? 0 : np * 16);
-  p.off_qc16 = take(p.wrap ? 0 : np * 32);
+  p.off_qc16 = take(np * 32);
   p.off_cell_of = take(np * 4);
   p.off_rank = take(np * 4);
   p.off_cell_count = take((size_t)p.ncells * 4);
@@ -175,7 +175,17 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.fxscale = 4294967296.0 / s->box_l;
   h.fxinv = s->box_l / 4294967296.0;
   h.qinv = (double)kQScale / h.lsc;
-  {
+  if (p.wrap) {
+    // n_cell <= 2: prefilter on 16-bit wrapped coordinates, unit Delta = L/2^16;
+    // |u_j - u_i|^2 < tq keeps every pair within r_l,max (each axis is off by
+    // at most one unit), and a row is skipped when the gaps to its subcells,
+    // one unit short per axis, reach r_l,max
+    const double delta = s->box_l / 65536.0;
+    const double thr = p.rlmax / delta + std::sqrt((double)p.d) * (1.0 + 1e-6);
+    h.tq = (int32_t)std::min(std::floor(thr * thr) + 1.0, 2147483000.0);
+    const double rc = p.rlmax / delta;
+    h.tcull = (int32_t)std::min(std::ceil(rc * rc), 2147483000.0);
+  } else {
     // int8 prefilter threshold: ((r_l,max + Delta sqrt(d)) / Delta)^2, Delta =
     // L_sc / 250, rounded down and made strict (+1), with slack on sqrt(d)
     const double delta = h.lsc / (double)kQScale;
@@ -203,7 +213,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.xref = at<double>(ws, p.off_xref);
   h.ycell = p.wrap ? at<float>(ws, p.off_ycell) : nullptr;
   h.qc = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc);
-  h.qc16 = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc16);
+  h.qc16 = at<int32_t>(ws, p.off_qc16);  // int16 offsets, or wrapped 16-bit coordinates
   h.cell_of = at<int32_t>(ws, p.off_cell_of);
   h.rank = at<int32_t>(ws, p.off_rank);
   h.cell_count = at<int32_t>(ws, p.off_cell_count);
@@ -247,9 +257,8 @@ static int occ_bucket(const Plan& p) {
 static int default_blk(const Plan& p) {
   const char* e = std::getenv("HDMD_BUILD_BLK");
   if (e) return std::atoi(e);
-  if (!p.wrap) return 1;
-  double occ = (double)p.n / (double)p.ncells;
-  return occ > 160 ? 256 : (occ > 80 ? 128 : 64);
+  (void)p;
+  return 1;
 }
 
 static int lookup_blk(const Plan& p, bool* known) {
@@ -358,7 +367,6 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
     float best = 1e30f;
     int best_blk = blk;
     for (int cand : {1, 2, 4, 64, 128, 256}) {
-      if (cand < 64 && p.wrap) continue;
       K->build(p.wrap, cand, a, p.ncells, st);  // warm-up
       HIPCHK(hipEventRecord(e0, st));
       K->build(p.wrap, cand, a, p.ncells, st);
@@ -879,7 +887,8 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
     atom_base += B->n_atom[d];
     cell_base += B->n_cell[d];
     double occ = occ_n ? (double)occ_tot / occ_n : 1.0;
-    B->blk[d] = occ > 160 ? 256 : (occ > 80 ? 128 : 64);
+    (void)occ;
+    B->blk[d] = 1;  // candidate-lane build for the n_cell <= 2 systems too
   }
   for (int s = 0; s < B->max_slots; s++) {
     const SlotInfo& S = B->slots[s];

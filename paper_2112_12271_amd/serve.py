@@ -55,6 +55,7 @@ class Result:
     status: int
     retries: int
     x: np.ndarray | None = None
+    builds: int = 0
 
     @property
     def latency(self) -> float:
@@ -83,7 +84,7 @@ class Server:
     executor must provide: workspace_bytes(req, width) -> int;
     add(slot, req, width) (allocates the request's device memory);
     run(iterations); poll() -> (state[], iters[]);
-    take(slot) -> (x, iterations, fmax, energy, status); release(slot).
+    take(slot) -> (x, iterations, fmax, energy, status, builds); release(slot).
     """
 
     STATE_EMPTY, STATE_RUNNING, STATE_DONE = 0, 1, 2
@@ -154,7 +155,7 @@ class Server:
                 if state[slot] != self.STATE_DONE:
                     continue
                 req, adm, nbytes, width, retries = self.slot_req.pop(slot)
-                x, iters, fmax, energy, status = self.ex.take(slot)
+                x, iters, fmax, energy, status, builds = self.ex.take(slot)
                 self.ex.release(slot)
                 self.in_use -= nbytes
                 if status == self.ERR_OVERFLOW:
@@ -164,7 +165,7 @@ class Server:
                     continue
                 results.append(Result(req.rid, req.kind, req.d, req.n, req.arrival, adm, now,
                                       iters, fmax, energy, status, retries,
-                                      x if self.keep else None))
+                                      x if self.keep else None, builds))
         return results
 
 
@@ -224,8 +225,8 @@ class GpuExecutor:
         try:
             pos, _, res = self.batch.hdmd_batch_take(slot)
         except H.HdmdError as e:
-            return None, 0, float("nan"), float("nan"), e.status
-        return pos.cpu().numpy(), res.iterations, res.fmax, res.energy, res.status
+            return None, 0, float("nan"), float("nan"), e.status, 0
+        return pos.cpu().numpy(), res.iterations, res.fmax, res.energy, res.status, res.builds
 
     def release(self, slot: int):
         self.mem.pop(slot, None)

@@ -138,15 +138,17 @@ def test_full_size_sampled_rows(orc, name):
     assert np.array_equal(np.sort(fwd), np.sort(bwd))
 
 
-@pytest.mark.parametrize("d,nc,per_cell", [(3, 3, 150), (4, 3, 140), (6, 3, 10), (8, 3, 1)])
+@pytest.mark.parametrize("d,nc,per_cell", [(3, 3, 150), (4, 3, 140), (6, 3, 10), (8, 3, 1),
+                                           (3, 2, 200), (6, 2, 40), (8, 2, 4), (4, 1, 300)])
 def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
     """Each list-build variant (candidate-lane with 1, 2 or 4 waves per subcell,
     home-lane with 64/128/256 lanes), forced in turn, gives the definition's
-    list; crowded subcells (more than 64 and 128 atoms) take several home passes."""
+    list; crowded subcells (more than 64 and 128 atoms) take several home
+    passes; n_cell = 2 and 1 take the wrapped-coordinate prefilter."""
     import os
     c, s = C6, 0.3
     rlmax = c * 1.4 + s
-    L = nc * rlmax * 1.02
+    L = nc * rlmax * 1.02 if nc > 1 else max(2.0 * c * 1.4 * 1.001, 1.02 * rlmax)
     n = per_cell * nc ** d
     x, sig = partnered(d, n, L, 77 * d + nc, rlmax)
     ref = orc.nlist_brute(x, sig, L, c, s)

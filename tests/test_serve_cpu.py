@@ -41,10 +41,10 @@ class FakeExecutor:
         req = s["req"]
         if req.rid in self.overflow_once:
             self.overflow_once.discard(req.rid)
-            return None, 0, 0.0, 0.0, -4
+            return None, 0, 0.0, 0.0, -4, 0
         x, res = self.orc.fire(req.x, req.sig, req.box_l, self.orc.HARMONIC, 1.0, 0.25, 1.0,
                                self.orc.fire_params(ftol=1e-8, maxiter=20000))
-        return x, res.iters, res.fmax, res.energy, 0
+        return x, res.iters, res.fmax, res.energy, 0, res.builds
 
     def release(self, slot):
         del self.slots[slot]
