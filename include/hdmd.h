@@ -57,9 +57,10 @@ typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
  *   precision  HDMD_FP64: everything in FP64.  HDMD_MIXED: neighbour
  *              positions are gathered as 32-bit fixed-point coordinates whose
  *              integer difference is the exact minimum-image displacement;
- *              the pair distance and force coefficient are FP64, the force
- *              vector and the velocities FP32; positions, energy sums and
- *              FIRE's reductions FP64.  Verlet lists are FP64-exact in both.
+ *              pair distances, coefficients and the force sums are FP64, the
+ *              stored forces and the velocities FP32; positions, energy sums
+ *              and FIRE's reductions FP64.  Verlet lists are FP64-exact in
+ *              both.
  *   sigma_max  largest diameter present; it sizes the subcells (eq. setnc).
  *   max_neighbors  Verlet row capacity W of the workspace. */
 typedef struct {

@@ -951,8 +951,12 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
   const double* __restrict__ xb = s->x[s->xcur];
   const int32_t* __restrict__ qb = MIX ? s->q[s->xcur] : nullptr;
   const double fxinv = s->fxinv;
+  // forces are summed in FP64 in both forms (the precision form stores them
+  // as FP32): summing ~10^2-10^3 terms of mixed sign in FP32 would lose more
+  // than 1e-5 of F_rms at high overlap
+  double Fs[D];
 #pragma unroll
-  for (int k = 0; k < D; k++) F[k] = FT(0);
+  for (int k = 0; k < D; k++) Fs[k] = 0.0;
   e = 0.0;
   // row entries are read unconditionally from a clamped (in-bounds) slot and
   // masked afterwards, so the loads issue without branches and the wait for
@@ -994,13 +998,13 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
           double fc, uu;
           pair_f64(pot, eps, r2, sij, fc, uu);
 #pragma unroll
-          for (int k = 0; k < D; k++) F[k] -= FT(fc * dx[k]);
+          for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
         }
       }
     } else {
-      // mixed: exact integer displacements; distance and pair coefficient in
-      // FP64, force vector accumulated in FP32
+      // mixed: exact integer displacements; distance, pair coefficient and
+      // force sum in FP64 (stored as FP32 by the caller)
       int uj[U][D];
       double sj[U];
 #pragma unroll
@@ -1021,7 +1025,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
           double fc, uu;
           pair_f64(pot, eps, r2, sij, fc, uu);
 #pragma unroll
-          for (int k = 0; k < D; k++) F[k] -= FT(fc * dx[k]);
+          for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
         }
       }
@@ -1030,9 +1034,11 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
   for (int o = 1; o < LPA; o <<= 1) {
 #pragma unroll
-    for (int k = 0; k < D; k++) F[k] += (FT)__shfl_xor((FT)F[k], o, 64);
+    for (int k = 0; k < D; k++) Fs[k] += __shfl_xor(Fs[k], o, 64);
     e += __shfl_xor(e, o, 64);
   }
+#pragma unroll
+  for (int k = 0; k < D; k++) F[k] = FT(Fs[k]);
 }
 
 template <int D, bool MIX>

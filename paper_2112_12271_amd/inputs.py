@@ -126,7 +126,11 @@ C1 = MDConfig("c1_d3_n1000", 3, 1000, 1.0, 1.4, None, 0.8, 0.005, 0.3, 1000, see
 C2 = MDConfig("c2_d4_n65536", 4, 65536, 1.0, 1.0, 0.4, None, 0.005, 0.3, 10000, seed=2000)
 C3 = MDConfig("c3_d6_n262144", 6, 262144, 1.0, 1.2, 0.42, None, 0.002, 0.25, 10000, seed=3000)
 C5 = MDConfig("c5_d8_n131072", 8, 131072, 1.0, 1.0, 0.3, None, 0.002, 0.25, 5000, seed=5000)
-CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c5": C5}
+# C5 geometry at a liquid packing fraction: same d, N, n_cell = 2, WCA, dt and T,
+# for the NVE part of the precision stress (at 0.3 the relaxed state keeps
+# ~100 overlaps per atom and WCA dynamics at dt = 0.002 diverge)
+C5_MD = MDConfig("c5md_d8_n131072", 8, 131072, 1.0, 1.0, 0.05, None, 0.002, 0.25, 5000, seed=5000)
+CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c5": C5, "c5md": C5_MD}
 
 
 @dataclasses.dataclass
