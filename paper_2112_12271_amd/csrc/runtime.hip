@@ -887,8 +887,14 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
     atom_base += B->n_atom[d];
     cell_base += B->n_cell[d];
     double occ = occ_n ? (double)occ_tot / occ_n : 1.0;
+    // candidate-lane build for the n_cell <= 2 systems too, four waves per
+    // subcell (few, crowded subcells per system; HDMD_WRAP_G overrides)
+    {
+      const char* e = std::getenv("HDMD_WRAP_G");
+      const int g = e ? std::atoi(e) : 4;
+      B->blk[d] = (g == 1 || g == 2 || g == 4) ? g : 4;
+    }
     (void)occ;
-    B->blk[d] = 1;  // candidate-lane build for the n_cell <= 2 systems too
   }
   for (int s = 0; s < B->max_slots; s++) {
     const SlotInfo& S = B->slots[s];
