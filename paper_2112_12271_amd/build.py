@@ -41,7 +41,8 @@ def _compile(src: str, obj: str, extra: list[str]) -> str:
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = [(os.path.join(CSRC, "common.hip"), os.path.join(BUILD, "common.o"), []),
-             (os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), [])]
+             (os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []),
+             (os.path.join(CSRC, "kern_all.hip"), os.path.join(BUILD, "kern_all.o"), [])]
     for d in DIMS:
         units.append((os.path.join(CSRC, "kern_dim.hip"), os.path.join(BUILD, "kern_d%d.o" % d),
                       ["-DHDMD_DIM=%d" % d]))

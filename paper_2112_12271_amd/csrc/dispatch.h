@@ -22,6 +22,12 @@ struct DKernels {
 
 const DKernels* dkernels(int d);
 
+// per-tile kernels over the tiles of every dimension class of a batch
+// (KArgs.cls = 0; kern_all.hip)
+void launch_bin_all(const KArgs& a, int grid, hipStream_t st);
+void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st);
+void launch_cellsort_all(const KArgs& a, int grid, hipStream_t st);
+
 // dimension-independent kernels (common.hip)
 void launch_setdesc(SysDev* dst, const SysDev& val, hipStream_t st);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);

@@ -115,6 +115,19 @@ __device__ inline int flat_cell(const SysDev* s, const double (&x)[D]) {
   return I;
 }
 
+// One atom tile of a system that rebuilds: subcell index and arrival rank.
+template <int D>
+__device__ inline void bin_tile(SysDev* s, int tile) {
+  if (tile == 0 && threadIdx.x == 0) s->max_cell = 0;
+  int i = tile * kTile + threadIdx.x;
+  if (i >= s->n) return;
+  double x[D];
+  load_x<D>(s->x[s->xcur ^ 1], i, x);
+  int c = flat_cell<D>(s, x);
+  s->cell_of[i] = c;
+  s->rank[i] = atomicAdd(&s->cell_count[c], 1);
+}
+
 template <int D>
 __global__ __launch_bounds__(kTile) void k_bin(KArgs a) {
   for (int t = blockIdx.x;; t += gridDim.x) {
@@ -122,14 +135,7 @@ __global__ __launch_bounds__(kTile) void k_bin(KArgs a) {
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s) || !need_rebuild(s)) continue;
-    if (tile == 0 && threadIdx.x == 0) s->max_cell = 0;
-    int i = tile * kTile + threadIdx.x;
-    if (i >= s->n) continue;
-    double x[D];
-    load_x<D>(s->x[s->xcur ^ 1], i, x);
-    int c = flat_cell<D>(s, x);
-    s->cell_of[i] = c;
-    s->rank[i] = atomicAdd(&s->cell_count[c], 1);
+    bin_tile<D>(s, tile);
   }
 }
 
@@ -175,10 +181,114 @@ __device__ inline int quant8(double y, double qinv) {
   return q < -127 ? -127 : (q > 127 ? 127 : q);
 }
 
+// One subcell of a system that rebuilds (a block of 256 threads): its atoms
+// sorted by caller id, then every per-atom array permuted into subcell order.
 template <int D, typename VT>
-__global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
+__device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
   constexpr int DY = Dims<D>::DY, QW = Dims<D>::QW;
   constexpr bool MIX = sizeof(VT) == 4;
+  const int s0 = cell_start(s, c), cnt = cell_start(s, c + 1) - s0;
+  if (threadIdx.x == 0) {
+    s->cell_count[c] = 0;  // ready for the next build
+    s->cell_flat[c] = s0;
+    if (c == s->ncells - 1) s->cell_flat[s->ncells] = s->n;
+  }
+  if (cnt == 0) return;
+  int* keys;
+  int* vals;
+  if (cnt <= kSortCap) {
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+      sk[q] = s->key[s0 + q];
+      sv[q] = s->src[s0 + q];
+    }
+    keys = sk;
+    vals = sv;
+  } else {
+    keys = s->key + s0;
+    vals = s->src + s0;
+  }
+  __syncthreads();
+  bitonic_sort<true>(keys, vals, cnt);
+  // subcell centre
+  const int nc = s->ncell;
+  double cen[D];
+  {
+    int u = c;
+#pragma unroll
+    for (int k = D - 1; k >= 0; k--) {
+      cen[k] = ((double)(u % nc) + 0.5) * s->lsc - s->hL;
+      u /= nc;
+    }
+  }
+  const int cur = s->xcur, pc = s->pcur, pn = pc ^ 1, npad = s->npad;
+  const bool wrap = s->wrap != 0;
+  const VT* vin = reinterpret_cast<const VT*>(s->v[pc]);
+  VT* vout = reinterpret_cast<VT*>(s->v[pn]);
+  for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+    const int src = vals[q], dst = s0 + q;
+    double x[D], sg;
+    load_rec<D>(s->x[cur ^ 1], src, x, sg);
+    store_rec<D>(s->x[cur], dst, x, sg);
+    if (MIX) store_q<D>(s->q[cur], dst, x, sg, s->hL, s->fxscale);
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+      s->xref[(size_t)k * npad + dst] = x[k];
+      vout[(size_t)k * npad + dst] = vin[(size_t)k * npad + src];
+    }
+    if (wrap) {
+      float y[DY];
+#pragma unroll
+      for (int k = 0; k < DY; k++) y[k] = k < D ? (float)(x[k] - cen[k]) : 0.0f;
+      float4* yp = reinterpret_cast<float4*>(s->ycell + (size_t)dst * DY);
+#pragma unroll
+      for (int k = 0; k < DY / 4; k++) yp[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
+      // 16-bit coordinates u = (x + L/2) 2^16 / L, wrapping at L: the 16-bit
+      // difference u_j - u_i is the minimum-image displacement in L/2^16
+      // units (candidate-lane build with n_cell <= 2)
+      const double ws16 = 65536.0 / s->L;
+      int p16[8];
+#pragma unroll
+      for (int k = 0; k < 8; k++) p16[k] = 0;
+#pragma unroll
+      for (int k = 0; k < D; k++) {
+        const int u = (int)((long long)rint((x[k] + s->hL) * ws16) & 0xffff);
+        p16[k / 2] |= u << (16 * (k % 2));
+      }
+      int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
+      pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
+      pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
+    } else {
+      int w[QW];
+#pragma unroll
+      for (int k = 0; k < QW; k++) w[k] = 0;
+#pragma unroll
+      for (int k = 0; k < D; k++)
+        w[k / 4] |= (quant8(x[k] - cen[k], s->qinv) & 0xff) << (8 * (k % 4));
+#pragma unroll
+      for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
+      // the same offsets as int16 pairs for the candidate-lane build
+      // and |q|^2 in the last word read by the home-atom loads
+      int p16[8], B = 0;
+#pragma unroll
+      for (int k = 0; k < 8; k++) p16[k] = 0;
+#pragma unroll
+      for (int k = 0; k < D; k++) {
+        const int qv = sext8(w[k / 4], k % 4);
+        p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
+        B += qv * qv;
+      }
+      p16[(D + 1) / 2 < 4 ? 3 : 7] = B;
+      int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
+      pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
+      if (D > 6) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
+    }
+    s->oid[pn][dst] = keys[q];
+  }
+  __syncthreads();
+}
+
+template <int D, typename VT>
+__global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
   __shared__ int sk[kSortCap];
   __shared__ int sv[kSortCap];
   for (int t = blockIdx.x;; t += gridDim.x) {
@@ -186,104 +296,7 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
     int c;
     if (!fetch_cell_tile(a, t, s, c)) break;
     if (!running(s) || !need_rebuild(s)) continue;
-    const int s0 = cell_start(s, c), cnt = cell_start(s, c + 1) - s0;
-    if (threadIdx.x == 0) {
-      s->cell_count[c] = 0;  // ready for the next build
-      s->cell_flat[c] = s0;
-      if (c == s->ncells - 1) s->cell_flat[s->ncells] = s->n;
-    }
-    if (cnt == 0) continue;
-    int* keys;
-    int* vals;
-    if (cnt <= kSortCap) {
-      for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-        sk[q] = s->key[s0 + q];
-        sv[q] = s->src[s0 + q];
-      }
-      keys = sk;
-      vals = sv;
-    } else {
-      keys = s->key + s0;
-      vals = s->src + s0;
-    }
-    __syncthreads();
-    bitonic_sort<true>(keys, vals, cnt);
-    // subcell centre
-    const int nc = s->ncell;
-    double cen[D];
-    {
-      int u = c;
-#pragma unroll
-      for (int k = D - 1; k >= 0; k--) {
-        cen[k] = ((double)(u % nc) + 0.5) * s->lsc - s->hL;
-        u /= nc;
-      }
-    }
-    const int cur = s->xcur, pc = s->pcur, pn = pc ^ 1, npad = s->npad;
-    const bool wrap = s->wrap != 0;
-    const VT* vin = reinterpret_cast<const VT*>(s->v[pc]);
-    VT* vout = reinterpret_cast<VT*>(s->v[pn]);
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-      const int src = vals[q], dst = s0 + q;
-      double x[D], sg;
-      load_rec<D>(s->x[cur ^ 1], src, x, sg);
-      store_rec<D>(s->x[cur], dst, x, sg);
-      if (MIX) store_q<D>(s->q[cur], dst, x, sg, s->hL, s->fxscale);
-#pragma unroll
-      for (int k = 0; k < D; k++) {
-        s->xref[(size_t)k * npad + dst] = x[k];
-        vout[(size_t)k * npad + dst] = vin[(size_t)k * npad + src];
-      }
-      if (wrap) {
-        float y[DY];
-#pragma unroll
-        for (int k = 0; k < DY; k++) y[k] = k < D ? (float)(x[k] - cen[k]) : 0.0f;
-        float4* yp = reinterpret_cast<float4*>(s->ycell + (size_t)dst * DY);
-#pragma unroll
-        for (int k = 0; k < DY / 4; k++) yp[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
-        // 16-bit coordinates u = (x + L/2) 2^16 / L, wrapping at L: the 16-bit
-        // difference u_j - u_i is the minimum-image displacement in L/2^16
-        // units (candidate-lane build with n_cell <= 2)
-        const double ws16 = 65536.0 / s->L;
-        int p16[8];
-#pragma unroll
-        for (int k = 0; k < 8; k++) p16[k] = 0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-          const int u = (int)((long long)rint((x[k] + s->hL) * ws16) & 0xffff);
-          p16[k / 2] |= u << (16 * (k % 2));
-        }
-        int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
-        pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
-        pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
-      } else {
-        int w[QW];
-#pragma unroll
-        for (int k = 0; k < QW; k++) w[k] = 0;
-#pragma unroll
-        for (int k = 0; k < D; k++)
-          w[k / 4] |= (quant8(x[k] - cen[k], s->qinv) & 0xff) << (8 * (k % 4));
-#pragma unroll
-        for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
-        // the same offsets as int16 pairs for the candidate-lane build
-        // and |q|^2 in the last word read by the home-atom loads
-        int p16[8], B = 0;
-#pragma unroll
-        for (int k = 0; k < 8; k++) p16[k] = 0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-          const int qv = sext8(w[k / 4], k % 4);
-          p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
-          B += qv * qv;
-        }
-        p16[(D + 1) / 2 < 4 ? 3 : 7] = B;
-        int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
-        pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
-        if (D > 6) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
-      }
-      s->oid[pn][dst] = keys[q];
-    }
-    __syncthreads();
+    cellsort_tile<D, VT>(s, c, sk, sv);
   }
 }
 
@@ -1213,48 +1226,53 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
 //   on P <= 0: x -= dt/2 v, v = 0;  v += dt F;  v = (1-a) v + a |v|/|F| F;
 //   x += dt v (wrapped, into the other buffer); displacement for the trigger.
 template <int D, bool MIX>
-__global__ __launch_bounds__(kTile) void k_fire_update(KArgs a) {
+__device__ inline void fire_update_tile(SysDev* s, int tile) {
   typedef typename VType<MIX>::T VT;
+  const int i = tile * kTile + threadIdx.x;
+  const int n = s->n, npad = s->npad, pc = s->pcur, cur = s->xcur;
+  double disp2 = 0.0;
+  if (i < n) {
+    const double dt = s->c_dt, keep = s->c_keep, mix = s->c_mix;
+    const bool zero = s->c_zero != 0;
+    const double L = s->L, h = s->hL;
+    double x[D], sg;
+    load_rec<D>(s->x[cur], i, x, sg);
+    VT* v = reinterpret_cast<VT*>(s->v[pc]);
+    const VT* f = reinterpret_cast<const VT*>(s->f);
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+      double vk = (double)v[(size_t)k * npad + i];
+      const double fk = (double)f[(size_t)k * npad + i];
+      if (zero) {
+        x[k] = x[k] - 0.5 * dt * vk;
+        vk = 0.0;
+      }
+      vk = vk + dt * fk;
+      vk = keep * vk + mix * fk;
+      const VT vs = VT(vk);
+      v[(size_t)k * npad + i] = vs;
+      x[k] = wrap1(x[k] + dt * (double)vs, L, h);
+      double dx = min_image(x[k] - s->xref[(size_t)k * npad + i], L, h);
+      r2 = __builtin_fma(dx, dx, r2);
+    }
+    store_rec<D>(s->x[cur ^ 1], i, x, sg);
+    if (MIX) store_q<D>(s->q[cur ^ 1], i, x, sg, h, s->fxscale);
+    disp2 = r2;
+  }
+  const double dm = wave_max(disp2);
+  if ((threadIdx.x & (kWave - 1)) == 0 && dm > 0.0)
+    atomicMax(&s->maxdisp2, (unsigned long long)__double_as_longlong(dm));
+}
+
+template <int D, bool MIX>
+__global__ __launch_bounds__(kTile) void k_fire_update(KArgs a) {
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s) || s->mode != MODE_FIRE) continue;
-    const int i = tile * kTile + threadIdx.x;
-    const int n = s->n, npad = s->npad, pc = s->pcur, cur = s->xcur;
-    double disp2 = 0.0;
-    if (i < n) {
-      const double dt = s->c_dt, keep = s->c_keep, mix = s->c_mix;
-      const bool zero = s->c_zero != 0;
-      const double L = s->L, h = s->hL;
-      double x[D], sg;
-      load_rec<D>(s->x[cur], i, x, sg);
-      VT* v = reinterpret_cast<VT*>(s->v[pc]);
-      const VT* f = reinterpret_cast<const VT*>(s->f);
-      double r2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; k++) {
-        double vk = (double)v[(size_t)k * npad + i];
-        const double fk = (double)f[(size_t)k * npad + i];
-        if (zero) {
-          x[k] = x[k] - 0.5 * dt * vk;
-          vk = 0.0;
-        }
-        vk = vk + dt * fk;
-        vk = keep * vk + mix * fk;
-        const VT vs = VT(vk);
-        v[(size_t)k * npad + i] = vs;
-        x[k] = wrap1(x[k] + dt * (double)vs, L, h);
-        double dx = min_image(x[k] - s->xref[(size_t)k * npad + i], L, h);
-        r2 = __builtin_fma(dx, dx, r2);
-      }
-      store_rec<D>(s->x[cur ^ 1], i, x, sg);
-      if (MIX) store_q<D>(s->q[cur ^ 1], i, x, sg, h, s->fxscale);
-      disp2 = r2;
-    }
-    const double dm = wave_max(disp2);
-    if ((threadIdx.x & (kWave - 1)) == 0 && dm > 0.0)
-      atomicMax(&s->maxdisp2, (unsigned long long)__double_as_longlong(dm));
+    fire_update_tile<D, MIX>(s, tile);
   }
 }
 

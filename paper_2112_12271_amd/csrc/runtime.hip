@@ -801,6 +801,7 @@ struct HostBatch {
   // current composition
   int n_atom[kMaxD + 1] = {0}, n_cell[kMaxD + 1] = {0}, n_nowrap[kMaxD + 1] = {0};
   int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};  // wrap-variant build tile per d
+  int n_atom_all = 0, n_cell_all = 0;
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
        has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
@@ -917,6 +918,13 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
     t.atom_tiles[d] = B->d_atom + a_off[d];
     t.cell_tiles[d] = B->d_cell + c_off[d];
   }
+  t.n_atom[0] = (int32_t)atom_base;  // class 0: every class
+  t.n_cell[0] = (int32_t)cell_base;
+  t.n_cell_nowrap[0] = (int32_t)cell_base;
+  t.atom_tiles[0] = B->d_atom;
+  t.cell_tiles[0] = B->d_cell;
+  B->n_atom_all = (int)atom_base;
+  B->n_cell_all = (int)cell_base;
   t.n_chunk = B->n_chunk;
   t.n_sys = B->n_sys;
   t.chunk_tiles = B->d_chunk;
@@ -952,23 +960,20 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   const int gsys = grids[0], gchunk = grids[1];
   auto ga = [&](int d) { return grids[2 + 3 * (d - kMinD)]; };
   auto gc = [&](int d) { return grids[3 + 3 * (d - kMinD)]; };
-  KArgs a0 = batch_args(B, 0);
+  KArgs a0 = batch_args(B, 0);  // class 0: the tiles of every class
+  const int ga_all = grids[grids.size() - 3], gc_all = grids[grids.size() - 2];
   if (B->has_fire) {
     launch_fire_ctrl(a0, gsys, st);
-    for (int d = kMinD; d <= kMaxD; d++)
-      if (B->n_atom[d]) dkernels(d)->fire_update(B->mix[d], batch_args(B, d), ga(d), st);
+    launch_fire_update_all(a0, ga_all, st);
   }
   if (B->has_md)
     for (int d = kMinD; d <= kMaxD; d++)
       if (B->n_atom[d]) dkernels(d)->step(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), st);
-  for (int d = kMinD; d <= kMaxD; d++)
-    if (B->n_atom[d]) dkernels(d)->bin(batch_args(B, d), ga(d), st);
+  launch_bin_all(a0, ga_all, st);
   launch_scan1(a0, gchunk, st);
   launch_scan2(a0, gsys, st);
-  for (int d = kMinD; d <= kMaxD; d++)
-    if (B->n_atom[d]) launch_scatter(batch_args(B, d), ga(d), st);
-  for (int d = kMinD; d <= kMaxD; d++)
-    if (B->n_cell[d]) dkernels(d)->cellsort(B->mix[d], batch_args(B, d), gc(d), st);
+  launch_scatter(a0, ga_all, st);
+  launch_cellsort_all(a0, gc_all, st);
   for (int d = kMinD; d <= kMaxD; d++) {
     if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
     if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
@@ -1107,6 +1112,8 @@ int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
   }
   grids.push_back(B->has_fire ? 1 : 0);
   grids.push_back(B->has_md ? 1 : 0);
+  grids.push_back(pow2_grid(B->n_atom_all, 4096));  // all-class launches
+  grids.push_back(pow2_grid(B->n_cell_all, 8192));
   grids.push_back(iterations);
   if (!graphs_enabled()) {
     for (int k = 0; k < iterations; k++) enqueue_batch_iter(B, grids, st);
