@@ -1,6 +1,6 @@
-// kern_all.hip -- light per-tile kernels of a batch launched once over the
-// tiles of every dimension class: each tile's system selects the
-// dimension-templated body (update, binning, subcell sort).  One launch per
+// kern_all.hip -- per-tile kernels of a batch launched once over the tiles
+// of every dimension class: each tile's system selects the
+// dimension-templated body (update, binning, subcell sort, forces).  One launch per
 // kernel instead of one per class keeps the launch count of a batch
 // iteration independent of how many dimensions it mixes.
 #include "kernels.h"
@@ -67,7 +67,31 @@ __global__ __launch_bounds__(256) void k_cellsort_all(KArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
+  __shared__ double sh[kPart];
+  for (int t = blockIdx.x;; t += gridDim.x) {
+    SysDev* s;
+    int tile;
+    if (!fetch_atom_tile(a, t, s, tile)) break;
+    if (!running(s)) continue;
+    if (fire && s->mode != MODE_FIRE) continue;
+    const bool mix = s->precision != 0;
+    switch (s->d) {
+#define HDMD_CASE(DD)                                           \
+  case DD:                                                      \
+    if (mix) force_tile<DD, true, 1>(s, tile, fire, sh);        \
+    else force_tile<DD, false, 1>(s, tile, fire, sh);           \
+    break;
+      HDMD_EACH_D(HDMD_CASE)
+#undef HDMD_CASE
+    }
+  }
+}
+
 void launch_bin_all(const KArgs& a, int grid, hipStream_t st) { k_bin_all<<<grid, kTile, 0, st>>>(a); }
+void launch_force_all(const KArgs& a, int grid, int fire, hipStream_t st) {
+  k_force_all<<<grid, kTile, 0, st>>>(a, fire);
+}
 void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st) {
   k_fire_update_all<<<grid, kTile, 0, st>>>(a);
 }

@@ -1106,50 +1106,57 @@ __device__ inline void tile_partials(double* dst, double (&vals)[kPart], double&
 
 // Forces (stored in s->f) with the tile's energy and, for FIRE, the power
 // P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
+// One atom tile's forces (stored in s->f) with the tile's energy and, for
+// FIRE, the power P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
+template <int D, bool MIX, int LPA>
+__device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
+  typedef typename VType<MIX>::T FT;
+  const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
+  const int i = tile * kTile + slot;
+  const int n = s->n, npad = s->npad, pc = s->pcur;
+  const bool vi = i < n;
+  const int ii = vi ? i : 0;
+  Own<D, MIX> me;
+  load_own<D, MIX>(s, ii, me);
+  FT F[D];
+  double e;
+  force_part<D, MIX, LPA, FT>(s, ii, sub, me, F, e);
+  double vals[kPart], mx = 0.0;
+#pragma unroll
+  for (int p = 0; p < kPart; p++) vals[p] = 0.0;
+  if (vi && sub == 0) {
+    FT* fo = reinterpret_cast<FT*>(s->f);
+    const FT* v = reinterpret_cast<const FT*>(s->v[pc]);
+    double fv = 0.0, ff = 0.0, vv = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+      fo[(size_t)k * npad + i] = F[k];
+      if (fire) {
+        const double fk = (double)F[k], vk = (double)v[(size_t)k * npad + i];
+        fv += fk * vk;
+        ff += fk * fk;
+        vv += vk * vk;
+      }
+    }
+    vals[P_PE] = e;
+    vals[P_FV] = fv;
+    vals[P_FF] = ff;
+    vals[P_VV] = vv;
+    mx = ff;
+  }
+  tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh);
+}
+
 template <int D, bool MIX, int LPA>
 __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
-  typedef typename VType<MIX>::T FT;
   __shared__ double sh[LPA * kPart];
-  const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s)) continue;
     if (fire && s->mode != MODE_FIRE) continue;
-    const int i = tile * kTile + slot;
-    const int n = s->n, npad = s->npad, pc = s->pcur;
-    const bool vi = i < n;
-    const int ii = vi ? i : 0;
-    Own<D, MIX> me;
-    load_own<D, MIX>(s, ii, me);
-    FT F[D];
-    double e;
-    force_part<D, MIX, LPA, FT>(s, ii, sub, me, F, e);
-    double vals[kPart], mx = 0.0;
-#pragma unroll
-    for (int p = 0; p < kPart; p++) vals[p] = 0.0;
-    if (vi && sub == 0) {
-      FT* fo = reinterpret_cast<FT*>(s->f);
-      const FT* v = reinterpret_cast<const FT*>(s->v[pc]);
-      double fv = 0.0, ff = 0.0, vv = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; k++) {
-        fo[(size_t)k * npad + i] = F[k];
-        if (fire) {
-          const double fk = (double)F[k], vk = (double)v[(size_t)k * npad + i];
-          fv += fk * vk;
-          ff += fk * fk;
-          vv += vk * vk;
-        }
-      }
-      vals[P_PE] = e;
-      vals[P_FV] = fv;
-      vals[P_FF] = ff;
-      vals[P_VV] = vv;
-      mx = ff;
-    }
-    tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh);
+    force_tile<D, MIX, LPA>(s, tile, fire, sh);
   }
 }
 

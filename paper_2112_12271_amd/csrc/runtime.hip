@@ -979,9 +979,14 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
     if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
   }
   launch_finalize(a0, gsys, st);
-  if (B->has_fire)
-    for (int d = kMinD; d <= kMaxD; d++)
-      if (B->n_atom[d]) dkernels(d)->force(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), 1, st);
+  if (B->has_fire) {
+    if (!std::getenv("HDMD_LPA")) {
+      launch_force_all(a0, ga_all, 1, st);  // one lane per atom in every class
+    } else {
+      for (int d = kMinD; d <= kMaxD; d++)
+        if (B->n_atom[d]) dkernels(d)->force(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), 1, st);
+    }
+  }
 }
 
 }  // namespace hdmd
