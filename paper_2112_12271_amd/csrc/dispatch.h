@@ -28,6 +28,7 @@ void launch_bin_all(const KArgs& a, int grid, hipStream_t st);
 void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st);
 void launch_cellsort_all(const KArgs& a, int grid, hipStream_t st);
 void launch_force_all(const KArgs& a, int grid, int fire, hipStream_t st);
+void launch_build_all(const KArgs& a, int grid, hipStream_t st);
 
 // dimension-independent kernels (common.hip)
 void launch_setdesc(SysDev* dst, const SysDev& val, hipStream_t st);

@@ -111,8 +111,10 @@ struct SysDev {
 // Tile tables of a batch: one list per dimension class (index d).
 struct Table {
   int32_t max_slots, pad;
-  // index d: dimension class d; index 0: all classes (tiles of class d follow
-  // those of class d-1 in one array, so class 0 covers them all)
+  // index d: dimension class d; index 0: all classes (atom tiles of class d
+  // follow those of class d-1 in one array, so class 0 covers them all; the
+  // cell tiles of class 0 are an array of their own that lists the n_cell >= 3
+  // subcells of every class before the wrap ones)
   int32_t n_atom[kMaxD + 1];
   int32_t n_cell[kMaxD + 1];
   int32_t n_cell_nowrap[kMaxD + 1];  // cell tiles of systems with n_cell >= 3 come first

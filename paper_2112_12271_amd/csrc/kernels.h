@@ -586,8 +586,11 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// One home subcell of a system that rebuilds, split over G waves: gw (< G)
+// selects this wave's share of the home atoms; msk/cand are the wave's LDS
+// arrays.
 template <int D, int G, bool WR>
-__global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
+__device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long long* msk, int* cand) {
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
   constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
   constexpr int BW = RW - 1;             // word of B = |q|^2
@@ -597,13 +600,300 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
   typedef typename std::conditional<RW == 4, cv4i, cv8i>::type CRec;
   typedef __attribute__((address_space(4))) const int cint;
   typedef short short2v __attribute__((ext_vector_type(2)));
-  // per wave: survivor masks of up to 128 home atoms and the candidates of NB chunks
-  __shared__ unsigned long long msk_all[G][NB * 128];
-  __shared__ int cand_all[G][NB * 64];
   const int lane = threadIdx.x & 63;
+  // subcell starts come through the scalar cache (written by an earlier kernel)
+  cint* flat = (cint*)uniform_ptr(s->cell_flat);
+  const int c0h = flat[hc];
+  const int c1h = flat[hc + 1];
+  // this wave's share of the home atoms
+  const int per = (c1h - c0h + G - 1) / G;
+  const int h0 = c0h + gw * per;
+  const int h1 = min(c1h, h0 + per);
+  if (h0 >= h1) return;
+  const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
+  const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
+  const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
+  const int* __restrict__ qc16 = uniform_ptr(s->qc16);
+  HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
+  const double L = uniform_dbl(s->L), invL = 1.0 / L, hL = uniform_dbl(s->hL);
+  const double cut = uniform_dbl(s->cutoff), skin = uniform_dbl(s->skin);
+  int ci[D - 1], stride[D - 1];
+  int cl;
+  {
+    int u = hc, st = 1;
+    cl = u % nc;
+    u /= nc;
+    st = nc;
+#pragma unroll
+    for (int k = D - 2; k >= 0; k--) {
+      ci[k] = u % nc;
+      u /= nc;
+      stride[k] = st;
+      st *= nc;
+    }
+  }
+  // rows of linked subcells: radix 3 (offsets -1, 0, +1) or, for n_cell <= 2,
+  // radix n_cell (offsets 0, +1: the deduplicated stencil)
+  const int R = WR ? nc : 3;
+  int nrow = 1;
+#pragma unroll
+  for (int k = 0; k < D - 1; k++) nrow *= R;
+  const int lm = WR ? cl : (cl == 0 ? nc - 1 : cl - 1);
+  const int lp = cl == nc - 1 ? 0 : cl + 1;
+  // offsets of the last axis (-1, 0, +1 subcells) in their int16 half
+  constexpr int lsh = 16 * ((D - 1) % 2);
+  const int lastm = (int)((unsigned)(-kQScale & 0xffff) << lsh);
+  const int lastpp = (int)((unsigned)(kQScale & 0xffff) << lsh);
+  // base subcell index of a row of linked subcells (offset digits of `row`
+  // in base 3 over the first d-1 axes, last digit fastest)
+  auto row_base = [&](int row, int (&Dp)[HW], int (&og)[D - 1]) -> int {
+    int P = 0, r = row;
+#pragma unroll
+    for (int k = 0; k < HW; k++) Dp[k] = 0;
+#pragma unroll
+    for (int k = D - 2; k >= 0; k--) {
+      const int o = WR ? r % R : r % 3 - 1;
+      r /= R;
+      og[k] = o;
+      int c2 = ci[k] + o;
+      c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
+      P += c2 * stride[k];
+      Dp[k / 2] |= ((kQScale * o) & 0xffff) << (16 * (k % 2));
+    }
+    return P;
+  };
+  int rowmax = 0;
+  // home atoms in passes of up to 128: lane l holds atoms hb + l and hb + 64 + l
+  for (int hb = h0; hb < h1; hb += 128) {
+    const int hcnt = uniform_int(min(128, h1 - hb));
+    const bool two = hcnt > 64;
+    const int i0 = hb + lane, i1 = hb + 64 + lane;
+    const bool v0 = lane < hcnt, v1 = lane + 64 < hcnt;
+    const int ii0 = v0 ? i0 : hb, ii1 = v1 ? i1 : hb;
+    int qh0[D], qh1[D];
+    auto own_q = [&](int ii, int (&qh)[D]) {
+      const v4i w0 = *reinterpret_cast<const v4i*>(qc16 + (size_t)ii * 8);
+      int w[5] = {w0.x, w0.y, w0.z, w0.w, 0};
+      if (HW > 4) w[4] = qc16[(size_t)ii * 8 + 4];
+#pragma unroll
+      for (int k = 0; k < D; k++) {
+        const int word = w[k / 2];
+        if (WR) {
+          // gap to the other subcell along axis k (n_cell = 2: it touches both
+          // faces), one unit short: L_sc/2 - |u - centre| - 1 in 2^16/L units
+          const int u = (k % 2) ? ((word >> 16) & 0xffff) : (word & 0xffff);
+          const int cc = (k < D - 1 ? ci[k < D - 1 ? k : 0] : cl) * 32768 + 16384;
+          const int y = (int)(short)((u - cc) & 0xffff);
+          qh[k] = max(16384 - abs(y) - 1, 0);
+        } else {
+          qh[k] = (k % 2) ? (word >> 16) : (int)(short)(word & 0xffff);
+        }
+      }
+    };
+    own_q(ii0, qh0);
+    own_q(ii1, qh1);
+    int len0 = 0, len1 = 0, nb = 0;
+
+    // exact test of one home atom's survivors, in chunk and lane order.
+    // The nearest image is taken with rint: with n_cell >= 3 the list radius
+    // is at most L/3, so every pair it can admit has all |dx_k| clear of
+    // L/2, where rint and the definition's shift give the same value bit
+    // for bit; pairs with some |dx_k| near L/2 are beyond the radius either
+    // way.
+    auto exact_one = [&](int set, int ii, int i, int& len) {
+      double xi[D], si;  // own record, reloaded (cache hit) to keep registers free
+      load_rec<D>(xb, ii, xi, si);
+      for (int b = 0; b < nb; b++) {
+        unsigned long long m = msk[b * 128 + set * 64 + lane];
+        while (m) {
+          const int j = cand[b * 64 + __builtin_ctzll(m)];
+          m &= m - 1;
+          double xj[D], sj;
+          load_rec<D>(xb, j, xj, sj);
+          if (j != i) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+              const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
+                                   : near_image(xj[k] - xi[k], L, invL);
+              r2 = __builtin_fma(dx, dx, r2);
+              __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
+            }
+            if (r2 < list_r2(si, sj, cut, skin)) {
+              if (len < W) nl[(size_t)len * npad + i] = j;
+              len++;
+            }
+          }
+        }
+      }
+    };
+    auto exact_pass = [&]() {
+      wave_lds_sync();
+      exact_one(0, ii0, i0, len0);
+      if (two) exact_one(1, ii1, i1, len1);
+      wave_lds_sync();
+      nb = 0;
+    };
+
+    // ballots of the kept home atoms of one set against `nch` chunks, four
+    // home atoms per group of scalar loads (a short last group repeats its
+    // last atom); lane h of m[c] receives home atom h's ballot for chunk c
+    auto test_set = [&](unsigned long long km, int rb, int nch, const int (&cw)[CB][HW],
+                        const int (&tA)[CB], unsigned (&mlo)[CB], unsigned (&mhi)[CB]) {
+      while (km) {
+        int hh[4];
+        hh[0] = __builtin_ctzll(km);
+        km &= km - 1;
+#pragma unroll
+        for (int u = 1; u < 4; u++) {
+          hh[u] = km ? __builtin_ctzll(km) : hh[u - 1];
+          km &= km - 1;
+        }
+        Rec r[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) r[u] = *(CRec*)(qc16 + (size_t)(rb + hh[u]) * 8);
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          if (c >= nch) break;
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            unsigned long long m;
+            if (WR) {
+              // |u_j - u_i|^2 over 16-bit wrapped differences (saturating: far
+              // pairs clamp at INT_MAX) against the lane's threshold
+              int acc = 0;
+#pragma unroll
+              for (int k = 0; k < HW; k++) {
+                const short2v dq = __builtin_bit_cast(short2v, cw[c][k]) -
+                                   __builtin_bit_cast(short2v, (int)r[u][k]);
+                acc = __builtin_amdgcn_sdot2(dq, dq, acc, true);
+              }
+              m = __ballot(acc < tA[c]);
+            } else {
+              int acc = tA[c];
+#pragma unroll
+              for (int k = 0; k < HW; k++)
+                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
+                                             __builtin_bit_cast(short2v, cw[c][k]), acc, false);
+              m = __ballot(acc > r[u][BW]);
+            }
+            mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo[c]);
+            mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi[c]);
+          }
+        }
+      }
+    };
+
+    for (int row = 0; row < nrow; row++) {
+      int Dp[HW], og[D - 1];
+      const int P = row_base(row, Dp, og);
+      // home atoms that can reach this row: gap to the neighbouring faces
+      // along the first d-1 axes, one quantisation unit short per axis
+      unsigned long long keep0, keep1;
+      {
+        int S0 = 0, S1 = 0;
+#pragma unroll
+        for (int k = 0; k < D - 1; k++) {
+          const int o = og[k];
+          int g0, g1;
+          if (WR) {
+            g0 = o ? qh0[k] : 0;
+            g1 = o ? qh1[k] : 0;
+          } else {
+            g0 = (kQScale / 2) - o * qh0[k] - 1;
+            g1 = (kQScale / 2) - o * qh1[k] - 1;
+            g0 = (o == 0 || g0 < 0) ? 0 : g0;
+            g1 = (o == 0 || g1 < 0) ? 0 : g1;
+          }
+          S0 += g0 * g0;
+          S1 += g1 * g1;
+        }
+        keep0 = __ballot(v0 && S0 < tcull);
+        keep1 = __ballot(v1 && S1 < tcull);
+      }
+      if ((keep0 | keep1) == 0) continue;
+      // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
+      const int st0 = flat[P + lm];
+      const int n0 = flat[P + lm + 1] - st0;
+      const int c1 = WR ? lp : cl;
+      const int st1 = (WR && R < 2) ? 0 : flat[P + c1];
+      const int n1 = (WR && R < 2) ? 0 : flat[P + c1 + 1] - st1;
+      const int st2 = WR ? 0 : flat[P + lp];
+      const int n2 = WR ? 0 : flat[P + lp + 1] - st2;
+      const int T = n0 + n1 + n2;
+      for (int k0 = 0; k0 < T; k0 += CB * 64) {
+        const int nch = min(CB, (T - k0 + 63) / 64);
+        if (nb + CB > NB) exact_pass();
+        // candidates of up to CB chunks: records (an in-range atom for the
+        // empty lanes) shifted by the subcell offset as packed int16 adds
+        int cw[CB][HW], tA[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          if (c >= nch) continue;
+          const int tt = k0 + c * 64 + lane;
+          const bool valid = c < nch && tt < T;
+          const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
+          const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
+          const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
+          const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
+          if (WR) {
+#pragma unroll
+            for (int k = 0; k < HW; k++) cw[c][k] = src[k];
+            tA[c] = valid ? tq : -1;  // the lane's threshold; none for an empty lane
+          } else {
+            int A = 0;
+#pragma unroll
+            for (int k = 0; k < HW; k++) {
+              const short2v q2 = __builtin_bit_cast(short2v, src[k]);
+              const short2v o2 =
+                  __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
+              const short2v r2 = q2 + o2;
+              A = __builtin_amdgcn_sdot2(r2, r2, A, false);
+              cw[c][k] = __builtin_bit_cast(int, r2 + r2);
+            }
+            tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
+          }
+          cand[(nb + c) * 64 + lane] = valid ? j : -1;
+        }
+        // (tq - A_j) + q_i.(2 q'_j) > B_i  <=>  |q'_j - q_i|^2 < tq
+        unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
+        test_set(keep0, hb, nch, cw, tA, m0lo, m0hi);
+        test_set(keep1, hb + 64, nch, cw, tA, m1lo, m1hi);
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          if (c < nch) {
+            msk[(nb + c) * 128 + lane] = ((unsigned long long)m0hi[c] << 32) | m0lo[c];
+            msk[(nb + c) * 128 + 64 + lane] = ((unsigned long long)m1hi[c] << 32) | m1lo[c];
+          }
+        }
+        nb += nch;
+      }
+    }
+    exact_pass();
+    if (v0) {
+      s->nlen[i0] = len0;
+      rowmax = max(rowmax, len0);
+    }
+    if (v1) {
+      s->nlen[i1] = len1;
+      rowmax = max(rowmax, len1);
+    }
+  }
+  rowmax = wave_max_i(rowmax);
+  if (lane == 0 && rowmax > 0) {
+    atomicMax(&s->max_row, rowmax);
+    if (rowmax > W) atomicOr(&s->err, ERR_OVERFLOW);
+  }
+}
+
+template <int D, int G, bool WR>
+__global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
+  // per wave: survivor masks of up to 128 home atoms and the candidates of 8 chunks
+  __shared__ unsigned long long msk_all[G][8 * 128];
+  __shared__ int cand_all[G][8 * 64];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned long long* msk = msk_all[wv];
-  int* cand = cand_all[wv];
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     int hc;
@@ -611,291 +901,7 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
     s = uniform_ptr(s);
     hc = uniform_int(hc);
     if (!running(s) || !need_rebuild(s)) continue;
-    // subcell starts come through the scalar cache (written by an earlier kernel)
-    cint* flat = (cint*)uniform_ptr(s->cell_flat);
-    const int c0h = flat[hc];
-    const int c1h = flat[hc + 1];
-    // this wave's share of the home atoms
-    const int per = (c1h - c0h + G - 1) / G;
-    const int h0 = c0h + wv * per;
-    const int h1 = min(c1h, h0 + per);
-    if (h0 >= h1) continue;
-    const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
-    const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
-    const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
-    const int* __restrict__ qc16 = uniform_ptr(s->qc16);
-    HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
-    const double L = uniform_dbl(s->L), invL = 1.0 / L, hL = uniform_dbl(s->hL);
-    const double cut = uniform_dbl(s->cutoff), skin = uniform_dbl(s->skin);
-    int ci[D - 1], stride[D - 1];
-    int cl;
-    {
-      int u = hc, st = 1;
-      cl = u % nc;
-      u /= nc;
-      st = nc;
-#pragma unroll
-      for (int k = D - 2; k >= 0; k--) {
-        ci[k] = u % nc;
-        u /= nc;
-        stride[k] = st;
-        st *= nc;
-      }
-    }
-    // rows of linked subcells: radix 3 (offsets -1, 0, +1) or, for n_cell <= 2,
-    // radix n_cell (offsets 0, +1: the deduplicated stencil)
-    const int R = WR ? nc : 3;
-    int nrow = 1;
-#pragma unroll
-    for (int k = 0; k < D - 1; k++) nrow *= R;
-    const int lm = WR ? cl : (cl == 0 ? nc - 1 : cl - 1);
-    const int lp = cl == nc - 1 ? 0 : cl + 1;
-    // offsets of the last axis (-1, 0, +1 subcells) in their int16 half
-    constexpr int lsh = 16 * ((D - 1) % 2);
-    const int lastm = (int)((unsigned)(-kQScale & 0xffff) << lsh);
-    const int lastpp = (int)((unsigned)(kQScale & 0xffff) << lsh);
-    // base subcell index of a row of linked subcells (offset digits of `row`
-    // in base 3 over the first d-1 axes, last digit fastest)
-    auto row_base = [&](int row, int (&Dp)[HW], int (&og)[D - 1]) -> int {
-      int P = 0, r = row;
-#pragma unroll
-      for (int k = 0; k < HW; k++) Dp[k] = 0;
-#pragma unroll
-      for (int k = D - 2; k >= 0; k--) {
-        const int o = WR ? r % R : r % 3 - 1;
-        r /= R;
-        og[k] = o;
-        int c2 = ci[k] + o;
-        c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
-        P += c2 * stride[k];
-        Dp[k / 2] |= ((kQScale * o) & 0xffff) << (16 * (k % 2));
-      }
-      return P;
-    };
-    int rowmax = 0;
-    // home atoms in passes of up to 128: lane l holds atoms hb + l and hb + 64 + l
-    for (int hb = h0; hb < h1; hb += 128) {
-      const int hcnt = uniform_int(min(128, h1 - hb));
-      const bool two = hcnt > 64;
-      const int i0 = hb + lane, i1 = hb + 64 + lane;
-      const bool v0 = lane < hcnt, v1 = lane + 64 < hcnt;
-      const int ii0 = v0 ? i0 : hb, ii1 = v1 ? i1 : hb;
-      int qh0[D], qh1[D];
-      auto own_q = [&](int ii, int (&qh)[D]) {
-        const v4i w0 = *reinterpret_cast<const v4i*>(qc16 + (size_t)ii * 8);
-        int w[5] = {w0.x, w0.y, w0.z, w0.w, 0};
-        if (HW > 4) w[4] = qc16[(size_t)ii * 8 + 4];
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-          const int word = w[k / 2];
-          if (WR) {
-            // gap to the other subcell along axis k (n_cell = 2: it touches both
-            // faces), one unit short: L_sc/2 - |u - centre| - 1 in 2^16/L units
-            const int u = (k % 2) ? ((word >> 16) & 0xffff) : (word & 0xffff);
-            const int cc = (k < D - 1 ? ci[k < D - 1 ? k : 0] : cl) * 32768 + 16384;
-            const int y = (int)(short)((u - cc) & 0xffff);
-            qh[k] = max(16384 - abs(y) - 1, 0);
-          } else {
-            qh[k] = (k % 2) ? (word >> 16) : (int)(short)(word & 0xffff);
-          }
-        }
-      };
-      own_q(ii0, qh0);
-      own_q(ii1, qh1);
-      int len0 = 0, len1 = 0, nb = 0;
-
-      // exact test of one home atom's survivors, in chunk and lane order.
-      // The nearest image is taken with rint: with n_cell >= 3 the list radius
-      // is at most L/3, so every pair it can admit has all |dx_k| clear of
-      // L/2, where rint and the definition's shift give the same value bit
-      // for bit; pairs with some |dx_k| near L/2 are beyond the radius either
-      // way.
-      auto exact_one = [&](int set, int ii, int i, int& len) {
-        double xi[D], si;  // own record, reloaded (cache hit) to keep registers free
-        load_rec<D>(xb, ii, xi, si);
-        for (int b = 0; b < nb; b++) {
-          unsigned long long m = msk[b * 128 + set * 64 + lane];
-          while (m) {
-            const int j = cand[b * 64 + __builtin_ctzll(m)];
-            m &= m - 1;
-            double xj[D], sj;
-            load_rec<D>(xb, j, xj, sj);
-            if (j != i) {
-              double r2 = 0.0;
-#pragma unroll
-              for (int k = 0; k < D; k++) {
-                const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
-                                     : near_image(xj[k] - xi[k], L, invL);
-                r2 = __builtin_fma(dx, dx, r2);
-                __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
-              }
-              if (r2 < list_r2(si, sj, cut, skin)) {
-                if (len < W) nl[(size_t)len * npad + i] = j;
-                len++;
-              }
-            }
-          }
-        }
-      };
-      auto exact_pass = [&]() {
-        wave_lds_sync();
-        exact_one(0, ii0, i0, len0);
-        if (two) exact_one(1, ii1, i1, len1);
-        wave_lds_sync();
-        nb = 0;
-      };
-
-      // ballots of the kept home atoms of one set against `nch` chunks, four
-      // home atoms per group of scalar loads (a short last group repeats its
-      // last atom); lane h of m[c] receives home atom h's ballot for chunk c
-      auto test_set = [&](unsigned long long km, int rb, int nch, const int (&cw)[CB][HW],
-                          const int (&tA)[CB], unsigned (&mlo)[CB], unsigned (&mhi)[CB]) {
-        while (km) {
-          int hh[4];
-          hh[0] = __builtin_ctzll(km);
-          km &= km - 1;
-#pragma unroll
-          for (int u = 1; u < 4; u++) {
-            hh[u] = km ? __builtin_ctzll(km) : hh[u - 1];
-            km &= km - 1;
-          }
-          Rec r[4];
-#pragma unroll
-          for (int u = 0; u < 4; u++) r[u] = *(CRec*)(qc16 + (size_t)(rb + hh[u]) * 8);
-#pragma unroll
-          for (int c = 0; c < CB; c++) {
-            if (c >= nch) break;
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              unsigned long long m;
-              if (WR) {
-                // |u_j - u_i|^2 over 16-bit wrapped differences (saturating: far
-                // pairs clamp at INT_MAX) against the lane's threshold
-                int acc = 0;
-#pragma unroll
-                for (int k = 0; k < HW; k++) {
-                  const short2v dq = __builtin_bit_cast(short2v, cw[c][k]) -
-                                     __builtin_bit_cast(short2v, (int)r[u][k]);
-                  acc = __builtin_amdgcn_sdot2(dq, dq, acc, true);
-                }
-                m = __ballot(acc < tA[c]);
-              } else {
-                int acc = tA[c];
-#pragma unroll
-                for (int k = 0; k < HW; k++)
-                  acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
-                                               __builtin_bit_cast(short2v, cw[c][k]), acc, false);
-                m = __ballot(acc > r[u][BW]);
-              }
-              mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo[c]);
-              mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi[c]);
-            }
-          }
-        }
-      };
-
-      for (int row = 0; row < nrow; row++) {
-        int Dp[HW], og[D - 1];
-        const int P = row_base(row, Dp, og);
-        // home atoms that can reach this row: gap to the neighbouring faces
-        // along the first d-1 axes, one quantisation unit short per axis
-        unsigned long long keep0, keep1;
-        {
-          int S0 = 0, S1 = 0;
-#pragma unroll
-          for (int k = 0; k < D - 1; k++) {
-            const int o = og[k];
-            int g0, g1;
-            if (WR) {
-              g0 = o ? qh0[k] : 0;
-              g1 = o ? qh1[k] : 0;
-            } else {
-              g0 = (kQScale / 2) - o * qh0[k] - 1;
-              g1 = (kQScale / 2) - o * qh1[k] - 1;
-              g0 = (o == 0 || g0 < 0) ? 0 : g0;
-              g1 = (o == 0 || g1 < 0) ? 0 : g1;
-            }
-            S0 += g0 * g0;
-            S1 += g1 * g1;
-          }
-          keep0 = __ballot(v0 && S0 < tcull);
-          keep1 = __ballot(v1 && S1 < tcull);
-        }
-        if ((keep0 | keep1) == 0) continue;
-        // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
-        const int st0 = flat[P + lm];
-        const int n0 = flat[P + lm + 1] - st0;
-        const int c1 = WR ? lp : cl;
-        const int st1 = (WR && R < 2) ? 0 : flat[P + c1];
-        const int n1 = (WR && R < 2) ? 0 : flat[P + c1 + 1] - st1;
-        const int st2 = WR ? 0 : flat[P + lp];
-        const int n2 = WR ? 0 : flat[P + lp + 1] - st2;
-        const int T = n0 + n1 + n2;
-        for (int k0 = 0; k0 < T; k0 += CB * 64) {
-          const int nch = min(CB, (T - k0 + 63) / 64);
-          if (nb + CB > NB) exact_pass();
-          // candidates of up to CB chunks: records (an in-range atom for the
-          // empty lanes) shifted by the subcell offset as packed int16 adds
-          int cw[CB][HW], tA[CB];
-#pragma unroll
-          for (int c = 0; c < CB; c++) {
-            if (c >= nch) continue;
-            const int tt = k0 + c * 64 + lane;
-            const bool valid = c < nch && tt < T;
-            const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
-            const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
-            const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
-            const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
-            if (WR) {
-#pragma unroll
-              for (int k = 0; k < HW; k++) cw[c][k] = src[k];
-              tA[c] = valid ? tq : -1;  // the lane's threshold; none for an empty lane
-            } else {
-              int A = 0;
-#pragma unroll
-              for (int k = 0; k < HW; k++) {
-                const short2v q2 = __builtin_bit_cast(short2v, src[k]);
-                const short2v o2 =
-                    __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
-                const short2v r2 = q2 + o2;
-                A = __builtin_amdgcn_sdot2(r2, r2, A, false);
-                cw[c][k] = __builtin_bit_cast(int, r2 + r2);
-              }
-              tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
-            }
-            cand[(nb + c) * 64 + lane] = valid ? j : -1;
-          }
-          // (tq - A_j) + q_i.(2 q'_j) > B_i  <=>  |q'_j - q_i|^2 < tq
-          unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
-#pragma unroll
-          for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
-          test_set(keep0, hb, nch, cw, tA, m0lo, m0hi);
-          test_set(keep1, hb + 64, nch, cw, tA, m1lo, m1hi);
-#pragma unroll
-          for (int c = 0; c < CB; c++) {
-            if (c < nch) {
-              msk[(nb + c) * 128 + lane] = ((unsigned long long)m0hi[c] << 32) | m0lo[c];
-              msk[(nb + c) * 128 + 64 + lane] = ((unsigned long long)m1hi[c] << 32) | m1lo[c];
-            }
-          }
-          nb += nch;
-        }
-      }
-      exact_pass();
-      if (v0) {
-        s->nlen[i0] = len0;
-        rowmax = max(rowmax, len0);
-      }
-      if (v1) {
-        s->nlen[i1] = len1;
-        rowmax = max(rowmax, len1);
-      }
-    }
-    rowmax = wave_max_i(rowmax);
-    if (lane == 0 && rowmax > 0) {
-      atomicMax(&s->max_row, rowmax);
-      if (rowmax > W) atomicOr(&s->err, ERR_OVERFLOW);
-    }
+    build_t_tile<D, G, WR>(s, hc, wv, msk_all[wv], cand_all[wv]);
   }
 }
 

@@ -792,6 +792,7 @@ struct HostBatch {
   Table* dtab = nullptr;
   int2* d_atom = nullptr;
   int2* d_cell = nullptr;
+  int2* d_cell_all = nullptr;  // every class: all n_cell >= 3 subcells, then all wrap ones
   int2* d_chunk = nullptr;
   int32_t* d_syslist = nullptr;
   int32_t* d_state = nullptr;
@@ -801,7 +802,7 @@ struct HostBatch {
   // current composition
   int n_atom[kMaxD + 1] = {0}, n_cell[kMaxD + 1] = {0}, n_nowrap[kMaxD + 1] = {0};
   int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};  // wrap-variant build tile per d
-  int n_atom_all = 0, n_cell_all = 0;
+  int n_atom_all = 0, n_cell_all = 0, n_nowrap_all = 0;
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
        has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
@@ -811,7 +812,7 @@ static std::mutex g_batch_mu;
 static std::unordered_map<void*, HostBatch*> g_batches;
 
 struct BatchLayout {
-  size_t off_tab, off_atom, off_cell, off_chunk, off_sys, off_state, off_iters, bytes;
+  size_t off_tab, off_atom, off_cell, off_cell_all, off_chunk, off_sys, off_state, off_iters, bytes;
 };
 
 static BatchLayout batch_layout(int max_slots, int64_t cap_atom, int64_t cap_cell,
@@ -826,6 +827,7 @@ static BatchLayout batch_layout(int max_slots, int64_t cap_atom, int64_t cap_cel
   L.off_tab = take(sizeof(Table));
   L.off_atom = take((size_t)cap_atom * sizeof(int2));
   L.off_cell = take((size_t)cap_cell * sizeof(int2));
+  L.off_cell_all = take((size_t)cap_cell * sizeof(int2));
   L.off_chunk = take((size_t)cap_chunk * sizeof(int2));
   L.off_sys = take((size_t)max_slots * 4);
   L.off_state = take((size_t)max_slots * 4);
@@ -919,10 +921,23 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
     t.cell_tiles[d] = B->d_cell + c_off[d];
   }
   t.n_atom[0] = (int32_t)atom_base;  // class 0: every class
+  // class 0 lists its cell tiles in an array of its own, the n_cell >= 3
+  // subcells of every class before the wrap ones (the list build of a batch
+  // gives the former one wave each and the latter a workgroup each)
+  std::vector<int2> cell_all;
+  cell_all.reserve(cell.size());
+  for (int pass = 0; pass < 2; pass++)
+    for (int d = kMinD; d <= kMaxD; d++) {
+      const int64_t lo = c_off[d] + (pass ? B->n_nowrap[d] : 0);
+      const int64_t hi = c_off[d] + (pass ? B->n_cell[d] : B->n_nowrap[d]);
+      cell_all.insert(cell_all.end(), cell.begin() + lo, cell.begin() + hi);
+    }
+  B->n_nowrap_all = 0;
+  for (int d = kMinD; d <= kMaxD; d++) B->n_nowrap_all += B->n_nowrap[d];
   t.n_cell[0] = (int32_t)cell_base;
-  t.n_cell_nowrap[0] = (int32_t)cell_base;
+  t.n_cell_nowrap[0] = B->n_nowrap_all;
   t.atom_tiles[0] = B->d_atom;
-  t.cell_tiles[0] = B->d_cell;
+  t.cell_tiles[0] = B->d_cell_all;
   B->n_atom_all = (int)atom_base;
   B->n_cell_all = (int)cell_base;
   t.n_chunk = B->n_chunk;
@@ -931,6 +946,8 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
   t.sys_list = B->d_syslist;
   if (!atom.empty()) HIPCHK(hipMemcpyAsync(B->d_atom, atom.data(), atom.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   if (!cell.empty()) HIPCHK(hipMemcpyAsync(B->d_cell, cell.data(), cell.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  if (!cell_all.empty())
+    HIPCHK(hipMemcpyAsync(B->d_cell_all, cell_all.data(), cell_all.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   if (!chunk.empty()) HIPCHK(hipMemcpyAsync(B->d_chunk, chunk.data(), chunk.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   if (!sys.empty()) HIPCHK(hipMemcpyAsync(B->d_syslist, sys.data(), sys.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(B->dtab, &t, sizeof(Table), hipMemcpyHostToDevice, st));
@@ -961,7 +978,8 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   auto ga = [&](int d) { return grids[2 + 3 * (d - kMinD)]; };
   auto gc = [&](int d) { return grids[3 + 3 * (d - kMinD)]; };
   KArgs a0 = batch_args(B, 0);  // class 0: the tiles of every class
-  const int ga_all = grids[grids.size() - 3], gc_all = grids[grids.size() - 2];
+  const int ga_all = grids[grids.size() - 4], gc_all = grids[grids.size() - 3];
+  const int gb_all = grids[grids.size() - 2];
   if (B->has_fire) {
     launch_fire_ctrl(a0, gsys, st);
     launch_fire_update_all(a0, ga_all, st);
@@ -974,9 +992,13 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   launch_scan2(a0, gsys, st);
   launch_scatter(a0, ga_all, st);
   launch_cellsort_all(a0, gc_all, st);
-  for (int d = kMinD; d <= kMaxD; d++) {
-    if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
-    if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
+  if (gb_all > 0) {
+    launch_build_all(a0, gb_all, st);
+  } else {
+    for (int d = kMinD; d <= kMaxD; d++) {
+      if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
+      if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
+    }
   }
   launch_finalize(a0, gsys, st);
   if (B->has_fire) {
@@ -1016,6 +1038,7 @@ int hdmd_batch_init(void* table_ws, size_t table_bytes, int32_t max_slots, int64
   B->dtab = at<Table>(table_ws, L.off_tab);
   B->d_atom = at<int2>(table_ws, L.off_atom);
   B->d_cell = at<int2>(table_ws, L.off_cell);
+  B->d_cell_all = at<int2>(table_ws, L.off_cell_all);
   B->d_chunk = at<int2>(table_ws, L.off_chunk);
   B->d_syslist = at<int32_t>(table_ws, L.off_sys);
   B->d_state = at<int32_t>(table_ws, L.off_state);
@@ -1119,6 +1142,10 @@ int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
   grids.push_back(B->has_md ? 1 : 0);
   grids.push_back(pow2_grid(B->n_atom_all, 4096));  // all-class launches
   grids.push_back(pow2_grid(B->n_cell_all, 8192));
+  // one list-build launch over every class (0: one launch per class and variant)
+  grids.push_back(std::getenv("HDMD_BUILD_PER_CLASS")
+                      ? 0
+                      : pow2_grid((B->n_nowrap_all + 3) / 4 + (B->n_cell_all - B->n_nowrap_all), 8192));
   grids.push_back(iterations);
   if (!graphs_enabled()) {
     for (int k = 0; k < iterations; k++) enqueue_batch_iter(B, grids, st);
