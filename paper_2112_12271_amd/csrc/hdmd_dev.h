@@ -137,6 +137,19 @@ struct KArgs {
   int32_t part;
 };
 
+// Workgroups of a launch are handed to the eight XCDs in turn (workgroup b to
+// XCD b mod 8), each XCD with its own L2.  For a grid that is a multiple of
+// eight, this maps workgroup b to tile (b mod 8)·(grid/8) + b/8, so that each
+// XCD takes one contiguous run of tiles (neighbouring subcells, whose linked
+// subcells overlap) instead of every eighth tile.  A bijection on [0, grid).
+__device__ inline int xcd_tile(int b, int g) {
+#ifdef HDMD_NO_XCD
+  return b;
+#else
+  return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
+#endif
+}
+
 __device__ inline bool fetch_atom_tile(const KArgs& a, int t, SysDev*& s, int& tile) {
   if (a.single) {
     s = a.single;

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_cellsort_all(KArgs a) {
 
 __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
   __shared__ double sh[kPart];
-  for (int t = blockIdx.x;; t += gridDim.x) {
+  for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
   const int unw = (nnw + 3) / 4;
   const int units = unw + (ntot - nnw);
   const int2* tiles = a.tab->cell_tiles[0];
-  for (int u = blockIdx.x; u < units; u += gridDim.x) {
+  for (int u = xcd_tile(blockIdx.x, gridDim.x); u < units; u += gridDim.x) {
     const bool wr = u >= unw;
     const int idx = wr ? nnw + (u - unw) : 4 * u + wv;
     if (idx >= ntot || (!wr && idx >= nnw)) continue;

@@ -694,43 +694,59 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     own_q(ii1, qh1);
     int len0 = 0, len1 = 0, nb = 0;
 
-    // exact test of one home atom's survivors, in chunk and lane order.
+    // exact test of the survivors.  Each lane walks its own: home set 0
+    // before set 1, each in chunk and lane order (the row order), so the
+    // wave's trip count is the largest per-lane survivor count of the pass.
     // The nearest image is taken with rint: with n_cell >= 3 the list radius
     // is at most L/3, so every pair it can admit has all |dx_k| clear of
     // L/2, where rint and the definition's shift give the same value bit
     // for bit; pairs with some |dx_k| near L/2 are beyond the radius either
     // way.
-    auto exact_one = [&](int set, int ii, int i, int& len) {
-      double xi[D], si;  // own record, reloaded (cache hit) to keep registers free
-      load_rec<D>(xb, ii, xi, si);
+    static_assert(NB <= 16, "chunk bits of both sets fit 32 bits");
+    auto exact_pass = [&]() {
+      wave_lds_sync();
+      unsigned ne = 0;  // bit set*NB + b: chunk b holds survivors of home set `set`
       for (int b = 0; b < nb; b++) {
-        unsigned long long m = msk[b * 128 + set * 64 + lane];
-        while (m) {
-          const int j = cand[b * 64 + __builtin_ctzll(m)];
-          m &= m - 1;
-          double xj[D], sj;
-          load_rec<D>(xb, j, xj, sj);
-          if (j != i) {
-            double r2 = 0.0;
+        if (msk[b * 128 + lane]) ne |= 1u << b;
+        if (two && msk[b * 128 + 64 + lane]) ne |= 1u << (NB + b);
+      }
+      unsigned long long m = 0;
+      int cb = 0, cur = -1, i = 0;
+      double xi[D], si;  // own record, loaded when the walk reaches its set
+      while (true) {
+        if (m == 0) {
+          if (ne == 0) break;
+          cb = __builtin_ctz(ne);
+          ne &= ne - 1;
+          const int set = cb >= NB ? 1 : 0;
+          m = msk[(cb % NB) * 128 + set * 64 + lane];
+          if (set != cur) {
+            cur = set;
+            i = set ? i1 : i0;
+            load_rec<D>(xb, set ? ii1 : ii0, xi, si);
+          }
+        }
+        const int j = cand[(cb % NB) * 64 + __builtin_ctzll(m)];
+        m &= m - 1;
+        double xj[D], sj;
+        load_rec<D>(xb, j, xj, sj);
+        if (j != i) {
+          double r2 = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; k++) {
-              const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
-                                   : near_image(xj[k] - xi[k], L, invL);
-              r2 = __builtin_fma(dx, dx, r2);
-              __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
-            }
-            if (r2 < list_r2(si, sj, cut, skin)) {
-              if (len < W) nl[(size_t)len * npad + i] = j;
-              len++;
-            }
+          for (int k = 0; k < D; k++) {
+            const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
+                                 : near_image(xj[k] - xi[k], L, invL);
+            r2 = __builtin_fma(dx, dx, r2);
+            __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
+          }
+          if (r2 < list_r2(si, sj, cut, skin)) {
+            const int len = cur ? len1 : len0;
+            if (len < W) nl[(size_t)len * npad + i] = j;
+            if (cur) len1 = len + 1;
+            else len0 = len + 1;
           }
         }
       }
-    };
-    auto exact_pass = [&]() {
-      wave_lds_sync();
-      exact_one(0, ii0, i0, len0);
-      if (two) exact_one(1, ii1, i1, len1);
       wave_lds_sync();
       nb = 0;
     };
@@ -894,7 +910,7 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
   __shared__ unsigned long long msk_all[G][8 * 128];
   __shared__ int cand_all[G][8 * 64];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int t = blockIdx.x;; t += gridDim.x) {
+  for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int hc;
     if (!fetch_cell_tile(a, t, s, hc)) break;
@@ -1156,7 +1172,7 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
 template <int D, bool MIX, int LPA>
 __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
   __shared__ double sh[LPA * kPart];
-  for (int t = blockIdx.x;; t += gridDim.x) {
+  for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
@@ -1177,7 +1193,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
   typedef typename VType<MIX>::T VT;
   __shared__ double sh[LPA * kPart];
   const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
-  for (int t = blockIdx.x;; t += gridDim.x) {
+  for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
