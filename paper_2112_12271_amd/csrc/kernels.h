@@ -786,9 +786,14 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
               }
               m = __ballot(acc < tA[c]);
             } else {
-              int acc = tA[c];
+              // the first product in the three-operand form, so the lane's
+              // threshold needs no copy into an accumulator register
+              int acc;
+              asm("v_dot2_i32_i16 %0, %1, %2, %3"
+                  : "=v"(acc)
+                  : "s"((int)r[u][0]), "v"(cw[c][0]), "v"(tA[c]));
 #pragma unroll
-              for (int k = 0; k < HW; k++)
+              for (int k = 1; k < HW; k++)
                 acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
                                              __builtin_bit_cast(short2v, cw[c][k]), acc, false);
               m = __ballot(acc > r[u][BW]);
