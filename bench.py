@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK = 78.6e12   # FP64 vector operations per second (MI355X, dense)
 
 
 def log(*a):
@@ -46,6 +47,20 @@ def step_bytes_per_atom(d: int, mean_row: float, mixed: bool) -> float:
     (4) and own diameter (8).  Gathered neighbour data is not counted."""
     bv = 4 if mixed else 8
     return 8 * d * 3 + 2 * bv * d + 4 * mean_row + 4 + 8
+
+
+def build_candidates(x: np.ndarray, L: float, nc: int) -> int:
+    """Candidate pairs one list build meets (Sec. II.B): for every subcell c,
+    its atoms times the atoms of the 3^d subcells linked to it, from the
+    subcell occupancy of positions x with nc >= 3 subcells per axis."""
+    d = x.shape[1]
+    idx = np.minimum((np.mod(x, L) * (nc / L)).astype(np.int64), nc - 1)
+    occ = np.zeros((nc,) * d, dtype=np.int64)
+    np.add.at(occ, tuple(idx.T), 1)
+    linked = np.zeros_like(occ)
+    for off in np.ndindex(*(3,) * d):
+        linked += np.roll(occ, tuple(o - 1 for o in off), axis=tuple(range(d)))
+    return int((occ * linked).sum())
 
 
 def kernel_hash() -> str:
@@ -111,8 +126,10 @@ def run_md(H, torch, cfg, x0, v0, sig, L, prec, steps, warmup, every, profile):
     os.environ.pop("HDMD_PROFILE", None)
     rp, cols = H.hdmd_nlist_export(sysd, ws)
     mean_row = cols.numel() / cfg.n
+    nc = H.hdmd_cells_per_axis(sysd)
+    cand = build_candidates(Xs.cpu().numpy(), L, nc) if nc >= 3 else None
     return dict(seconds=t1 - t0, stats=st, thermo=th.cpu().numpy(), mean_row=mean_row,
-                width=sysd.max_neighbors)
+                width=sysd.max_neighbors, candidates=cand)
 
 
 def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5):
@@ -351,6 +368,7 @@ def main():
                 ach = cfg.n * bpa / (avg_ms * 1e-3) / 1e9
                 rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
                            build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
+                           build_candidates=r["candidates"],
                            share_step_kernel=st.step_kernel_ms / (1e3 * r["seconds"]),
                            share_build_kernel=st.build_kernel_ms / (1e3 * r["seconds"]))
             out[name] = rec
@@ -366,6 +384,18 @@ def main():
                 "traffic": committed_traffic("step_kernel_c3_traffic.json"),
                 "kernel": "k_step<6,fp64>", "bytes_per_launch": cfg.n * f["step_bytes_per_atom"],
                 "launch_ms": f["step_kernel_ms"]}
+    # the list build against the vector peak: candidate pairs per second over
+    # the rate at which the FP64 vector units could test them one by one
+    # (3d + 2 operations: per axis a difference, its nearest-image shift and a
+    # fused square-accumulate; the pair radius; the compare)
+    roof_build = None
+    if f.get("build_ms") and f.get("build_candidates"):
+        ops = 3 * cfg.d + 2
+        ach = f["build_candidates"] / (f["build_ms"] * 1e-3)
+        roof_build = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK / ops,
+                      "unit": "candidates/s", "frac": ach * ops / FP64_VECTOR_PEAK,
+                      "kernel": "k_build_t<6,1>", "candidates_per_build": f["build_candidates"],
+                      "launch_ms": f["build_ms"], "ops_per_candidate": ops}
     cpu = None
     if not args.no_cpu_baseline and not args.no_md:
         cpu = cpu_baseline(cfg, f["steps_per_build"])
@@ -388,6 +418,7 @@ def main():
                                   cfg.skin, cfg.T),
                    "precision": "fp64", "timed_with_events": not args.no_profile},
         "roofline": roof,
+        "roofline_build": roof_build,
         "cpu_baseline": cpu,
         "fp64": out.get("fp64"),
         "mixed": out.get("mixed"),

@@ -579,6 +579,15 @@ __device__ inline double uniform_dbl(double v) {
 // replaced by the uniform `val`.
 __device__ int amdgcn_writelane(int val, int ln, int old) __asm("llvm.amdgcn.writelane");
 
+// Wave priority 3, 2, 1, 0 over the four quarters of done/total (uniform).
+__device__ inline void set_prio_by_progress(int done, int total) {
+  const int q = (4 * done) / total;
+  if (q == 0) __builtin_amdgcn_s_setprio(3);
+  else if (q == 1) __builtin_amdgcn_s_setprio(2);
+  else if (q == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // Orders this wave's LDS writes before its later LDS reads (other lanes).
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -806,6 +815,12 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     };
 
     for (int row = 0; row < nrow; row++) {
+      // A SIMD issues for its oldest waves first, so without this the waves
+      // of a launch finish one by one and the last ones run alone, their
+      // latencies exposed.  A wave's priority falls as it gets through its
+      // rows: the waves that lag get the issue slots, and those of a SIMD
+      // finish together.
+      set_prio_by_progress(row, nrow);
       int Dp[HW], og[D - 1];
       const int P = row_base(row, Dp, og);
       // home atoms that can reach this row: gap to the neighbouring faces
