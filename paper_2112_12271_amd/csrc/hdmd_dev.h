@@ -70,6 +70,7 @@ struct SysDev {
   double rlmax, lsc, inv_lsc, halfskin2;
   double fxscale, qinv;  // 2^32 / L; 250 / L_sc
   double fxinv;          // L / 2^32
+  double qmarg;          // sqrt(d)/2 with slack: half the quantisation error bound
   float rl2f, lscf, Lf, pad3;
   int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
                          // (squared quantised units)
@@ -81,7 +82,10 @@ struct SysDev {
   double* xref;
   float* ycell;
   int32_t* qc;
-  int32_t* qc16;  // int16 offsets or wrapped 16-bit coordinates, [npad][8]
+  int32_t* qc16;  // int16 offsets or wrapped 16-bit coordinates, [npad][8];
+                  // n_cell >= 3: words 0.. the offsets as int16 pairs, word
+                  // 3 (d <= 6) or 7 the home term |q|^2 - T, word 5 the
+                  // row-cull threshold, word 6 the threshold share T
   int32_t* cell_of;
   int32_t* rank;
   int32_t* cell_count;

@@ -266,8 +266,14 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
         w[k / 4] |= (quant8(x[k] - cen[k], s->qinv) & 0xff) << (8 * (k % 4));
 #pragma unroll
       for (int k = 0; k < QW; k++) s->qc[(size_t)dst * 4 + k] = w[k];
-      // the same offsets as int16 pairs for the candidate-lane build
-      // and |q|^2 in the last word read by the home-atom loads
+      // the same offsets as int16 pairs for the candidate-lane build, with
+      // the atom's share of the pair threshold.  A pair is within its list
+      // radius r_ij = a_i + a_j, a = (c sigma + s)/2, only if
+      // |q_j - q_i| < alpha_i + alpha_j, alpha = a/Delta + sqrt(d)/2 (each
+      // axis is off by at most one unit), and (alpha_i + alpha_j)^2 <=
+      // 2 alpha_i^2 + 2 alpha_j^2 < T_i + T_j with T = floor(2 alpha^2) + 1:
+      // one integer per atom, so the test stays one sum of products.  The
+      // row cull takes the atom's reach a_i + r_l,max/2 instead of r_l,max.
       int p16[8], B = 0;
 #pragma unroll
       for (int k = 0; k < 8; k++) p16[k] = 0;
@@ -277,10 +283,16 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
         p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
         B += qv * qv;
       }
-      p16[(D + 1) / 2 < 4 ? 3 : 7] = B;
+      const double ai = 0.5 * (s->cutoff * sg + s->skin);
+      const double al = ai * s->qinv + s->qmarg;
+      const int T = (int)floor(2.0 * al * al) + 1;
+      const double reach = (ai + 0.5 * s->rlmax) * s->qinv;
+      p16[(D + 1) / 2 < 4 ? 3 : 7] = B - T;
+      p16[5] = (int)ceil(reach * reach);
+      p16[6] = T;
       int4* pp = reinterpret_cast<int4*>(s->qc16 + (size_t)dst * 8);
       pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
-      if (D > 6) pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
+      pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
     }
     s->oid[pn][dst] = keys[q];
   }
@@ -534,10 +546,13 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 // 64-lane chunks: every lane takes one candidate j, shifts its quantised
 // offsets by the subcell offset (q'_j = q_j + 250 o as int16, |q'| <= 375)
 // and forms A_j = |q'_j|^2.  The home atoms i kept for the row are then
-// walked uniformly, their records (q_i as int16 pairs and B_i = |q_i|^2)
+// walked uniformly, their records (q_i as int16 pairs and B_i = |q_i|^2 - T_i)
 // coming through the scalar cache, each test being
-//   |q'_j - q_i|^2 < tq  <=>  (tq - A_j) + q_i.(2 q'_j) > B_i
-// (v_dot2_i32_i16 on int16 pairs) against the same threshold as k_build.
+//   |q'_j - q_i|^2 < T_i + T_j  <=>  (T_j - A_j) + q_i.(2 q'_j) > B_i
+// (v_dot2_i32_i16 on int16 pairs), with per-atom threshold shares T that
+// follow the pair's own list radius (set where the records are written).
+// Wrapped systems (n_cell <= 2) test |u_j - u_i|^2 < tq on 16-bit wrapped
+// coordinates against the largest list radius.
 // The ballot of each test is written into lane i of a mask register, so
 // after a chunk lane i holds the 64-bit mask of its surviving candidates.
 // Every NB chunks the lanes turn back into home atoms and run the exact
@@ -680,6 +695,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     const bool v0 = lane < hcnt, v1 = lane + 64 < hcnt;
     const int ii0 = v0 ? i0 : hb, ii1 = v1 ? i1 : hb;
     int qh0[D], qh1[D];
+    // the row-cull threshold of each home atom (n_cell >= 3: its own reach;
+    // wrapped: r_l,max)
+    const int tc0 = WR ? tcull : qc16[(size_t)ii0 * 8 + 5];
+    const int tc1 = WR ? tcull : qc16[(size_t)ii1 * 8 + 5];
     auto own_q = [&](int ii, int (&qh)[D]) {
       const v4i w0 = *reinterpret_cast<const v4i*>(qc16 + (size_t)ii * 8);
       int w[5] = {w0.x, w0.y, w0.z, w0.w, 0};
@@ -844,8 +863,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           S0 += g0 * g0;
           S1 += g1 * g1;
         }
-        keep0 = __ballot(v0 && S0 < tcull);
-        keep1 = __ballot(v1 && S1 < tcull);
+        keep0 = __ballot(v0 && S0 < tc0);
+        keep1 = __ballot(v1 && S1 < tc1);
       }
       if ((keep0 | keep1) == 0) continue;
       // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
@@ -887,11 +906,11 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
               A = __builtin_amdgcn_sdot2(r2, r2, A, false);
               cw[c][k] = __builtin_bit_cast(int, r2 + r2);
             }
-            tA[c] = valid ? tq - A : -0x3fffffff;  // never passes for an empty lane
+            tA[c] = valid ? src[6] - A : -0x3fffffff;  // never passes for an empty lane
           }
           cand[(nb + c) * 64 + lane] = valid ? j : -1;
         }
-        // (tq - A_j) + q_i.(2 q'_j) > B_i  <=>  |q'_j - q_i|^2 < tq
+        // (T_j - A_j) + q_i.(2 q'_j) > |q_i|^2 - T_i  <=>  |q'_j - q_i|^2 < T_i + T_j
         unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;

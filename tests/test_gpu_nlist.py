@@ -66,6 +66,41 @@ def test_boundary_band_bit_exact(orc, d, nc):
     assert csr_equal(got, ref)
 
 
+@pytest.mark.parametrize("d,nc", [(3, 3), (4, 3), (6, 3), (3, 5), (5, 4)])
+def test_pair_radius_band_bidisperse(orc, d, nc):
+    """Pairs at their own list radius c sigma_ij + s, a few ulps either side,
+    with diameters 1 and 2 mixed (n_cell >= 3): the prefilter's per-atom
+    shares of the pair threshold keep every pair the definition lists."""
+    c, s = 1.0, 0.25
+    sig_v = np.array([1.0, 2.0])
+    rlmax = c * 2.0 + s
+    L = nc * rlmax * (1.0 + 4e-9)
+    g = np.random.default_rng(53 * d + nc)
+    h = 0.5 * L
+    xs, sig = [], []
+    for p in range(300):
+        sa, sb = sig_v[g.integers(2)], sig_v[g.integers(2)]
+        a = g.uniform(-h, h, d)
+        u = g.normal(size=d)
+        u /= np.linalg.norm(u)
+        rl = c * 0.5 * (sa + sb) + s
+        b = a + (rl + g.integers(-4, 5) * np.spacing(rl)) * u
+        b = np.where(b >= h, b - L, b)
+        b = np.where(b < -h, b + L, b)
+        b = np.where(b >= h, -h, b)
+        xs += [a, b]
+        sig += [sa, sb]
+    x, sig = np.array(xs), np.array(sig)
+    ref = orc.nlist_brute(x, sig, L, c, s)
+    assert len(ref[1]) > 300
+    for prec in (H.HDMD_FP64, H.HDMD_MIXED):
+        sysd = H.System(d=d, n=len(x), box_l=L, cutoff=c, skin=s, sigma_max=2.0,
+                        precision=prec, max_neighbors=8)
+        assert H.hdmd_cells_per_axis(sysd) == nc
+        got, _, _ = gpu_list(sysd, x, sig)
+        assert csr_equal(got, ref), prec
+
+
 @pytest.mark.parametrize("d,m,kmax", [(3, 6, 4), (4, 5, 4), (6, 4, 2), (8, 3, 2), (10, 3, 1)])
 def test_lattice_shells(d, m, kmax):
     """Closed-form coordination shells of a lattice filling the periodic box."""
