@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_VECTOR_PEAK = 78.6e12   # FP64 vector operations per second (MI355X, dense)
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9   # vector lane-operations per second (MI355X)
 
 
 def log(*a):
@@ -384,18 +384,21 @@ def main():
                 "traffic": committed_traffic("step_kernel_c3_traffic.json"),
                 "kernel": "k_step<6,fp64>", "bytes_per_launch": cfg.n * f["step_bytes_per_atom"],
                 "launch_ms": f["step_kernel_ms"]}
-    # the list build against the vector peak: candidate pairs per second over
-    # the rate at which the FP64 vector units could test them one by one
-    # (3d + 2 operations: per axis a difference, its nearest-image shift and a
-    # fused square-accumulate; the pair radius; the compare)
+    # the list build against the vector ALU peak: every candidate pair of the
+    # subcell stencil (Sec. II.B) costs ceil(d/2) packed int16 dot products
+    # and a compare in the prefilter, one VALU lane-operation each; the peak
+    # is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second.
+    # (Row culling skips most candidates before any test, so the kernel's own
+    # VALU rate is lower than this algorithmic one.)
     roof_build = None
     if f.get("build_ms") and f.get("build_candidates"):
-        ops = 3 * cfg.d + 2
-        ach = f["build_candidates"] / (f["build_ms"] * 1e-3)
-        roof_build = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK / ops,
-                      "unit": "candidates/s", "frac": ach * ops / FP64_VECTOR_PEAK,
+        ops = (cfg.d + 1) // 2 + 1
+        ach = f["build_candidates"] * ops / (f["build_ms"] * 1e-3)
+        roof_build = {"bound": "alu", "achieved": ach, "peak": VALU_LANE_OPS_PEAK,
+                      "unit": "lane-op/s", "frac": ach / VALU_LANE_OPS_PEAK,
                       "kernel": "k_build_t<6,1>", "candidates_per_build": f["build_candidates"],
-                      "launch_ms": f["build_ms"], "ops_per_candidate": ops}
+                      "candidates_per_s": f["build_candidates"] / (f["build_ms"] * 1e-3),
+                      "launch_ms": f["build_ms"], "lane_ops_per_candidate": ops}
     cpu = None
     if not args.no_cpu_baseline and not args.no_md:
         cpu = cpu_baseline(cfg, f["steps_per_build"])
