@@ -720,6 +720,17 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     };
     own_q(ii0, qh0);
     own_q(ii1, qh1);
+    // the lane's own home record (offset words and the home term), from
+    // which the pair tests take each home atom's words with v_readlane: the
+    // records of every wave of a CU do not fit the scalar cache
+    int ow0[HW + 1], ow1[HW + 1];
+#pragma unroll
+    for (int k = 0; k < HW; k++) {
+      ow0[k] = qc16[(size_t)ii0 * 8 + k];
+      ow1[k] = qc16[(size_t)ii1 * 8 + k];
+    }
+    ow0[HW] = qc16[(size_t)ii0 * 8 + BW];
+    ow1[HW] = qc16[(size_t)ii1 * 8 + BW];
     int len0 = 0, len1 = 0, nb = 0;
 
     // exact test of the survivors.  Each lane walks its own: home set 0
@@ -782,8 +793,9 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // ballots of the kept home atoms of one set against `nch` chunks, four
     // home atoms per group of scalar loads (a short last group repeats its
     // last atom); lane h of m[c] receives home atom h's ballot for chunk c
-    auto test_set = [&](unsigned long long km, int rb, int nch, const int (&cw)[CB][HW],
-                        const int (&tA)[CB], unsigned (&mlo)[CB], unsigned (&mhi)[CB]) {
+    auto test_set = [&](unsigned long long km, const int (&ow)[HW + 1], int nch,
+                        const int (&cw)[CB][HW], const int (&tA)[CB], unsigned (&mlo)[CB],
+                        unsigned (&mhi)[CB]) {
       while (km) {
         int hh[4];
         hh[0] = __builtin_ctzll(km);
@@ -793,9 +805,12 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           hh[u] = km ? __builtin_ctzll(km) : hh[u - 1];
           km &= km - 1;
         }
-        Rec r[4];
+        int r[4][HW + 1];
 #pragma unroll
-        for (int u = 0; u < 4; u++) r[u] = *(CRec*)(qc16 + (size_t)(rb + hh[u]) * 8);
+        for (int u = 0; u < 4; u++) {
+#pragma unroll
+          for (int k = 0; k < HW + (WR ? 0 : 1); k++) r[u][k] = __builtin_amdgcn_readlane(ow[k], hh[u]);
+        }
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c >= nch) break;
@@ -824,7 +839,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
               for (int k = 1; k < HW; k++)
                 acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
                                              __builtin_bit_cast(short2v, cw[c][k]), acc, false);
-              m = __ballot(acc > r[u][BW]);
+              m = __ballot(acc > r[u][HW]);
             }
             mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo[c]);
             mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi[c]);
@@ -914,8 +929,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
-        test_set(keep0, hb, nch, cw, tA, m0lo, m0hi);
-        test_set(keep1, hb + 64, nch, cw, tA, m1lo, m1hi);
+        test_set(keep0, ow0, nch, cw, tA, m0lo, m0hi);
+        test_set(keep1, ow1, nch, cw, tA, m1lo, m1hi);
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c < nch) {
