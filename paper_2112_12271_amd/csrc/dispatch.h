@@ -28,6 +28,8 @@ void launch_bin_all(const KArgs& a, int grid, hipStream_t st);
 void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st);
 void launch_cellsort_all(const KArgs& a, int grid, hipStream_t st);
 void launch_force_all(const KArgs& a, int grid, int fire, hipStream_t st);
+// list build of the classes d <= kBuildAllMaxD; larger d keep per-class launches
+constexpr int kBuildAllMaxD = 8;
 void launch_build_all(const KArgs& a, int grid, hipStream_t st);
 
 // dimension-independent kernels (common.hip)

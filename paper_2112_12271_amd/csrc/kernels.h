@@ -721,8 +721,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     own_q(ii0, qh0);
     own_q(ii1, qh1);
     // the lane's own home record (offset words and the home term), from
-    // which the pair tests take each home atom's words with v_readlane: the
-    // records of every wave of a CU do not fit the scalar cache
+    // which the pair tests of n_cell >= 3 systems take each home atom's words
+    // with v_readlane: the records of every wave of a CU (one subcell each)
+    // do not fit the scalar cache.  Wrapped systems, whose waves walk long
+    // runs of one crowded subcell, read them with scalar loads.
     int ow0[HW + 1], ow1[HW + 1];
 #pragma unroll
     for (int k = 0; k < HW; k++) {
@@ -793,7 +795,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // ballots of the kept home atoms of one set against `nch` chunks, four
     // home atoms per group of scalar loads (a short last group repeats its
     // last atom); lane h of m[c] receives home atom h's ballot for chunk c
-    auto test_set = [&](unsigned long long km, const int (&ow)[HW + 1], int nch,
+    auto test_set = [&](unsigned long long km, const int (&ow)[HW + 1], int rb, int nch,
                         const int (&cw)[CB][HW], const int (&tA)[CB], unsigned (&mlo)[CB],
                         unsigned (&mhi)[CB]) {
       while (km) {
@@ -808,8 +810,14 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         int r[4][HW + 1];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
+          if constexpr (WR) {
+            const Rec w = *(CRec*)(qc16 + (size_t)(rb + hh[u]) * 8);
 #pragma unroll
-          for (int k = 0; k < HW + (WR ? 0 : 1); k++) r[u][k] = __builtin_amdgcn_readlane(ow[k], hh[u]);
+            for (int k = 0; k < HW; k++) r[u][k] = w[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k <= HW; k++) r[u][k] = __builtin_amdgcn_readlane(ow[k], hh[u]);
+          }
         }
 #pragma unroll
         for (int c = 0; c < CB; c++) {
@@ -929,8 +937,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
-        test_set(keep0, ow0, nch, cw, tA, m0lo, m0hi);
-        test_set(keep1, ow1, nch, cw, tA, m1lo, m1hi);
+        test_set(keep0, ow0, hb, nch, cw, tA, m0lo, m0hi);
+        test_set(keep1, ow1, hb + 64, nch, cw, tA, m1lo, m1hi);
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c < nch) {

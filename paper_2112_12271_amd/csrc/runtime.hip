@@ -995,6 +995,10 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   launch_cellsort_all(a0, gc_all, st);
   if (gb_all > 0) {
     launch_build_all(a0, gb_all, st);
+    for (int d = kBuildAllMaxD + 1; d <= kMaxD; d++) {
+      if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
+      if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
+    }
   } else {
     for (int d = kMinD; d <= kMaxD; d++) {
       if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
