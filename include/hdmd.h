@@ -45,7 +45,7 @@ typedef enum {
   HDMD_ERR_STATE = -7          /* workspace not initialised for this system, or batch misuse */
 } hdmd_status;
 
-typedef enum { HDMD_WCA = 0, HDMD_HARMONIC = 1 } hdmd_potential;
+typedef enum { HDMD_WCA = 0, HDMD_HARMONIC = 1, HDMD_MORSE = 2 } hdmd_potential;
 typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
 
 /* One system (Sec. II.A-C).  Pair (i,j) interacts for r < r_c = cutoff*sigma_ij
@@ -53,7 +53,10 @@ typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
  * in the Verlet list for r < cutoff*sigma_ij + skin (Sec. II.C).
  *   potential  HDMD_WCA: U = 4 eps [(sigma/r)^12 - (sigma/r)^6] + eps (the
  *              paper's Mie n=6 form, Sec. II.A, with cutoff 2^(1/6));
- *              HDMD_HARMONIC: U = eps/2 (1 - r/sigma)^2 (cutoff 1).
+ *              HDMD_HARMONIC: U = eps/2 (1 - r/sigma)^2 (cutoff 1);
+ *              HDMD_MORSE: U = eps [e^{-2a(r-sigma)} - 2 e^{-a(r-sigma)} + 1],
+ *              the paper's truncated and shifted Morse form (Sec. II.A,
+ *              eq. morsepot), with cutoff 1 and a = morse_a (the paper: 30).
  *   precision  HDMD_FP64: everything in FP64.  HDMD_MIXED: neighbour
  *              positions are gathered as 32-bit fixed-point coordinates whose
  *              integer difference is the exact minimum-image displacement;
@@ -62,7 +65,8 @@ typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
  *              and FIRE's reductions FP64.  Verlet lists are FP64-exact in
  *              both.
  *   sigma_max  largest diameter present; it sizes the subcells (eq. setnc).
- *   max_neighbors  Verlet row capacity W of the workspace. */
+ *   max_neighbors  Verlet row capacity W of the workspace.
+ *   morse_a    Morse stiffness a in 1/length (read for HDMD_MORSE only; > 0). */
 typedef struct {
   int32_t d;
   int32_t potential;
@@ -74,6 +78,7 @@ typedef struct {
   double skin;
   double epsilon;
   double sigma_max;
+  double morse_a;
 } hdmd_system;
 
 /* FIRE 2.0 controls (Sec. II.B cites FIRE 2.0 with the semi-implicit Euler

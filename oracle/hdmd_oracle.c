@@ -24,6 +24,7 @@
 
 #define ORC_WCA 0
 #define ORC_HARMONIC 1
+#define ORC_MORSE 2
 
 /* ------------------------------------------------------------------------- */
 /* Geometry                                                                  */
@@ -291,13 +292,27 @@ orc_list* orc_nlist_cells(int d, int64_t n, double L, const double* x, const dou
  *  WCA: U = 4 eps [(sigma/r)^12 - (sigma/r)^6] + eps, the paper's Mie form with
  *       n = 6 (Sec. II.A) rewritten with sigma at the zero crossing and shifted
  *       so that U(2^(1/6) sigma) = 0.
- *  Harmonic soft spheres: U = eps/2 (1 - r/sigma)^2. */
+ *  Harmonic soft spheres: U = eps/2 (1 - r/sigma)^2.
+ *  Morse (Sec. II.A, eq. morsepot): U = eps [exp(-2a(r - sigma))
+ *       - 2 exp(-a(r - sigma)) + 1] for r <= sigma, zero beyond (cutoff 1);
+ *       -U'(r)/r = 2 a eps [exp(-2a(r - sigma)) - exp(-a(r - sigma))] / r. */
+static double g_morse_a = 30.0;
+
+/* Morse stiffness a used by every later call (the paper's value is 30). */
+void orc_set_morse_a(double a) { g_morse_a = a; }
+
 static double pair(int pot, double r2, double sij, double eps, double* fcoef) {
   if (pot == ORC_WCA) {
     double s2 = sij * sij / r2;
     double s6 = s2 * s2 * s2;
     *fcoef = 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
     return 4.0 * eps * (s6 * s6 - s6) + eps;
+  } else if (pot == ORC_MORSE) {
+    double r = sqrt(r2);
+    double e1 = exp(-g_morse_a * (r - sij));
+    double e2 = exp(-2.0 * g_morse_a * (r - sij));
+    *fcoef = 2.0 * g_morse_a * eps * (e2 - e1) / r;
+    return eps * (e2 - 2.0 * e1 + 1.0);
   } else {
     double r = sqrt(r2);
     double g = 1.0 - r / sij;

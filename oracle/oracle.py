@@ -20,6 +20,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 WCA = 0
 HARMONIC = 1
+MORSE = 2
+MORSE_A = 30.0
 WCA_CUT = 2.0 ** (1.0 / 6.0)
 
 
@@ -72,6 +74,8 @@ def lib():
         L = C.CDLL(LIB)
         L.orc_sphere_volume.restype = C.c_double
         L.orc_sphere_volume.argtypes = [C.c_int, C.c_double]
+        L.orc_set_morse_a.restype = None
+        L.orc_set_morse_a.argtypes = [C.c_double]
         L.orc_ncell.restype = C.c_int
         L.orc_ncell.argtypes = [C.c_double, C.c_double]
         L.orc_wrap1.restype = C.c_double
@@ -111,6 +115,11 @@ def lib():
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_morse_a(a: float) -> None:
+    """Morse stiffness for every later call (default 30, the paper's value)."""
+    lib().orc_set_morse_a(a)
 
 
 def sphere_volume(d: int, sigma: float) -> float:

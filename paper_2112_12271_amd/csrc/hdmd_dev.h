@@ -71,6 +71,7 @@ struct SysDev {
   double fxscale, qinv;  // 2^32 / L; 250 / L_sc
   double fxinv;          // L / 2^32
   double qmarg;          // sqrt(d)/2 with slack: half the quantisation error bound
+  double morse_a;        // Morse stiffness (potential 2)
   float rl2f, lscf, Lf, pad3;
   int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
                          // (squared quantised units)

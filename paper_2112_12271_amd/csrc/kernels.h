@@ -1007,7 +1007,7 @@ __device__ inline double rsqrt_nr(double x) {
   return y;
 }
 
-__device__ inline void pair_f64(int pot, double eps, double r2, double sij, double& fc,
+__device__ inline void pair_f64(int pot, double eps, double ma, double r2, double sij, double& fc,
                                 double& u) {
   if (pot == 0) {  // WCA
     const double inv = recip(r2);
@@ -1015,6 +1015,12 @@ __device__ inline void pair_f64(int pot, double eps, double r2, double sij, doub
     const double s6 = s2 * s2 * s2;
     fc = 24.0 * eps * (2.0 * s6 * s6 - s6) * inv;
     u = 4.0 * eps * (s6 * s6 - s6) + eps;
+  } else if (pot == 2) {  // truncated, shifted Morse (Sec. II.A, eq. morsepot)
+    // with t = e^{-a(r - sigma)}: U = eps (t - 1)^2, -U'(r)/r = 2 a eps t (t - 1) / r
+    const double ir = rsqrt_nr(r2);  // 1/r
+    const double t = exp(-ma * (r2 * ir - sij));
+    fc = 2.0 * ma * eps * t * (t - 1.0) * ir;
+    u = eps * (t - 1.0) * (t - 1.0);
   } else {         // harmonic soft spheres
     const double ir = rsqrt_nr(r2);  // 1/r
     const double is = recip(sij);
@@ -1043,7 +1049,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
   const int npad = s->npad;
   const int len = min(gbl(s->nlen)[i], s->width);
   const HDMD_GLOBAL int* __restrict__ nl = gbl(s->nl);
-  const double L = s->L, c = s->cutoff, eps = s->eps, invL = 1.0 / L;
+  const double L = s->L, c = s->cutoff, eps = s->eps, invL = 1.0 / L, ma = s->morse_a;
   const int pot = s->potential;
   const double* __restrict__ xb = s->x[s->xcur];
   const int32_t* __restrict__ qb = MIX ? s->q[s->xcur] : nullptr;
@@ -1093,7 +1099,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         }
         if (r2 < rc * rc) {
           double fc, uu;
-          pair_f64(pot, eps, r2, sij, fc, uu);
+          pair_f64(pot, eps, ma, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
@@ -1120,7 +1126,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         }
         if (r2 < rc * rc) {
           double fc, uu;
-          pair_f64(pot, eps, r2, sij, fc, uu);
+          pair_f64(pot, eps, ma, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;

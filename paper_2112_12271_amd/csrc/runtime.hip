@@ -84,7 +84,10 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   if (!(s->skin >= 0) || !std::isfinite(s->skin)) return fail(HDMD_ERR_ARG, "skin must be >= 0");
   if (!(s->epsilon > 0) || !std::isfinite(s->epsilon)) return fail(HDMD_ERR_ARG, "epsilon must be > 0");
   if (!(s->sigma_max > 0) || !std::isfinite(s->sigma_max)) return fail(HDMD_ERR_ARG, "sigma_max must be > 0");
-  if (s->potential != HDMD_WCA && s->potential != HDMD_HARMONIC) return fail(HDMD_ERR_ARG, "bad potential");
+  if (s->potential != HDMD_WCA && s->potential != HDMD_HARMONIC && s->potential != HDMD_MORSE)
+    return fail(HDMD_ERR_ARG, "bad potential");
+  if (s->potential == HDMD_MORSE && !(s->morse_a > 0.0 && std::isfinite(s->morse_a)))
+    return fail(HDMD_ERR_ARG, "morse_a must be positive");
   if (s->precision != HDMD_FP64 && s->precision != HDMD_MIXED) return fail(HDMD_ERR_ARG, "bad precision");
   if (s->max_neighbors < 1 || s->max_neighbors > (1 << 20)) return fail(HDMD_ERR_ARG, "max_neighbors must be in [1, 2^20]");
   if (s->box_l < 2.0 * s->cutoff * s->sigma_max)
@@ -149,6 +152,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   std::memset(&h, 0, sizeof(h));
   h.d = p.d;
   h.potential = s->potential;
+  h.morse_a = s->potential == HDMD_MORSE ? s->morse_a : 0.0;
   h.precision = s->precision;
   h.n = p.n;
   h.npad = p.npad;

@@ -29,6 +29,8 @@ HDMD_ERR_HIP = -6
 HDMD_ERR_STATE = -7
 HDMD_WCA = 0
 HDMD_HARMONIC = 1
+HDMD_MORSE = 2
+MORSE_A = 30.0  # the paper's Morse stiffness (Sec. II.A)
 HDMD_FP64 = 0
 HDMD_MIXED = 1
 HDMD_SLOT_EMPTY = 0
@@ -47,7 +49,7 @@ class hdmd_system(C.Structure):
     _fields_ = [("d", C.c_int32), ("potential", C.c_int32), ("precision", C.c_int32),
                 ("max_neighbors", C.c_int32), ("n", C.c_int64), ("box_l", C.c_double),
                 ("cutoff", C.c_double), ("skin", C.c_double), ("epsilon", C.c_double),
-                ("sigma_max", C.c_double)]
+                ("sigma_max", C.c_double), ("morse_a", C.c_double)]
 
 
 class hdmd_fire_params(C.Structure):
@@ -159,10 +161,12 @@ class System:
     sigma_max: float = 1.0
     precision: int = HDMD_FP64
     max_neighbors: int = 64
+    morse_a: float = MORSE_A
 
     def c(self) -> hdmd_system:
         return hdmd_system(self.d, self.potential, self.precision, self.max_neighbors, self.n,
-                           self.box_l, self.cutoff, self.skin, self.epsilon, self.sigma_max)
+                           self.box_l, self.cutoff, self.skin, self.epsilon, self.sigma_max,
+                           self.morse_a)
 
 
 def hdmd_fire_defaults(dt0: float = 0.05, f_tol: float = 1e-10,

@@ -32,13 +32,16 @@ CASES = {H.HDMD_FP64: (1.0, 0.3), H.HDMD_MIXED: (1.2, 0.12)}
 
 
 @pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
-@pytest.mark.parametrize("pot,c", [(H.HDMD_WCA, C6), (H.HDMD_HARMONIC, 1.0)])
+@pytest.mark.parametrize("pot,c", [(H.HDMD_WCA, C6), (H.HDMD_HARMONIC, 1.0),
+                                   (H.HDMD_MORSE, 1.0)])
 @pytest.mark.parametrize("d,m,vac", [(2, 20, 0.0), (3, 9, 0.0), (4, 6, 0.0), (6, 4, 0.0),
                                      (8, 3, 0.3), (10, 3, 0.92)])
 def test_forces_match_oracle(orc, prec, pot, c, d, m, vac):
     a, jit = CASES[prec]
     if pot == H.HDMD_HARMONIC:
         a = 1.0
+    elif pot == H.HDMD_MORSE:   # a = 30: overlaps of up to ~0.3 sigma (U up to ~10^7 eps)
+        a, jit = (1.05, 0.12) if prec == H.HDMD_FP64 else (1.12, 0.05)
     x, sig, L = _liquid(d, m, a, jit, 10 * d + pot, vac)
     rp, cols = orc.nlist_cells(x, sig, L, c, 0.3)
     Fo, _, Eo = orc.forces(x, sig, L, pot, c, 1.0, rp, cols)

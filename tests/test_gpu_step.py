@@ -43,6 +43,27 @@ def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
     assert st.builds + 1 == bo          # the oracle counts the initial build too
 
 
+@pytest.mark.parametrize("prec,tol", [(H.HDMD_FP64, 1e-9), (H.HDMD_MIXED, 1e-4)])
+def test_morse_trajectory_matches_oracle(orc, prec, tol):
+    """The paper's truncated, shifted Morse potential (a = 30) at its step
+    dt = 0.0016 (Sec. II.A), d = 4, 200 steps from a barely overlapping start."""
+    x, L = inputs.jittered_lattice(4, 6, 1.12, 0.02, 41)
+    n = len(x)
+    sig = inputs.bidisperse(n, 1.0, 1.1, 41)
+    v = inputs.gaussian_velocities(n, 4, 0.5, 42)
+    nsteps, dt = 200, 0.0016
+    xo, vo, tho, _ = orc.vv(x, v, sig, L, orc.MORSE, 1.0, 0.3, 1.0, nsteps, dt)
+    sysd = H.System(d=4, n=n, box_l=L, potential=H.HDMD_MORSE, cutoff=1.0, skin=0.3,
+                    sigma_max=1.1, precision=prec)
+    xg, vg, thg, st = _run_gpu(sysd, x, v, sig, nsteps, dt)
+    dx = xg - xo
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < tol
+    etot_o = tho.sum(axis=1)
+    assert np.abs(thg[:, 3] - etot_o).max() < tol * max(1.0, abs(etot_o[0]))
+    assert st.steps_done == nsteps
+
+
 def test_mixed_precision_short_trajectory(orc):
     x, v, sig, L = _state(3, 8, 1.12, 5)
     nsteps, dt = 100, 0.004

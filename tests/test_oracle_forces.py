@@ -66,6 +66,41 @@ def test_harmonic_values(orc, d):
     assert E == 0.0 and np.all(F == 0.0)
 
 
+@pytest.mark.parametrize("a", [30.0, 7.5])
+@pytest.mark.parametrize("d", [3, 6])
+def test_morse_values(orc, d, a):
+    """Truncated, shifted Morse (Sec. II.A, eq. morsepot) with t = e^{-a(r - sigma)}:
+    U = eps (t - 1)^2 and |F| = 2 a eps t (t - 1).  At t = 2 (r = sigma - ln2/a):
+    U = eps, |F| = 4 a eps; at t = 3: U = 4 eps, |F| = 12 a eps; nothing at r >= sigma."""
+    orc.set_morse_a(a)
+    try:
+        g = np.random.default_rng(d)
+        u = g.normal(size=d)
+        u /= np.linalg.norm(u)
+        sig = np.array([1.0, 1.4])
+        sij = 1.2
+        L = 5.0
+        for t, U, f in [(2.0, 1.0, 4.0 * a), (3.0, 4.0, 12.0 * a)]:
+            x = _two(d, L, sij - math.log(t) / a, u)
+            F, e, E = _pair_energy_force(orc, x, sig, L, orc.MORSE, 1.0, eps=0.7)
+            assert E == pytest.approx(0.7 * U, rel=1e-12)
+            assert np.linalg.norm(F[0]) == pytest.approx(0.7 * f, rel=1e-11)
+            assert np.dot(F[0], u) > 0       # repulsive: atom 0 pushed away from atom 1
+            assert np.abs(F[0] + F[1]).max() < 1e-12 * np.abs(F).max()
+        x = _two(d, L, sij * (1 + 1e-12), u)
+        F, e, E = _pair_energy_force(orc, x, sig, L, orc.MORSE, 1.0)
+        assert E == 0.0 and np.all(F == 0.0)
+        # continuous at the cutoff: at r = sigma - delta, U ~ eps (a delta)^2 and
+        # |F| ~ 2 a^2 eps delta
+        delta = sij * 1e-9
+        x = _two(d, L, sij - delta, u)
+        F, e, E = _pair_energy_force(orc, x, sig, L, orc.MORSE, 1.0)
+        assert abs(E) < 1e-12
+        assert np.linalg.norm(F[0]) == pytest.approx(2 * a * a * delta, rel=1e-4)
+    finally:
+        orc.set_morse_a(orc.MORSE_A)
+
+
 @pytest.mark.parametrize("r_over", [0.9, 0.95, 1.0, 1.05, 1.1])
 def test_wca_equals_papers_mie_n6_shifted(orc, r_over):
     """Sec. II.A gives the Mie form eps[(s/r)^2n - 2 (s/r)^n], which for n = 6 has
@@ -88,7 +123,7 @@ def _liquid(d, m, a, jitter, seed, bidisp=True):
     return x, sig, L
 
 
-@pytest.mark.parametrize("pot,c", [(0, C6), (1, 1.0)])
+@pytest.mark.parametrize("pot,c", [(0, C6), (1, 1.0), (2, 1.0)])
 @pytest.mark.parametrize("d", [3, 4, 6])
 def test_force_is_minus_gradient(orc, pot, c, d):
     """Central differences of the total energy reproduce F to ~1e-7."""

@@ -7,20 +7,24 @@ from paper_2112_12271_amd import inputs
 C6 = 2.0 ** (1.0 / 6.0)
 
 
-def _fluid(d=3, m=5, a=1.12, seed=0, T=0.5):
-    x, L = inputs.jittered_lattice(d, m, a, 0.15, seed)
+def _fluid(d=3, m=5, a=1.12, seed=0, T=0.5, jitter=0.15):
+    x, L = inputs.jittered_lattice(d, m, a, jitter, seed)
     n = len(x)
     sig = inputs.bidisperse(n, 1.0, 1.1, seed)
     v = inputs.gaussian_velocities(n, d, T, seed + 1)
     return x, v, sig, L
 
 
-def test_vv_energy_error_scales_as_dt_squared(orc):
-    x, v, sig, L = _fluid()
-    tot = 1.0
+@pytest.mark.parametrize("pot,c,dts", [(0, C6, (0.004, 0.002)), (2, 1.0, (0.0032, 0.0016))])
+def test_vv_energy_error_scales_as_dt_squared(orc, pot, c, dts):
+    """Energy fluctuation of velocity Verlet ~ dt^2: WCA, and the Morse potential
+    (a = 30) at twice and at the paper's step dt = 6/(125 a) = 0.0016 (Sec. II.A),
+    from a barely overlapping start."""
+    x, v, sig, L = _fluid(jitter=0.15 if pot == 0 else 0.02)
+    tot = 1.0 if pot == 0 else 0.5
     fl = []
-    for dt in (0.004, 0.002):
-        _, _, th, _ = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, int(round(tot / dt)), dt)
+    for dt in dts:
+        _, _, th, _ = orc.vv(x, v, sig, L, pot, c, 0.3, 1.0, int(round(tot / dt)), dt)
         e = th.sum(axis=1)
         fl.append(np.sqrt(np.mean((e - e[0]) ** 2)))
     ratio = fl[0] / fl[1]
