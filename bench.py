@@ -63,6 +63,16 @@ def build_candidates(x: np.ndarray, L: float, nc: int) -> int:
     return int((occ * linked).sum())
 
 
+def workload_name(cfg) -> str:
+    if cfg.poly_R > 0:
+        mix = "polydisperse P(d,R=%g,sigma)" % cfg.poly_R
+    else:
+        mix = "50:50 sigma %.1f/%.1f" % (cfg.sig_a, cfg.sig_b)
+    pot = {0: "WCA", 1: "harmonic", 2: "Morse a=30"}[cfg.potential]
+    return "%s: d=%d N=%d %s %s phi=%.4g dt=%g skin=%g T=%g" % (
+        cfg.name, cfg.d, cfg.n, mix, pot, cfg.phi, cfg.dt, cfg.skin, cfg.T)
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for f in ("kernels.h", "hdmd_dev.h"):
@@ -99,7 +109,8 @@ def drift(th: np.ndarray, n: int, dt: float) -> tuple[float, float]:
 
 def run_md(H, torch, cfg, x0, v0, sig, L, prec, steps, warmup, every, profile):
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-    sysd = H.System(d=cfg.d, n=cfg.n, box_l=L, cutoff=cfg.cutoff, skin=cfg.skin,
+    sysd = H.System(d=cfg.d, n=cfg.n, box_l=L, potential=cfg.potential, cutoff=cfg.cutoff,
+                    skin=cfg.skin,
                     sigma_max=float(sig.max()), precision=prec, max_neighbors=64)
     X, V, SIG = dev(x0), dev(v0), dev(sig)
     sysd, _, _ = H.step_auto(sysd, X, V, SIG, max(warmup, 1), cfg.dt)   # warm-up (sizes the rows)
@@ -145,19 +156,23 @@ def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5):
     measured."""
     from oracle import oracle as O
     from paper_2112_12271_amd import inputs
-    sig = inputs.bidisperse(n, cfg.sig_a, cfg.sig_b, 77)
+    sig = (inputs.polydisperse(n, cfg.d, cfg.poly_R, 77) if cfg.poly_R > 0
+           else inputs.bidisperse(n, cfg.sig_a, cfg.sig_b, 77))
     L = inputs.box_for_packing(cfg.d, sig, cfg.phi)
     x = inputs.uniform_positions(n, cfg.d, L, 78)
     rlmax = cfg.cutoff * float(sig.max()) + cfg.skin
     O.lib()
-    assert O.ncell(L, rlmax) == 3
+    if O.ncell(L, rlmax) != 3:
+        log("cpu baseline skipped: the %d-atom sample of %s has %d subcells per axis, not 3"
+            % (n, cfg.name, O.ncell(L, rlmax)))
+        return None
     t0 = time.perf_counter()
     rp, cols = O.nlist_cells(x, sig, L, cfg.cutoff, cfg.skin)
     t_build = time.perf_counter() - t0
     log("cpu baseline: oracle list build of %d atoms in %.1f s" % (n, t_build))
     t0 = time.perf_counter()
     for _ in range(reps):
-        O.forces(x, sig, L, O.WCA, cfg.cutoff, 1.0, rp, cols)
+        O.forces(x, sig, L, cfg.potential, cfg.cutoff, 1.0, rp, cols)
     t_f = (time.perf_counter() - t0) / reps
     nc_full = O.ncell(cfg.box(cfg.diameters()), rlmax)
     cand_full = cfg.n * (3.0 / nc_full) ** cfg.d
@@ -416,9 +431,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded uniform positions relaxed by harmonic FIRE, Gaussian T=1)",
-        "config": {"workload": "%s: d=%d N=%d 50:50 WCA sigma %.1f/%.1f phi=%.2f dt=%g skin=%g T=%g"
-                               % (cfg.name, cfg.d, cfg.n, cfg.sig_a, cfg.sig_b, cfg.phi, cfg.dt,
-                                  cfg.skin, cfg.T),
+        "config": {"workload": workload_name(cfg),
                    "precision": "fp64", "timed_with_events": not args.no_profile},
         "roofline": roof,
         "roofline_build": roof_build,

@@ -13,6 +13,8 @@ public dataset):
 * ``c4`` 512 harmonic soft-sphere FIRE requests, d in {3,4,5,6},
   N log-uniform in [256, 8192], 50:50 sigma 1.0/1.4, phi near phi_J.
 * ``c5`` d=8, N=131072, monodisperse WCA, packing fraction 0.3 (n_cell = 2).
+* ``p6`` the paper's d=6 state point: N=10^5, polydisperse P(6, 6, sigma),
+  Morse a=30, phi = 0.1850, T = 0.25, dt = 0.0016.
 """
 from __future__ import annotations
 
@@ -50,6 +52,34 @@ def bidisperse(n: int, s_a: float, s_b: float, seed: int) -> np.ndarray:
     sig[: n // 2] = s_a
     rng(seed).shuffle(sig)
     return sig
+
+
+def polydisperse(n: int, d: int, R: float, seed: int) -> np.ndarray:
+    """Diameters drawn from the paper's distribution P(d, R, sigma) (Sec. II.A,
+    eq. sigmadist): density proportional to sigma^-d on [R^(-1/2d), R^(1/2d)],
+    R the ratio of the largest to the smallest particle volume, so that every
+    diameter interval of equal width holds the same particle volume.  Drawn by
+    inverting the cumulative distribution,
+    F(sigma) = (lo^(1-d) - sigma^(1-d)) / (lo^(1-d) - hi^(1-d))."""
+    lo, hi = R ** (-0.5 / d), R ** (0.5 / d)
+    u = rng(seed).uniform(size=n)
+    a, b = lo ** (1 - d), hi ** (1 - d)
+    return (a - u * (a - b)) ** (1.0 / (1 - d))
+
+
+def polydispersity_index(d: int, R: float) -> float:
+    """Delta = sqrt(<sigma^2> - <sigma>^2) / <sigma> of P(d, R, sigma), from its
+    moments in closed form: <sigma^k> = int sigma^(k-d) / int sigma^(-d) over
+    [R^(-1/2d), R^(1/2d)]."""
+    lo, hi = R ** (-0.5 / d), R ** (0.5 / d)
+
+    def mom(k: int) -> float:  # integral of sigma^(k-d) over [lo, hi]
+        e = k - d + 1
+        return math.log(hi / lo) if e == 0 else (hi ** e - lo ** e) / e
+
+    m0 = mom(0)
+    m1, m2 = mom(1) / m0, mom(2) / m0
+    return math.sqrt(m2 - m1 * m1) / m1
 
 
 def uniform_positions(n: int, d: int, L: float, seed: int) -> np.ndarray:
@@ -104,8 +134,12 @@ class MDConfig:
     T: float = 1.0
     cutoff: float = WCA_CUT
     seed: int = 0
+    potential: int = 0      # 0 WCA, 2 Morse (a = 30)
+    poly_R: float = 0.0     # > 0: diameters from P(d, R, sigma) with R = poly_R
 
     def diameters(self) -> np.ndarray:
+        if self.poly_R > 0:
+            return polydisperse(self.n, self.d, self.poly_R, self.seed + 1)
         if self.sig_a == self.sig_b:
             return np.full(self.n, self.sig_a)
         return bidisperse(self.n, self.sig_a, self.sig_b, self.seed + 1)
@@ -130,7 +164,12 @@ C5 = MDConfig("c5_d8_n131072", 8, 131072, 1.0, 1.0, 0.3, None, 0.002, 0.25, 5000
 # for the NVE part of the precision stress (at 0.3 the relaxed state keeps
 # ~100 overlaps per atom and WCA dynamics at dt = 0.002 diverge)
 C5_MD = MDConfig("c5md_d8_n131072", 8, 131072, 1.0, 1.0, 0.05, None, 0.002, 0.25, 5000, seed=5000)
-CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c5": C5, "c5md": C5_MD}
+# The paper's own d = 6 state point (Sec. IV, Table tab:phiefftab): N = 10^5,
+# diameters from P(6, R = 6, sigma), truncated and shifted Morse with a = 30,
+# phi = phi*_6 = 0.1850, k_B T = 0.25, dt = 0.0016; unit masses and one epsilon.
+P6 = MDConfig("p6_d6_n100000", 6, 100000, 6.0 ** (-1 / 12), 6.0 ** (1 / 12), 0.1850, None, 0.0016,
+              0.25, 10000, T=0.25, cutoff=1.0, seed=6000, potential=2, poly_R=6.0)
+CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c5": C5, "c5md": C5_MD, "p6": P6}
 
 
 @dataclasses.dataclass
