@@ -15,8 +15,10 @@ struct DKernels {
   // blk: workgroup size of the home-atom-lane build (64/128/256), or 1 for the
   // candidate-lane build (n_cell >= 3 only)
   void (*build)(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st);
-  void (*force)(bool mix, int lpa, const KArgs& a, int grid, int fire, hipStream_t st);
-  void (*step)(bool mix, int lpa, const KArgs& a, int grid, hipStream_t st);
+  // the force kernels serve the systems of one precision form (mix) and one
+  // potential class (morse: the Morse form; otherwise WCA and harmonic)
+  void (*force)(bool mix, int lpa, bool morse, const KArgs& a, int grid, int fire, hipStream_t st);
+  void (*step)(bool mix, int lpa, bool morse, const KArgs& a, int grid, hipStream_t st);
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
 };
 
@@ -27,8 +29,9 @@ const DKernels* dkernels(int d);
 void launch_bin_all(const KArgs& a, int grid, hipStream_t st);
 void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st);
 void launch_cellsort_all(const KArgs& a, int grid, hipStream_t st);
-void launch_force_all(const KArgs& a, int grid, int fire, hipStream_t st);
-// list build of the classes d <= kBuildAllMaxD; larger d keep per-class launches
+void launch_force_all(const KArgs& a, int grid, int fire, bool morse, hipStream_t st);
+// list build and FIRE forces of the classes d <= kBuildAllMaxD; larger d keep
+// per-class launches
 constexpr int kBuildAllMaxD = 8;
 void launch_build_all(const KArgs& a, int grid, hipStream_t st);
 

@@ -42,6 +42,7 @@ constexpr int kSortCap = 4096;  // subcell occupancy sorted in LDS (larger: in g
 constexpr int kPart = 8;        // doubles per wave in the partial-sum array
 constexpr int kMaxSlots = 1024;
 constexpr int kQCap = 16;       // per-lane prefilter queue of the build
+constexpr int kPotMorse = 2;     // hdmd_system.potential of the Morse form
 constexpr int kQScale = 250;    // int8 quantisation: subcell side = 250 units
 
 enum Mode : int32_t { MODE_NONE = 0, MODE_FIRE = 1, MODE_MD = 2, MODE_STATIC = 3 };

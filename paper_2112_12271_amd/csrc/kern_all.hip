@@ -9,6 +9,9 @@
 namespace hdmd {
 
 #define HDMD_EACH_D(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+// classes of the all-class list build and forces: the d = 9, 10 bodies need
+// more registers than four waves per SIMD allow, so those classes keep
+// launches of their own
 #define HDMD_BUILD_D(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 // The rebuild chain's kernels (binning, subcell sort, list build) run in
@@ -121,22 +124,24 @@ __global__ __launch_bounds__(256) void k_cellsort_all(KArgs a) {
   }
 }
 
+// FIRE forces of every class d <= kBuildAllMaxD (larger d: per-class launches)
+template <bool MORSE>
 __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
   __shared__ double sh[kPart];
   for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s)) continue;
+    if (!running(s) || (s->potential == kPotMorse) != MORSE) continue;
     if (fire && s->mode != MODE_FIRE) continue;
     const bool mix = s->precision != 0;
     switch (s->d) {
 #define HDMD_CASE(DD)                                           \
   case DD:                                                      \
-    if (mix) force_tile<DD, true, 1>(s, tile, fire, sh);        \
-    else force_tile<DD, false, 1>(s, tile, fire, sh);           \
+    if (mix) force_tile<DD, true, 1, MORSE>(s, tile, fire, sh); \
+    else force_tile<DD, false, 1, MORSE>(s, tile, fire, sh);    \
     break;
-      HDMD_EACH_D(HDMD_CASE)
+      HDMD_BUILD_D(HDMD_CASE)
 #undef HDMD_CASE
     }
   }
@@ -200,8 +205,9 @@ __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
 
 void launch_build_all(const KArgs& a, int grid, hipStream_t st) { k_build_all<<<grid, 256, 0, st>>>(a); }
 void launch_bin_all(const KArgs& a, int grid, hipStream_t st) { k_bin_all<<<grid, kTile, 0, st>>>(a); }
-void launch_force_all(const KArgs& a, int grid, int fire, hipStream_t st) {
-  k_force_all<<<grid, kTile, 0, st>>>(a, fire);
+void launch_force_all(const KArgs& a, int grid, int fire, bool morse, hipStream_t st) {
+  if (morse) k_force_all<true><<<grid, kTile, 0, st>>>(a, fire);
+  else k_force_all<false><<<grid, kTile, 0, st>>>(a, fire);
 }
 void launch_fire_update_all(const KArgs& a, int grid, hipStream_t st) {
   k_fire_update_all<<<grid, kTile, 0, st>>>(a);

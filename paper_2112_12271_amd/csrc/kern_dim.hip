@@ -43,16 +43,20 @@ void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
     else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);
   }
 }
-template <bool MIX, int LPA>
+template <bool MIX, int LPA, bool MORSE = false>
 void force_lpa(const KArgs& a, int grid, int fire, hipStream_t st) {
-  k_force<D, MIX, LPA><<<grid, kTile * LPA, 0, st>>>(a, fire);
+  k_force<D, MIX, LPA, MORSE><<<grid, kTile * LPA, 0, st>>>(a, fire);
 }
-template <bool MIX, int LPA>
+template <bool MIX, int LPA, bool MORSE = false>
 void step_lpa(const KArgs& a, int grid, hipStream_t st) {
-  k_step<D, MIX, LPA><<<grid, kTile * LPA, 0, st>>>(a);
+  k_step<D, MIX, LPA, MORSE><<<grid, kTile * LPA, 0, st>>>(a);
 }
-void l_force(bool mix, int lpa, const KArgs& a, int grid, int fire, hipStream_t st) {
-  if (mix) {
+// Morse systems run one lane per atom
+void l_force(bool mix, int lpa, bool morse, const KArgs& a, int grid, int fire, hipStream_t st) {
+  if (morse) {
+    if (mix) force_lpa<true, 1, true>(a, grid, fire, st);
+    else force_lpa<false, 1, true>(a, grid, fire, st);
+  } else if (mix) {
     if (lpa >= 4) force_lpa<true, 4>(a, grid, fire, st);
     else if (lpa == 2) force_lpa<true, 2>(a, grid, fire, st);
     else force_lpa<true, 1>(a, grid, fire, st);
@@ -62,8 +66,11 @@ void l_force(bool mix, int lpa, const KArgs& a, int grid, int fire, hipStream_t 
     else force_lpa<false, 1>(a, grid, fire, st);
   }
 }
-void l_step(bool mix, int lpa, const KArgs& a, int grid, hipStream_t st) {
-  if (mix) {
+void l_step(bool mix, int lpa, bool morse, const KArgs& a, int grid, hipStream_t st) {
+  if (morse) {
+    if (mix) step_lpa<true, 1, true>(a, grid, st);
+    else step_lpa<false, 1, true>(a, grid, st);
+  } else if (mix) {
     if (lpa >= 4) step_lpa<true, 4>(a, grid, st);
     else if (lpa == 2) step_lpa<true, 2>(a, grid, st);
     else step_lpa<true, 1>(a, grid, st);

@@ -1007,20 +1007,25 @@ __device__ inline double rsqrt_nr(double x) {
   return y;
 }
 
+// MORSE selects the truncated, shifted Morse form at compile time: its
+// exponential needs registers that would otherwise count against every force
+// loop (WCA and harmonic share the other instantiation, switched at run time).
+template <bool MORSE>
 __device__ inline void pair_f64(int pot, double eps, double ma, double r2, double sij, double& fc,
                                 double& u) {
-  if (pot == 0) {  // WCA
-    const double inv = recip(r2);
-    const double s2 = sij * sij * inv;
-    const double s6 = s2 * s2 * s2;
-    fc = 24.0 * eps * (2.0 * s6 * s6 - s6) * inv;
-    u = 4.0 * eps * (s6 * s6 - s6) + eps;
-  } else if (pot == 2) {  // truncated, shifted Morse (Sec. II.A, eq. morsepot)
+  if constexpr (MORSE) {  // truncated, shifted Morse (Sec. II.A, eq. morsepot)
     // with t = e^{-a(r - sigma)}: U = eps (t - 1)^2, -U'(r)/r = 2 a eps t (t - 1) / r
     const double ir = rsqrt_nr(r2);  // 1/r
     const double t = exp(-ma * (r2 * ir - sij));
     fc = 2.0 * ma * eps * t * (t - 1.0) * ir;
     u = eps * (t - 1.0) * (t - 1.0);
+    (void)pot;
+  } else if (pot == 0) {  // WCA
+    const double inv = recip(r2);
+    const double s2 = sij * sij * inv;
+    const double s6 = s2 * s2 * s2;
+    fc = 24.0 * eps * (2.0 * s6 * s6 - s6) * inv;
+    u = 4.0 * eps * (s6 * s6 - s6) + eps;
   } else {         // harmonic soft spheres
     const double ir = rsqrt_nr(r2);  // 1/r
     const double is = recip(sij);
@@ -1042,7 +1047,7 @@ struct Own {
 // k = sub, sub + LPA, ...; the next group's row indices are fetched before
 // the current group's records are used.  The LPA partial sums are combined
 // with the same butterfly on every lane of the group.
-template <int D, bool MIX, int LPA, typename FT>
+template <int D, bool MIX, int LPA, typename FT, bool MORSE>
 __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, MIX>& me,
                                   FT (&F)[D], double& e) {
   constexpr int U = MIX ? 4 : 2;
@@ -1099,7 +1104,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         }
         if (r2 < rc * rc) {
           double fc, uu;
-          pair_f64(pot, eps, ma, r2, sij, fc, uu);
+          pair_f64<MORSE>(pot, eps, ma, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
@@ -1126,7 +1131,7 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
         }
         if (r2 < rc * rc) {
           double fc, uu;
-          pair_f64(pot, eps, ma, r2, sij, fc, uu);
+          pair_f64<MORSE>(pot, eps, ma, r2, sij, fc, uu);
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
@@ -1198,7 +1203,13 @@ __device__ inline void tile_partials(double* dst, double (&vals)[kPart], double&
 // P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
 // One atom tile's forces (stored in s->f) with the tile's energy and, for
 // FIRE, the power P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
-template <int D, bool MIX, int LPA>
+// The force kernels serve the systems of one potential class: MORSE, or WCA
+// and harmonic (run-time switch); and of one precision form.
+__device__ inline bool kernel_serves(const SysDev* s, bool mix, bool morse) {
+  return (s->precision != 0) == mix && (s->potential == kPotMorse) == morse;
+}
+
+template <int D, bool MIX, int LPA, bool MORSE>
 __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
   typedef typename VType<MIX>::T FT;
   const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
@@ -1210,7 +1221,7 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
   load_own<D, MIX>(s, ii, me);
   FT F[D];
   double e;
-  force_part<D, MIX, LPA, FT>(s, ii, sub, me, F, e);
+  force_part<D, MIX, LPA, FT, MORSE>(s, ii, sub, me, F, e);
   double vals[kPart], mx = 0.0;
 #pragma unroll
   for (int p = 0; p < kPart; p++) vals[p] = 0.0;
@@ -1237,16 +1248,16 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
   tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh);
 }
 
-template <int D, bool MIX, int LPA>
+template <int D, bool MIX, int LPA, bool MORSE>
 __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
   __shared__ double sh[LPA * kPart];
   for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s)) continue;
+    if (!running(s) || !kernel_serves(s, MIX, MORSE)) continue;
     if (fire && s->mode != MODE_FIRE) continue;
-    force_tile<D, MIX, LPA>(s, tile, fire, sh);
+    force_tile<D, MIX, LPA, MORSE>(s, tile, fire, sh);
   }
 }
 
@@ -1256,7 +1267,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
 //   x^(n+1) = wrap(x^n + dt v^(n+1/2)) into the other record buffer;
 //   max_i |x^(n+1)_i - x_ref,i|^2 for the rebuild trigger (skin/2).
 // At the closing step (n == nsteps) only the second kick is applied.
-template <int D, bool MIX, int LPA>
+template <int D, bool MIX, int LPA, bool MORSE>
 __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
   typedef typename VType<MIX>::T VT;
   __shared__ double sh[LPA * kPart];
@@ -1265,7 +1276,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || s->mode != MODE_MD) continue;
+    if (!running(s) || s->mode != MODE_MD || !kernel_serves(s, MIX, MORSE)) continue;
     const int i = tile * kTile + slot;
     const int n = s->n, npad = s->npad, pc = s->pcur, cur = s->xcur;
     const bool vi = i < n;
@@ -1276,7 +1287,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     load_own<D, MIX>(s, ii, me);
     VT F[D];
     double e;
-    force_part<D, MIX, LPA, VT>(s, ii, sub, me, F, e);
+    force_part<D, MIX, LPA, VT, MORSE>(s, ii, sub, me, F, e);
     double vals[kPart], mx = 0.0;
 #pragma unroll
     for (int p = 0; p < kPart; p++) vals[p] = 0.0;

@@ -42,7 +42,7 @@ struct Plan {
   int d = 0, dr = 0, dq = 0, dy = 0;
   int n = 0, npad = 0, ncell = 0, radix = 0, ncells = 0, nstencil = 0, nchunks = 0;
   int ntiles = 0, nwaves = 0, width = 0;
-  bool wrap = false, mix = false;
+  bool wrap = false, mix = false, morse = false;
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
          off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_qc = 0, off_qc16 = 0,
@@ -109,6 +109,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.width = s->max_neighbors;
   p.wrap = p.ncell <= 2;
   p.mix = s->precision == HDMD_MIXED;
+  p.morse = s->potential == HDMD_MORSE;
   const size_t np = (size_t)p.npad, vsz = p.mix ? 4 : 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -404,12 +405,15 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
 // ---------------------------------------------------------------------------
 // graph cache (chunks of steps / iterations captured once per workspace)
 // ---------------------------------------------------------------------------
+// A captured chunk is valid for every system with the same key: the key holds
+// each input that selects a kernel or a grid (the workspace address fixes the
+// device descriptor the kernels read).
 struct GraphKey {
   void* ws;
-  int kind, chunk, d, mix, wrap, blk, ntiles, ncells, nchunks;
+  int kind, chunk, d, mix, morse, wrap, blk, ntiles, ncells, nchunks;
   bool operator<(const GraphKey& o) const {
-    return std::tie(ws, kind, chunk, d, mix, wrap, blk, ntiles, ncells, nchunks) <
-           std::tie(o.ws, o.kind, o.chunk, o.d, o.mix, o.wrap, o.blk, o.ntiles, o.ncells,
+    return std::tie(ws, kind, chunk, d, mix, morse, wrap, blk, ntiles, ncells, nchunks) <
+           std::tie(o.ws, o.kind, o.chunk, o.d, o.mix, o.morse, o.wrap, o.blk, o.ntiles, o.ncells,
                     o.nchunks);
   }
 };
@@ -427,7 +431,7 @@ typedef void (*EnqueueFn)(const Plan& p, SysDev* dev, hipStream_t st, int blk);
 static void enqueue_md_step(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
   const DKernels* K = dkernels(p.d);
   KArgs a = single_args(dev, p.d);
-  K->step(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, st);
+  K->step(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
 }
@@ -439,7 +443,7 @@ static void enqueue_fire_iter(const Plan& p, SysDev* dev, hipStream_t st, int bl
   K->fire_update(p.mix, a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
-  K->force(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, 1, st);
+  K->force(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, 1, st);
 }
 
 static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p, SysDev* dev,
@@ -449,7 +453,8 @@ static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p,
     HIPCHK(hipGetLastError());
     return HDMD_OK;
   }
-  GraphKey key{ws, kind, chunk, p.d, (int)p.mix, (int)p.wrap, blk, p.ntiles, p.ncells, p.nchunks};
+  GraphKey key{ws,      kind,  chunk, p.d,     (int)p.mix, (int)p.morse, (int)p.wrap,
+               blk,     p.ntiles, p.ncells, p.nchunks};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> g(g_graph_mu);
@@ -565,7 +570,7 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
   if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   const DKernels* K = dkernels(p.d);
-  K->force(p.mix, lpa_for(p.d, p.mix), single_args(dev, p.d), p.ntiles, 0, st);
+  K->force(p.mix, lpa_for(p.d, p.mix), p.morse, single_args(dev, p.d), p.ntiles, 0, st);
   launch_reduce_pe(dev, energy, st);
   K->unload(p.mix, dev, p.ntiles, st, nullptr, nullptr, force);
   HIPCHK(hipGetLastError());
@@ -623,7 +628,7 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
     for (auto& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     for (int64_t k = 0; k <= nsteps; k++) {
       HIPCHK(hipEventRecord(ev[4 * k], st));
-      K->step(p.mix, lpa_for(p.d, p.mix), a, p.ntiles, st);
+      K->step(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, st);
       HIPCHK(hipEventRecord(ev[4 * k + 1], st));
       K->bin(a, p.ntiles, st);
       launch_scan1(a, p.nchunks, st);
@@ -732,7 +737,7 @@ static int fire_start(const hdmd_system* sys, const Plan& p, const double* pos, 
   if (rc) return rc;
   set_fire(h, fp);
   launch_setdesc(dev, h, st);
-  dkernels(p.d)->force(p.mix, lpa_for(p.d, p.mix), single_args(dev, p.d), p.ntiles, 1, st);
+  dkernels(p.d)->force(p.mix, lpa_for(p.d, p.mix), p.morse, single_args(dev, p.d), p.ntiles, 1, st);
   HIPCHK(hipGetLastError());
   return HDMD_OK;
 }
@@ -810,6 +815,8 @@ struct HostBatch {
   int n_atom_all = 0, n_cell_all = 0, n_nowrap_all = 0;
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
        has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
+  // kernel kinds present per class, bit (mix | 2 morse): MD systems, FIRE systems
+  int kinds_md[kMaxD + 1] = {0}, kinds_fire[kMaxD + 1] = {0};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
 };
 
@@ -865,7 +872,10 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
   std::memset(B->n_cell, 0, sizeof(B->n_cell));
   std::memset(B->n_nowrap, 0, sizeof(B->n_nowrap));
   B->has_fire = B->has_md = false;
-  for (int d = 0; d <= kMaxD; d++) B->has_wrap[d] = B->has_nowrap[d] = B->mix[d] = false;
+  for (int d = 0; d <= kMaxD; d++) {
+    B->has_wrap[d] = B->has_nowrap[d] = B->mix[d] = false;
+    B->kinds_md[d] = B->kinds_fire[d] = 0;
+  }
   int64_t atom_base = 0, cell_base = 0;
   int64_t a_off[kMaxD + 1], c_off[kMaxD + 1];
   for (int d = kMinD; d <= kMaxD; d++) {
@@ -878,6 +888,9 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
       for (int k = 0; k < S.p.ntiles; k++) atom.push_back(make_int2(s, k));
       B->n_atom[d] += S.p.ntiles;
       if (S.p.mix) B->mix[d] = true;
+      const int kind = 1 << ((S.p.mix ? 1 : 0) | (S.p.morse ? 2 : 0));
+      if (S.mode == MODE_MD) B->kinds_md[d] |= kind;
+      else B->kinds_fire[d] |= kind;
       occ_tot += S.p.n;
       occ_n += S.p.ncells;
     }
@@ -991,7 +1004,9 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   }
   if (B->has_md)
     for (int d = kMinD; d <= kMaxD; d++)
-      if (B->n_atom[d]) dkernels(d)->step(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), st);
+      for (int k = 0; k < 4; k++)
+        if (B->kinds_md[d] >> k & 1)
+          dkernels(d)->step(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), st);
   launch_bin_all(a0, ga_all, st);
   launch_scan1(a0, gchunk, st);
   launch_scan2(a0, gsys, st);
@@ -1012,10 +1027,20 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   launch_finalize(a0, gsys, st);
   if (B->has_fire) {
     if (!std::getenv("HDMD_LPA")) {
-      launch_force_all(a0, ga_all, 1, st);  // one lane per atom in every class
+      // one lane per atom in every class; Morse systems in a launch of their own
+      int kinds = 0;
+      for (int d = kMinD; d <= kMaxD; d++) kinds |= B->kinds_fire[d];
+      if (kinds & 0x3) launch_force_all(a0, ga_all, 1, false, st);
+      if (kinds & 0xc) launch_force_all(a0, ga_all, 1, true, st);
+      for (int d = kBuildAllMaxD + 1; d <= kMaxD; d++)
+        for (int k = 0; k < 4; k++)
+          if (B->kinds_fire[d] >> k & 1)
+            dkernels(d)->force(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), 1, st);
     } else {
       for (int d = kMinD; d <= kMaxD; d++)
-        if (B->n_atom[d]) dkernels(d)->force(B->mix[d], lpa_for(d, B->mix[d]), batch_args(B, d), ga(d), 1, st);
+        for (int k = 0; k < 4; k++)
+          if (B->kinds_fire[d] >> k & 1)
+            dkernels(d)->force(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), 1, st);
     }
   }
 }
@@ -1145,7 +1170,7 @@ int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
     grids.push_back(B->n_atom[d] ? pow2_grid(B->n_atom[d], 4096) : 0);
     grids.push_back(B->n_cell[d] ? pow2_grid(B->n_cell[d], 8192) : 0);
     grids.push_back(B->blk[d] * 4 + (B->has_wrap[d] ? 2 : 0) + (B->has_nowrap[d] ? 1 : 0) +
-                    (B->mix[d] ? 1024 : 0));
+                    (B->mix[d] ? 1024 : 0) + (B->kinds_md[d] << 16) + (B->kinds_fire[d] << 20));
   }
   grids.push_back(B->has_fire ? 1 : 0);
   grids.push_back(B->has_md ? 1 : 0);

@@ -11,12 +11,21 @@ from tests.gpu_util import dev
 pytestmark = pytest.mark.gpu
 
 
-def _fire_case(d, n, phi, seed):
+def _fire_case(d, n, phi, seed, pot=H.HDMD_HARMONIC):
     sig = inputs.bidisperse(n, 1.0, 1.4, seed)
     L = inputs.box_for_packing(d, sig, phi)
     x = inputs.uniform_positions(n, d, L, seed + 1)
-    sysd = H.System(d=d, n=n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0, skin=0.25,
-                    sigma_max=1.4, max_neighbors=64)
+    if pot == H.HDMD_MORSE:
+        # the Morse minimisation starts from the harmonic jammed packing (the
+        # uniform start's deep overlaps would throw atoms many boxes per step)
+        X = dev(x)
+        sysh = H.System(d=d, n=n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0, skin=0.25,
+                        sigma_max=1.4, max_neighbors=64)
+        H.fire_auto(sysh, X, dev(sig), H.hdmd_fire_defaults(0.05, 1e-8, 2000))
+        x = X.cpu().numpy()
+    # a = 5: a Morse wall on the time scale of the other systems' FIRE step
+    sysd = H.System(d=d, n=n, box_l=L, potential=pot, cutoff=1.0, skin=0.25,
+                    sigma_max=1.4, max_neighbors=64, morse_a=5.0)
     sysd, _ = H.build_with_width(sysd, dev(x), dev(sig), slack=2.0)
     return sysd, x, sig
 
@@ -30,21 +39,24 @@ def _alone_fire(sysd, x, sig, params):
     return X.cpu().numpy(), res, sysf
 
 
+# the last two: a Morse system (its own force launch) and a d = 9 system (the
+# classes above 8 keep per-class build and force launches)
 CASES = [(3, 700, 0.62, 1), (4, 450, 0.44, 2), (5, 900, 0.3, 3), (6, 1300, 0.2, 4),
-         (3, 2500, 0.66, 5), (6, 600, 0.22, 6)]
+         (3, 2500, 0.66, 5), (6, 600, 0.22, 6), (4, 500, 0.48, 7, H.HDMD_MORSE),
+         (9, 3100, 0.02, 8)]
 
 
 @pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
 def test_fire_mix_equals_alone(prec):
     params = H.hdmd_fire_defaults(0.05, 1e-10 if prec == H.HDMD_FP64 else 1e-5, 3000)
     systems = []
-    for d, n, phi, seed in CASES:
-        sysd, x, sig = _fire_case(d, n, phi, seed)
+    for case in CASES:
+        sysd, x, sig = _fire_case(*case)
         sysd.precision = prec
         systems.append((sysd, x, sig))
     alone = [_alone_fire(s, x, sig, params) for s, x, sig in systems]
     systems = [(a[2], x, sig) for a, (s, x, sig) in zip(alone, systems)]
-    B = H.Batch(max_slots=8, max_atoms=20000, max_cells=200000)
+    B = H.Batch(max_slots=8, max_atoms=30000, max_cells=200000)
     keep = []
     for k, (s, x, sig) in enumerate(systems[:4]):
         ws = H.workspace(s)
@@ -82,23 +94,29 @@ def test_fire_mix_equals_alone(prec):
 
 
 def test_md_mix_equals_alone():
-    cases = [(3, 8, 1.12, 1), (4, 5, 1.1, 2), (6, 4, 1.05, 3)]
+    """Classes holding systems of both precision forms (d = 4) and of both
+    potential classes (d = 3) take one step launch per kind."""
+    W, M = H.HDMD_WCA, H.HDMD_MORSE
+    cases = [(3, 8, 1.12, 1, H.HDMD_FP64, W), (4, 5, 1.1, 2, H.HDMD_FP64, W),
+             (6, 4, 1.05, 3, H.HDMD_FP64, W), (4, 5, 1.12, 4, H.HDMD_MIXED, W),
+             (3, 8, 1.15, 5, H.HDMD_FP64, M)]
     nsteps, dt = 60, 0.003
     alone, states = [], []
-    for d, m, a, seed in cases:
-        x, L = inputs.jittered_lattice(d, m, a, 0.12 * a, seed)
+    for d, m, a, seed, prec, pot in cases:
+        x, L = inputs.jittered_lattice(d, m, a, (0.12 if pot == W else 0.02) * a, seed)
         n = len(x)
-        sig = inputs.bidisperse(n, 1.0, 1.2, seed)
-        v = inputs.gaussian_velocities(n, d, 1.0, seed + 1)
-        sysd = H.System(d=d, n=n, box_l=L, cutoff=inputs.WCA_CUT, skin=0.3, sigma_max=1.2,
-                        max_neighbors=64)
+        sig = inputs.bidisperse(n, 1.0, 1.2 if pot == W else 1.1, seed)
+        v = inputs.gaussian_velocities(n, d, 1.0 if pot == W else 0.25, seed + 1)
+        sysd = H.System(d=d, n=n, box_l=L, potential=pot,
+                        cutoff=inputs.WCA_CUT if pot == W else 1.0, skin=0.3, sigma_max=1.2,
+                        precision=prec, max_neighbors=64)
         sysd, _ = H.build_with_width(sysd, dev(x), dev(sig), slack=2.0)
         ws = H.workspace(sysd)
         X, V = dev(x), dev(v)
         H.hdmd_step(sysd, X, V, dev(sig), ws, nsteps, dt)
         alone.append((X.cpu().numpy(), V.cpu().numpy()))
         states.append((sysd, x, v, sig))
-    B = H.Batch(max_slots=4, max_atoms=10000, max_cells=100000)
+    B = H.Batch(max_slots=8, max_atoms=10000, max_cells=100000)
     for k, (s, x, v, sig) in enumerate(states):
         B.hdmd_batch_add_md(k, s, dev(x), dev(v), dev(sig), H.workspace(s), nsteps, dt)
     for _ in range(100):

@@ -75,3 +75,29 @@ def test_two_particles_separate():
     xg, res = _gpu_fire(sysd, x, sig, H.hdmd_fire_defaults(0.05, 1e-12, 10000))
     assert res.status == 0
     assert np.linalg.norm(xg[0] - xg[1]) >= 1.2 * (1 - 1e-10)
+
+
+def test_workspace_reused_across_potentials():
+    """One workspace serves a harmonic and then a Morse minimisation of the same
+    size: the Morse result equals the one on a fresh workspace (the captured
+    launch chunks are keyed by the force kernel's potential class)."""
+    d, n = 4, 500
+    sig = inputs.bidisperse(n, 1.0, 1.4, 11)
+    L = inputs.box_for_packing(d, sig, 0.48)
+    x = inputs.uniform_positions(n, d, L, 12)
+    kw = dict(d=d, n=n, box_l=L, cutoff=1.0, skin=0.25, sigma_max=1.4, max_neighbors=96)
+    sys_h = H.System(potential=H.HDMD_HARMONIC, **kw)
+    sys_m = H.System(potential=H.HDMD_MORSE, morse_a=5.0, **kw)
+    p = H.hdmd_fire_defaults(0.05, 1e-10, 300)
+    Xh = dev(x)
+    H.hdmd_fire_minimize(sys_h, Xh, dev(sig), H.workspace(sys_h), p)   # relaxed start
+    x0 = Xh.cpu().numpy()
+    ws = H.workspace(sys_m)
+    Xa = dev(x0)
+    H.hdmd_fire_minimize(sys_h, Xa, dev(sig), ws, p)                    # harmonic on ws
+    Xb, Xc = dev(x0), dev(x0)
+    rb = H.hdmd_fire_minimize(sys_m, Xb, dev(sig), ws, p)               # Morse on the same ws
+    rc = H.hdmd_fire_minimize(sys_m, Xc, dev(sig), H.workspace(sys_m), p)
+    assert rb.iterations == rc.iterations and rb.energy == rc.energy
+    assert np.array_equal(Xb.cpu().numpy(), Xc.cpu().numpy())
+    assert rb.energy > 0.0
