@@ -157,7 +157,10 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
  * displacement since the last build exceeds skin/2; F = F(x); v += dt/2 F.
  * pos and vel ([n][d] FP64, device) are read on entry and written on exit.
  * thermo (device, may be NULL) receives floor(nsteps/thermo_every)+1 rows of
- * (step, KE, PE, KE+PE) FP64 at steps 0, thermo_every, ...  Synchronises. */
+ * (step, KE, PE, KE+PE, W, Z) FP64 at steps 0, thermo_every, ...: W is the
+ * virial, the sum over pairs inside the cutoff of r_ij . F_ij (pressure
+ * P = (2 KE + W) / (d L^d)), and Z the mean number of neighbours inside the
+ * cutoff per atom (getthermo, Sec. II.E).  Synchronises. */
 int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
               size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
               hdmd_step_stats* stats, void* stream);

@@ -352,6 +352,31 @@ double orc_forces(int d, int64_t n, double L, const double* x, const double* sig
   return etot;
 }
 
+/* The virial and the coordination number of getthermo (Sec. II.E) from a
+ * full CSR list: out[0] = W = sum over pairs i<j inside the cutoff of
+ * r_ij . F_ij = fcoef r^2 (so that P = (2 KE + W) / (d V)); out[1] = Z, the
+ * mean number of neighbours inside the cutoff per atom. */
+void orc_virial(int d, int64_t n, double L, const double* x, const double* sig, int pot, double c,
+                double eps, const int64_t* row_ptr, const int32_t* cols, double* out) {
+  double w = 0.0, pairs = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    for (int64_t a = row_ptr[i]; a < row_ptr[i + 1]; a++) {
+      int64_t j = cols[a];
+      if (j <= i) continue;
+      double sij = 0.5 * (sig[i] + sig[j]);
+      double rc = c * sij;
+      double r2 = dist2(d, x + i * d, x + j * d, L);
+      if (!(r2 < rc * rc)) continue;
+      double fc;
+      pair(pot, r2, sij, eps, &fc);
+      w += fc * r2;
+      pairs += 1.0;
+    }
+  }
+  out[0] = w;
+  out[1] = 2.0 * pairs / (double)n;
+}
+
 /* Force on one atom by the definition (every other atom, ascending j). */
 double orc_force_one(int d, int64_t n, double L, const double* x, const double* sig, int pot,
                      double c, double eps, int64_t i, double* Fi) {

@@ -99,6 +99,9 @@ def lib():
         L.orc_forces.restype = C.c_double
         L.orc_forces.argtypes = [C.c_int, C.c_int64, C.c_double, _dp, _dp, C.c_int, C.c_double,
                                  C.c_double, _i64p, _i32p, _dp, _dp]
+        L.orc_virial.restype = None
+        L.orc_virial.argtypes = [C.c_int, C.c_int64, C.c_double, _dp, _dp, C.c_int, C.c_double,
+                                 C.c_double, _i64p, _i32p, _dp]
         L.orc_force_one.restype = C.c_double
         L.orc_force_one.argtypes = [C.c_int, C.c_int64, C.c_double, _dp, _dp, C.c_int,
                                     C.c_double, C.c_double, C.c_int64, _dp]
@@ -182,6 +185,16 @@ def forces(x, sig, L, pot, c, eps, rp, cols):
     E = lib().orc_forces(d, n, L, x, _f64(sig), pot, c, eps, np.ascontiguousarray(rp, np.int64),
                          np.ascontiguousarray(cols, np.int32), F, e)
     return F, e, E
+
+
+def virial(x, sig, L, pot, c, eps, rp, cols):
+    """(W, Z): sum over pairs of r_ij . F_ij, and mean neighbours inside the cutoff."""
+    x = _f64(x)
+    n, d = x.shape
+    out = np.zeros(2)
+    lib().orc_virial(d, n, L, x, _f64(sig), pot, c, eps, np.ascontiguousarray(rp, np.int64),
+                     np.ascontiguousarray(cols, np.int32), out)
+    return float(out[0]), float(out[1])
 
 
 def force_one(x, sig, L, pot, c, eps, i):

@@ -155,23 +155,29 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
     const bool rb = need_rebuild(s);
     if (s->mode == MODE_MD) {
       const int nw = s->nwaves, per = (nw + 255) / 256;
-      double pe = 0.0, ke = 0.0;
+      double pe = 0.0, ke = 0.0, vir = 0.0, nc = 0.0;
       for (int w = tid * per; w < min(nw, (tid + 1) * per); w++) {
         pe += s->part[(size_t)w * kPart + P_PE];
         ke += s->part[(size_t)w * kPart + P_KE];
+        vir += s->part[(size_t)w * kPart + P_VIR];
+        nc += s->part[(size_t)w * kPart + P_NC];
       }
       pe = block_sum<256>(pe, sh);
       ke = block_sum<256>(ke, sh);
+      vir = block_sum<256>(vir, sh);
+      nc = block_sum<256>(nc, sh);
       if (tid == 0) {
         s->pe = pe;
         s->ke = ke;
         if (!isfinite(pe + ke)) s->err |= ERR_RUN_NAN;
         if (s->thermo && s->thermo_every > 0 && s->step % s->thermo_every == 0) {
-          double* r = s->thermo + 4 * (s->step / s->thermo_every);
+          double* r = s->thermo + kThermoCols * (s->step / s->thermo_every);
           r[0] = (double)s->step;
           r[1] = ke;
           r[2] = pe;
           r[3] = ke + pe;
+          r[4] = vir;                 // sum over pairs of r_ij . F_ij
+          r[5] = nc / (double)s->n;   // mean neighbours inside the cutoff (Z)
         }
       }
     }

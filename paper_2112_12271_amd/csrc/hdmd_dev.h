@@ -40,6 +40,7 @@ constexpr int kWave = 64;
 constexpr int kChunk = 1024;    // subcells per scan chunk
 constexpr int kSortCap = 4096;  // subcell occupancy sorted in LDS (larger: in global memory)
 constexpr int kPart = 8;        // doubles per wave in the partial-sum array
+constexpr int kThermoCols = 6;  // step, KE, PE, KE+PE, virial W, coordination Z
 constexpr int kMaxSlots = 1024;
 constexpr int kQCap = 16;       // per-lane prefilter queue of the build
 constexpr int kPotMorse = 2;     // hdmd_system.potential of the Morse form
@@ -54,7 +55,9 @@ enum Err : int32_t {
   ERR_RUN_NAN = 8,    // non-finite energy during a run
 };
 // partial-sum record of one wave
-enum Part : int { P_PE = 0, P_KE = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_FMAX2 = 5 };
+// P_VIR: sum over the atom's row of fc r^2 / 2 (the pair virial r_ij . F_ij shared
+// between the two rows of a pair); P_NC: neighbours inside the interaction cutoff
+enum Part : int { P_PE = 0, P_KE = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_FMAX2 = 5, P_VIR = 6, P_NC = 7 };
 
 struct FireCtl {
   double dt0, dtmax, dtmin, finc, fdec, alpha0, falpha, ftol, etol;

@@ -1049,7 +1049,7 @@ struct Own {
 // with the same butterfly on every lane of the group.
 template <int D, bool MIX, int LPA, typename FT, bool MORSE>
 __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, MIX>& me,
-                                  FT (&F)[D], double& e) {
+                                  FT (&F)[D], double& e, double& w, double& z) {
   constexpr int U = MIX ? 4 : 2;
   const int npad = s->npad;
   const int len = min(gbl(s->nlen)[i], s->width);
@@ -1066,6 +1066,8 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
   for (int k = 0; k < D; k++) Fs[k] = 0.0;
   e = 0.0;
+  w = 0.0;
+  z = 0.0;
   // row entries are read unconditionally from a clamped (in-bounds) slot and
   // masked afterwards, so the loads issue without branches and the wait for
   // the current group does not also wait for the prefetched one
@@ -1108,6 +1110,8 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
+          w += 0.5 * fc * r2;
+          z += 1.0;
         }
       }
     } else {
@@ -1135,6 +1139,8 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
           for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
           e += 0.5 * uu;
+          w += 0.5 * fc * r2;
+          z += 1.0;
         }
       }
     }
@@ -1144,6 +1150,8 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
 #pragma unroll
     for (int k = 0; k < D; k++) Fs[k] += __shfl_xor(Fs[k], o, 64);
     e += __shfl_xor(e, o, 64);
+    w += __shfl_xor(w, o, 64);
+    z += __shfl_xor(z, o, 64);
   }
 #pragma unroll
   for (int k = 0; k < D; k++) F[k] = FT(Fs[k]);
@@ -1220,8 +1228,8 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
   Own<D, MIX> me;
   load_own<D, MIX>(s, ii, me);
   FT F[D];
-  double e;
-  force_part<D, MIX, LPA, FT, MORSE>(s, ii, sub, me, F, e);
+  double e, w, z;
+  force_part<D, MIX, LPA, FT, MORSE>(s, ii, sub, me, F, e, w, z);
   double vals[kPart], mx = 0.0;
 #pragma unroll
   for (int p = 0; p < kPart; p++) vals[p] = 0.0;
@@ -1240,6 +1248,8 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
       }
     }
     vals[P_PE] = e;
+    vals[P_VIR] = w;
+    vals[P_NC] = z;
     vals[P_FV] = fv;
     vals[P_FF] = ff;
     vals[P_VV] = vv;
@@ -1286,8 +1296,8 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     Own<D, MIX> me;
     load_own<D, MIX>(s, ii, me);
     VT F[D];
-    double e;
-    force_part<D, MIX, LPA, VT, MORSE>(s, ii, sub, me, F, e);
+    double e, w, z;
+    force_part<D, MIX, LPA, VT, MORSE>(s, ii, sub, me, F, e, w, z);
     double vals[kPart], mx = 0.0;
 #pragma unroll
     for (int p = 0; p < kPart; p++) vals[p] = 0.0;
@@ -1319,6 +1329,8 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
       if (MIX) store_q<D>(s->q[cur ^ 1], i, xn, me.sg, h, s->fxscale);
       vals[P_PE] = e;
       vals[P_KE] = 0.5 * ke;
+      vals[P_VIR] = w;
+      vals[P_NC] = z;
       mx = r2;
     }
     // the displacement maximum of the tile is reduced like the partial sums

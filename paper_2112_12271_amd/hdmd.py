@@ -243,10 +243,11 @@ def hdmd_forces(sys: System, pos, diam, ws, stream=None) -> tuple[torch.Tensor, 
 def hdmd_step(sys: System, pos, vel, diam, ws, nsteps: int, dt: float, thermo_every: int = 0,
               stream=None):
     """Runs nsteps of NVE velocity Verlet in place on pos/vel.
-    Returns (stats, thermo rows (k, 4) = (step, KE, PE, KE+PE) or None)."""
+    Returns (stats, thermo rows (k, 6) = (step, KE, PE, KE+PE, W, Z) or None), W the
+    virial sum over pairs of r_ij . F_ij and Z the mean neighbours inside the cutoff."""
     th = None
     if thermo_every > 0:
-        th = torch.zeros((nsteps // thermo_every + 1, 4), dtype=torch.float64, device=pos.device)
+        th = torch.zeros((nsteps // thermo_every + 1, 6), dtype=torch.float64, device=pos.device)
     st = hdmd_step_stats()
     rc = lib().hdmd_step(C.byref(sys.c()), _ptr(_dev_f64(pos, "pos")), _ptr(_dev_f64(vel, "vel")),
                          _ptr(_dev_f64(diam, "diam")), _ptr(ws), ws.numel(), nsteps, dt,

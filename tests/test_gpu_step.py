@@ -41,6 +41,12 @@ def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
     assert np.allclose(thg[:, 2], tho[:, 1], rtol=1e-10, atol=1e-12)
     assert st.steps_done == nsteps
     assert st.builds + 1 == bo          # the oracle counts the initial build too
+    # getthermo's virial and coordination number, at the first and the last step
+    for row, xs in ((0, x), (-1, xo)):
+        rp, cols = orc.nlist_brute(xs, sig, L, C6, skin)
+        W, Z = orc.virial(xs, sig, L, 0, C6, 1.0, rp, cols)
+        assert thg[row, 4] == pytest.approx(W, rel=1e-8)
+        assert thg[row, 5] == pytest.approx(Z, rel=1e-12)
 
 
 @pytest.mark.parametrize("prec,tol", [(H.HDMD_FP64, 1e-9), (H.HDMD_MIXED, 1e-4)])

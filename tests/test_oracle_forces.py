@@ -188,3 +188,42 @@ def test_translation_invariance(orc):
     F2, _, E2 = orc.forces(y, sig, L, 0, C6, 1.0, rp2, cols2)
     assert np.abs(F2 - F).max() <= 1e-10 * np.abs(F).max()
     assert E2 == pytest.approx(E, rel=1e-12)
+
+
+def test_virial_and_coordination_two_particles(orc):
+    """Harmonic pair at r = sigma/2: r.F = eps (1 - r/sigma) r/sigma = eps/4; the two
+    atoms are each other's only neighbour (Z = 1); beyond sigma both vanish."""
+    sig = np.array([1.0, 1.4])
+    L = 5.0
+    x = _two(3, L, 0.6, np.array([1.0, 0.0, 0.0]))
+    rp, cols = orc.nlist_brute(x, sig, L, 1.0, 0.3)
+    W, Z = orc.virial(x, sig, L, orc.HARMONIC, 1.0, 2.0, rp, cols)
+    assert W == pytest.approx(2.0 * 0.25, rel=1e-14) and Z == 1.0
+    x = _two(3, L, 1.2 * (1 + 1e-12), np.array([1.0, 0.0, 0.0]))
+    rp, cols = orc.nlist_brute(x, sig, L, 1.0, 0.3)
+    assert orc.virial(x, sig, L, orc.HARMONIC, 1.0, 2.0, rp, cols) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("pot,c", [(0, C6), (1, 1.0), (2, 1.0)])
+def test_virial_is_minus_the_scaling_derivative(orc, pot, c):
+    """Scaling every position and the box by lambda scales every pair distance:
+    dE/dlambda at lambda = 1 is sum over pairs of U'(r) r = -W (central
+    differences)."""
+    x, sig, L = _liquid(4, 4, 1.05, 0.25, 21)
+    rp, cols = orc.nlist_brute(x, sig, L, c, 0.4)
+    W, _ = orc.virial(x, sig, L, pot, c, 1.0, rp, cols)
+    h = 1e-6
+    Ep = orc.forces(x * (1 + h), sig, L * (1 + h), pot, c, 1.0, rp, cols)[2]
+    Em = orc.forces(x * (1 - h), sig, L * (1 - h), pot, c, 1.0, rp, cols)[2]
+    assert -(Ep - Em) / (2 * h) == pytest.approx(W, rel=1e-6)
+    assert W > 0.0
+
+
+def test_coordination_of_touching_lattice(orc):
+    """Simple cubic lattice of spacing 1 with diameters 1.05 (harmonic, cutoff 1):
+    exactly the 2d nearest neighbours overlap, so Z = 2d."""
+    for d in (3, 5):
+        x, L = inputs.jittered_lattice(d, 4, 1.0, 0.0, 0)
+        sig = np.full(len(x), 1.05)
+        rp, cols = orc.nlist_brute(x, sig, L, 1.0, 0.2)
+        assert orc.virial(x, sig, L, orc.HARMONIC, 1.0, 1.0, rp, cols)[1] == 2 * d
