@@ -152,15 +152,23 @@ int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_
 int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
                 size_t ws_bytes, double* force, double* energy, void* stream);
 
+#define HDMD_THERMO_COLS 10
+
 /* NVE velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B: per step
  * v += dt/2 F; x += dt v (wrapped); rebuild the list when the largest
  * displacement since the last build exceeds skin/2; F = F(x); v += dt/2 F.
  * pos and vel ([n][d] FP64, device) are read on entry and written on exit.
  * thermo (device, may be NULL) receives floor(nsteps/thermo_every)+1 rows of
- * (step, KE, PE, KE+PE, W, Z) FP64 at steps 0, thermo_every, ...: W is the
- * virial, the sum over pairs inside the cutoff of r_ij . F_ij (pressure
- * P = (2 KE + W) / (d L^d)), and Z the mean number of neighbours inside the
- * cutoff per atom (getthermo, Sec. II.E).  Synchronises. */
+ * HDMD_THERMO_COLS FP64 at steps 0, thermo_every, ...:
+ *   (step, KE, PE, KE+PE, W, Z, <|dr|^2>, <|dr|^4>, alpha_2, f_ov)
+ * W is the virial, the sum over pairs inside the cutoff of r_ij . F_ij
+ * (pressure P = (2 KE + W) / (d L^d)), and Z the mean number of neighbours
+ * inside the cutoff per atom (getthermo, Sec. II.E).  dr is each atom's
+ * unwrapped displacement since the call's step 0 (the reference state of
+ * the displacement observables, Sec. II.E): its second and fourth moments,
+ * the non-Gaussian parameter alpha_2 = d <|dr|^4> / ((d+2) <|dr|^2>^2) - 1
+ * (eq. ngp; 0 at step 0) and the overlap f_ov, the fraction of atoms with
+ * |dr| < 0.1 d (eq. fov, sigma~ = 1).  Synchronises. */
 int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
               size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
               hdmd_step_stats* stats, void* stream);

@@ -443,34 +443,69 @@ static double kinetic(int64_t m, const double* v) {
   return 0.5 * ke;
 }
 
+/* Displacement observables of Sec. II.E over the unwrapped displacements
+ * dr[n*d] of every atom since the reference state:
+ *   out[0] = <|dr|^2>, out[1] = <|dr|^4>  (averages over the n atoms),
+ *   out[2] = alpha_2 = d <|dr|^4> / ((d+2) <|dr|^2>^2) - 1   (eq. ngp),
+ *   out[3] = f_ov = (1/n) sum_i Theta(0.1 d - |dr_i|)        (eq. fov),
+ * with the diameter scale sigma~ = 1 (Sec. II.A) and Theta(0) = 0.  Reading:
+ * alpha_2 is undefined while nothing has moved; it is reported as 0. */
+void orc_disp_moments(int d, int64_t n, const double* dr, double* out) {
+  double m2 = 0.0, m4 = 0.0, ov = 0.0;
+  const double a = 0.1 * d;
+  for (int64_t i = 0; i < n; i++) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; k++) r2 += dr[i * d + k] * dr[i * d + k];
+    m2 += r2;
+    m4 += r2 * r2;
+    if (sqrt(r2) < a) ov += 1.0;
+  }
+  m2 /= (double)n;
+  m4 /= (double)n;
+  out[0] = m2;
+  out[1] = m4;
+  out[2] = m2 > 0.0 ? d * m4 / ((d + 2) * m2 * m2) - 1.0 : 0.0;
+  out[3] = ov / (double)n;
+}
+
 /* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B with unit masses
  * and no thermostat (NVE): per step v += dt/2 F; x += dt v; wrap; rebuild if
  * needed; F = F(x); v += dt/2 F.  The first list is built at step 0.
- * thermo (optional) receives nsteps+1 rows of (KE, PE) at the full steps.
- * Returns the number of list builds. */
+ * thermo (optional) receives nsteps+1 rows of (KE, PE) at the full steps;
+ * obs (optional) nsteps+1 rows of orc_disp_moments of the unwrapped
+ * displacement since step 0, which advances by dt v with every drift (the
+ * wrap only relabels the image).  Returns the number of list builds. */
 int64_t orc_vv(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
-               double* v, const double* sig, int64_t nsteps, double dt, double* thermo) {
+               double* v, const double* sig, int64_t nsteps, double dt, double* thermo,
+               double* obs) {
   orc_sys S = {d, n, L, pot, c, s, eps};
   int64_t m = n * d;
   orc_nlstate st = {0};
   st.xref = (double*)malloc((size_t)m * sizeof(double));
   double* F = (double*)malloc((size_t)m * sizeof(double));
+  double* dr = (double*)calloc((size_t)m, sizeof(double));
   for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a], L);
   rebuild(&S, x, sig, &st);
   double pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
   if (thermo) { thermo[0] = kinetic(m, v); thermo[1] = pe; }
+  if (obs) orc_disp_moments(d, n, dr, obs);
   for (int64_t t = 1; t <= nsteps; t++) {
     for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
-    for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a] + dt * v[a], L);
+    for (int64_t a = 0; a < m; a++) {
+      x[a] = orc_wrap1(x[a] + dt * v[a], L);
+      dr[a] += dt * v[a];
+    }
     if (needs_rebuild(&S, x, &st)) rebuild(&S, x, sig, &st);
     pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
     for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
     if (thermo) { thermo[2 * t] = kinetic(m, v); thermo[2 * t + 1] = pe; }
+    if (obs) orc_disp_moments(d, n, dr, obs + 4 * t);
   }
   int64_t b = st.builds;
   orc_list_free(st.nl);
   free(st.xref);
   free(F);
+  free(dr);
   return b;
 }
 

@@ -107,7 +107,10 @@ def lib():
                                     C.c_double, C.c_double, C.c_int64, _dp]
         L.orc_vv.restype = C.c_int64
         L.orc_vv.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
-                             C.c_double, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_void_p]
+                             C.c_double, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_void_p,
+                             C.c_void_p]
+        L.orc_disp_moments.restype = None
+        L.orc_disp_moments.argtypes = [C.c_int, C.c_int64, _dp, _dp]
         L.orc_fire.restype = None
         L.orc_fire.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
                                C.c_double, _dp, _dp, C.POINTER(FireParams),
@@ -205,15 +208,29 @@ def force_one(x, sig, L, pot, c, eps, i):
     return Fi, ei
 
 
-def vv(x, v, sig, L, pot, c, s, eps, nsteps, dt):
-    """Run NVE velocity Verlet; returns (x, v, thermo[nsteps+1, 2] = (KE, PE), builds)."""
+def vv(x, v, sig, L, pot, c, s, eps, nsteps, dt, obs=False):
+    """Run NVE velocity Verlet; returns (x, v, thermo[nsteps+1, 2] = (KE, PE), builds)
+    and, with obs, also the displacement observables [nsteps+1, 4] =
+    (<|dr|^2>, <|dr|^4>, alpha_2, f_ov) since step 0 (Sec. II.E)."""
     x = _f64(x).copy()
     v = _f64(v).copy()
     n, d = x.shape
     th = np.zeros((nsteps + 1, 2))
+    ob = np.zeros((nsteps + 1, 4)) if obs else None
     b = lib().orc_vv(d, n, L, pot, c, s, eps, x, v, _f64(sig), nsteps, dt,
-                     th.ctypes.data_as(C.c_void_p))
-    return x, v, th, b
+                     th.ctypes.data_as(C.c_void_p),
+                     ob.ctypes.data_as(C.c_void_p) if obs else None)
+    return (x, v, th, b, ob) if obs else (x, v, th, b)
+
+
+def disp_moments(dr):
+    """(<|dr|^2>, <|dr|^4>, alpha_2, f_ov) of unwrapped displacements dr[n, d]
+    (Sec. II.E, eqs. ngp and fov)."""
+    dr = _f64(dr)
+    n, d = dr.shape
+    out = np.zeros(4)
+    lib().orc_disp_moments(d, n, dr, out)
+    return out
 
 
 def fire(x, sig, L, pot, c, s, eps, params: FireParams):

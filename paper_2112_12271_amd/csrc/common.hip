@@ -155,22 +155,34 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
     const bool rb = need_rebuild(s);
     if (s->mode == MODE_MD) {
       const int nw = s->nwaves, per = (nw + 255) / 256;
-      double pe = 0.0, ke = 0.0, vir = 0.0, nc = 0.0;
+      const bool rec = s->thermo && s->thermo_every > 0 && s->step % s->thermo_every == 0;
+      double pe = 0.0, ke = 0.0, vir = 0.0, nc = 0.0, m2 = 0.0, m4 = 0.0, ov = 0.0;
       for (int w = tid * per; w < min(nw, (tid + 1) * per); w++) {
-        pe += s->part[(size_t)w * kPart + P_PE];
-        ke += s->part[(size_t)w * kPart + P_KE];
-        vir += s->part[(size_t)w * kPart + P_VIR];
-        nc += s->part[(size_t)w * kPart + P_NC];
+        const double* pw = s->part + (size_t)w * kPart;
+        pe += pw[P_PE];
+        ke += pw[P_KE];
+        vir += pw[P_VIR];
+        nc += pw[P_NC];
+        if (rec) {
+          m2 += pw[P_M2];
+          m4 += pw[P_M4];
+          ov += pw[P_OV];
+        }
       }
       pe = block_sum<256>(pe, sh);
       ke = block_sum<256>(ke, sh);
       vir = block_sum<256>(vir, sh);
       nc = block_sum<256>(nc, sh);
+      if (rec) {
+        m2 = block_sum<256>(m2, sh);
+        m4 = block_sum<256>(m4, sh);
+        ov = block_sum<256>(ov, sh);
+      }
       if (tid == 0) {
         s->pe = pe;
         s->ke = ke;
         if (!isfinite(pe + ke)) s->err |= ERR_RUN_NAN;
-        if (s->thermo && s->thermo_every > 0 && s->step % s->thermo_every == 0) {
+        if (rec) {
           double* r = s->thermo + kThermoCols * (s->step / s->thermo_every);
           r[0] = (double)s->step;
           r[1] = ke;
@@ -178,6 +190,13 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
           r[3] = ke + pe;
           r[4] = vir;                 // sum over pairs of r_ij . F_ij
           r[5] = nc / (double)s->n;   // mean neighbours inside the cutoff (Z)
+          // displacement moments since the run's start, alpha_2 (eq. ngp; 0
+          // while nothing has moved) and f_ov (eq. fov)
+          const double msd = m2 / (double)s->n, mqd = m4 / (double)s->n;
+          r[6] = msd;
+          r[7] = mqd;
+          r[8] = msd > 0.0 ? s->d * mqd / ((s->d + 2) * msd * msd) - 1.0 : 0.0;
+          r[9] = ov / (double)s->n;
         }
       }
     }

@@ -39,8 +39,10 @@ constexpr int kTile = 64;       // atoms per atom tile (one wave at one lane per
 constexpr int kWave = 64;
 constexpr int kChunk = 1024;    // subcells per scan chunk
 constexpr int kSortCap = 4096;  // subcell occupancy sorted in LDS (larger: in global memory)
-constexpr int kPart = 8;        // doubles per wave in the partial-sum array
-constexpr int kThermoCols = 6;  // step, KE, PE, KE+PE, virial W, coordination Z
+constexpr int kPart = 11;       // doubles per wave in the partial-sum array
+// step, KE, PE, KE+PE, virial W, coordination Z, <|Delta|^2>, <|Delta|^4>,
+// non-Gaussian alpha_2, overlap f_ov
+constexpr int kThermoCols = 10;
 constexpr int kMaxSlots = 1024;
 constexpr int kQCap = 16;       // per-lane prefilter queue of the build
 constexpr int kPotMorse = 2;     // hdmd_system.potential of the Morse form
@@ -57,7 +59,12 @@ enum Err : int32_t {
 // partial-sum record of one wave
 // P_VIR: sum over the atom's row of fc r^2 / 2 (the pair virial r_ij . F_ij shared
 // between the two rows of a pair); P_NC: neighbours inside the interaction cutoff
-enum Part : int { P_PE = 0, P_KE = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_FMAX2 = 5, P_VIR = 6, P_NC = 7 };
+// P_M2, P_M4: |Delta|^2 and |Delta|^4 of the unwrapped displacement since the
+// run's start; P_OV: atoms with |Delta| < 0.1 d (thermo steps only)
+enum Part : int {
+  P_PE = 0, P_KE = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_FMAX2 = 5, P_VIR = 6, P_NC = 7,
+  P_M2 = 8, P_M4 = 9, P_OV = 10
+};
 
 struct FireCtl {
   double dt0, dtmax, dtmin, finc, fdec, alpha0, falpha, ftol, etol;
@@ -85,6 +92,8 @@ struct SysDev {
   int32_t* oid[2];
   void* f;
   double* xref;
+  double* disp[2];  // unwrapped displacement since the run's start up to the
+                    // last build, [d][npad] (MD; permuted with the atoms)
   float* ycell;
   int32_t* qc;
   int32_t* qc16;  // int16 offsets or wrapped 16-bit coordinates, [npad][8];

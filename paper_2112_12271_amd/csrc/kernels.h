@@ -123,6 +123,16 @@ __device__ inline void bin_tile(SysDev* s, int tile) {
   if (i >= s->n) return;
   double x[D];
   load_x<D>(s->x[s->xcur ^ 1], i, x);
+  if (s->mode == MODE_MD) {
+    // fold the displacement since the last build into the unwrapped
+    // displacement (it stays below L/2 between builds, so the minimum image
+    // is the true one)
+    double* dp = s->disp[s->pcur];
+    const size_t np = s->npad;
+#pragma unroll
+    for (int k = 0; k < D; k++)
+      dp[k * np + i] += min_image(x[k] - s->xref[k * np + i], s->L, s->hL);
+  }
   int c = flat_cell<D>(s, x);
   s->cell_of[i] = c;
   s->rank[i] = atomicAdd(&s->cell_count[c], 1);
@@ -224,6 +234,9 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
   const bool wrap = s->wrap != 0;
   const VT* vin = reinterpret_cast<const VT*>(s->v[pc]);
   VT* vout = reinterpret_cast<VT*>(s->v[pn]);
+  const bool md = s->mode == MODE_MD;
+  const double* din = s->disp[pc];
+  double* dout = s->disp[pn];
   for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
     const int src = vals[q], dst = s0 + q;
     double x[D], sg;
@@ -234,6 +247,7 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
     for (int k = 0; k < D; k++) {
       s->xref[(size_t)k * npad + dst] = x[k];
       vout[(size_t)k * npad + dst] = vin[(size_t)k * npad + src];
+      if (md) dout[(size_t)k * npad + dst] = din[(size_t)k * npad + src];
     }
     if (wrap) {
       float y[DY];
@@ -1175,29 +1189,41 @@ struct VType<true> {
   typedef float T;
 };
 
-// Per-tile partial sums: each wave reduces its lanes, then (LPA > 1) thread
-// 0 adds the waves of the tile in order (deterministic for a given LPA).
+// Per-tile partial sums of the slots in `use` (a bit per Part; the others
+// are left as they are and read by nobody): each wave reduces its lanes, then
+// (LPA > 1) thread 0 adds the waves of the tile in order (deterministic for a
+// given LPA).  `use` is uniform over the block.
+constexpr unsigned kUseForce = (1u << P_PE) | (1u << P_FV) | (1u << P_FF) | (1u << P_VV) |
+                               (1u << P_FMAX2);
+constexpr unsigned kUseStep = (1u << P_PE) | (1u << P_KE) | (1u << P_FMAX2) | (1u << P_VIR) |
+                              (1u << P_NC);
+constexpr unsigned kUseDisp = (1u << P_M2) | (1u << P_M4) | (1u << P_OV);
+
 template <int LPA>
 __device__ inline void tile_partials(double* dst, double (&vals)[kPart], double& maxv,
-                                     double* sh) {
+                                     double* sh, unsigned use) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int p = 0; p < kPart; p++) vals[p] = wave_sum(vals[p]);
+  for (int p = 0; p < kPart; p++)
+    if (p != P_FMAX2 && (use >> p & 1u)) vals[p] = wave_sum(vals[p]);
   maxv = wave_max(maxv);
   if (LPA == 1) {
     if (lane == 0) {
 #pragma unroll
-      for (int p = 0; p < kPart; p++) dst[p] = p == P_FMAX2 ? maxv : vals[p];
+      for (int p = 0; p < kPart; p++)
+        if (use >> p & 1u) dst[p] = p == P_FMAX2 ? maxv : vals[p];
     }
     return;
   }
   if (lane == 0) {
 #pragma unroll
-    for (int p = 0; p < kPart; p++) sh[w * kPart + p] = p == P_FMAX2 ? maxv : vals[p];
+    for (int p = 0; p < kPart; p++)
+      if (use >> p & 1u) sh[w * kPart + p] = p == P_FMAX2 ? maxv : vals[p];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int p = 0; p < kPart; p++) {
+      if (!(use >> p & 1u)) continue;
       double acc = sh[p];
       for (int ww = 1; ww < LPA; ww++)
         acc = p == P_FMAX2 ? fmax(acc, sh[ww * kPart + p]) : acc + sh[ww * kPart + p];
@@ -1248,14 +1274,12 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
       }
     }
     vals[P_PE] = e;
-    vals[P_VIR] = w;
-    vals[P_NC] = z;
     vals[P_FV] = fv;
     vals[P_FF] = ff;
     vals[P_VV] = vv;
     mx = ff;
   }
-  tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh);
+  tile_partials<LPA>(s->part + (size_t)tile * kPart, vals, mx, sh, kUseForce);
 }
 
 template <int D, bool MIX, int LPA, bool MORSE>
@@ -1277,6 +1301,10 @@ __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
 //   x^(n+1) = wrap(x^n + dt v^(n+1/2)) into the other record buffer;
 //   max_i |x^(n+1)_i - x_ref,i|^2 for the rebuild trigger (skin/2).
 // At the closing step (n == nsteps) only the second kick is applied.
+// On steps that record a thermo row, the unwrapped displacement since the
+// run's start, Delta_i = disp_i + (x^n_i - x_ref,i), gives |Delta|^2,
+// |Delta|^4 and the overlap term Theta(0.1 d - |Delta|) (Sec. II.E, eqs. ngp
+// and fov); disp_i is advanced at each rebuild, so other steps read nothing.
 template <int D, bool MIX, int LPA, bool MORSE>
 __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
   typedef typename VType<MIX>::T VT;
@@ -1292,6 +1320,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     const bool vi = i < n;
     const int ii = vi ? i : 0;
     const bool first = s->step == 0, close = s->step >= s->nsteps;
+    const bool rec = s->thermo && s->thermo_every > 0 && s->step % s->thermo_every == 0;
     const double dt = s->dt, hdt = 0.5 * dt;
     Own<D, MIX> me;
     load_own<D, MIX>(s, ii, me);
@@ -1312,7 +1341,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
         ke += (double)vk[k] * (double)vk[k];
       }
       const double L = s->L, h = s->hL;
-      double r2 = 0.0;
+      double r2 = 0.0, m2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         if (!close) {
@@ -1322,8 +1351,13 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
           xn[k] = me.x[k];
         }
         v[(size_t)k * npad + i] = vk[k];
-        const double dx = min_image(xn[k] - s->xref[(size_t)k * npad + i], L, h);
+        const double xr = s->xref[(size_t)k * npad + i];
+        const double dx = min_image(xn[k] - xr, L, h);
         r2 = __builtin_fma(dx, dx, r2);
+        if (rec) {
+          const double dd = s->disp[pc][(size_t)k * npad + i] + min_image(me.x[k] - xr, L, h);
+          m2 = __builtin_fma(dd, dd, m2);
+        }
       }
       store_rec<D>(s->x[cur ^ 1], i, xn, me.sg);
       if (MIX) store_q<D>(s->q[cur ^ 1], i, xn, me.sg, h, s->fxscale);
@@ -1331,11 +1365,14 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
       vals[P_KE] = 0.5 * ke;
       vals[P_VIR] = w;
       vals[P_NC] = z;
+      vals[P_M2] = m2;
+      vals[P_M4] = m2 * m2;
+      vals[P_OV] = rec && m2 < 0.01 * D * D ? 1.0 : 0.0;
       mx = r2;
     }
     // the displacement maximum of the tile is reduced like the partial sums
     double* pt = s->part + (size_t)tile * kPart;
-    tile_partials<LPA>(pt, vals, mx, sh);
+    tile_partials<LPA>(pt, vals, mx, sh, kUseStep | kUseDisp);
     if (threadIdx.x == 0 && pt[P_FMAX2] > 0.0)
       atomicMax(&s->maxdisp2, (unsigned long long)__double_as_longlong(pt[P_FMAX2]));
   }

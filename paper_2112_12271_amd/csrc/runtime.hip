@@ -20,6 +20,8 @@
 
 namespace hdmd {
 
+static_assert(kThermoCols == HDMD_THERMO_COLS, "thermo row layout");
+
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string& msg) {
@@ -45,7 +47,7 @@ struct Plan {
   bool wrap = false, mix = false, morse = false;
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
-         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_ycell = 0, off_qc = 0, off_qc16 = 0,
+         off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_disp[2] = {0, 0}, off_ycell = 0, off_qc = 0, off_qc16 = 0,
          off_cell_of = 0,
          off_rank = 0, off_cell_count = 0, off_cell_flat = 0, off_cell_local = 0, off_chunk_sum = 0,
          off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0;
@@ -124,6 +126,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   for (int b = 0; b < 2; b++) p.off_oid[b] = take(np * 4);
   p.off_f = take(np * p.d * vsz);
   p.off_xref = take(np * p.d * 8);
+  for (int b = 0; b < 2; b++) p.off_disp[b] = take(np * p.d * 8);
   p.off_ycell = take(p.wrap ? np * p.dy * 4 : 0);
   p.off_qc = take(p.wrap ? 0 : np * 16);
   p.off_qc16 = take(np * 32);
@@ -217,6 +220,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   }
   h.f = at<void>(ws, p.off_f);
   h.xref = at<double>(ws, p.off_xref);
+  for (int b = 0; b < 2; b++) h.disp[b] = at<double>(ws, p.off_disp[b]);
   h.ycell = p.wrap ? at<float>(ws, p.off_ycell) : nullptr;
   h.qc = p.wrap ? nullptr : at<int32_t>(ws, p.off_qc);
   h.qc16 = at<int32_t>(ws, p.off_qc16);  // int16 offsets, or wrapped 16-bit coordinates
@@ -354,6 +358,9 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
   SysDev h = make_desc(sys, p, ws);
   launch_setdesc(dev, h, st);
   launch_fill_i32(h.cell_count, p.ncells, 0, st);
+  // displacements start at zero (both buffers; the first build permutes them)
+  launch_fill_i32(reinterpret_cast<int32_t*>(h.disp[0]), (int64_t)p.npad * p.d * 2, 0, st);
+  launch_fill_i32(reinterpret_cast<int32_t*>(h.disp[1]), (int64_t)p.npad * p.d * 2, 0, st);
   const DKernels* K = dkernels(p.d);
   K->load(p.mix, dev, p.ntiles, st, pos, diam, vel);
   bool known = false;

@@ -36,6 +36,7 @@ HDMD_MIXED = 1
 HDMD_SLOT_EMPTY = 0
 HDMD_SLOT_RUNNING = 1
 HDMD_SLOT_DONE = 2
+THERMO_COLS = 10  # columns of a thermo row of hdmd_step
 WCA_CUT = 2.0 ** (1.0 / 6.0)
 
 
@@ -243,11 +244,14 @@ def hdmd_forces(sys: System, pos, diam, ws, stream=None) -> tuple[torch.Tensor, 
 def hdmd_step(sys: System, pos, vel, diam, ws, nsteps: int, dt: float, thermo_every: int = 0,
               stream=None):
     """Runs nsteps of NVE velocity Verlet in place on pos/vel.
-    Returns (stats, thermo rows (k, 6) = (step, KE, PE, KE+PE, W, Z) or None), W the
-    virial sum over pairs of r_ij . F_ij and Z the mean neighbours inside the cutoff."""
+    Returns (stats, thermo rows (k, THERMO_COLS) or None); the columns are
+    step, KE, PE, KE+PE, W (virial sum over pairs of r_ij . F_ij), Z (mean
+    neighbours inside the cutoff), <|dr|^2>, <|dr|^4>, alpha_2 and f_ov of the
+    unwrapped displacement dr since step 0 of this call."""
     th = None
     if thermo_every > 0:
-        th = torch.zeros((nsteps // thermo_every + 1, 6), dtype=torch.float64, device=pos.device)
+        th = torch.zeros((nsteps // thermo_every + 1, THERMO_COLS), dtype=torch.float64,
+                         device=pos.device)
     st = hdmd_step_stats()
     rc = lib().hdmd_step(C.byref(sys.c()), _ptr(_dev_f64(pos, "pos")), _ptr(_dev_f64(vel, "vel")),
                          _ptr(_dev_f64(diam, "diam")), _ptr(ws), ws.numel(), nsteps, dt,

@@ -30,7 +30,7 @@ def _run_gpu(sysd, x, v, sig, nsteps, dt, every=1):
 def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
     x, v, sig, L = _state(d, m, a, 3 * d)
     nsteps, dt = 100, 0.004
-    xo, vo, tho, bo = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt)
+    xo, vo, tho, bo, obo = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt, obs=True)
     sysd = H.System(d=d, n=len(x), box_l=L, cutoff=C6, skin=skin, sigma_max=1.2)
     xg, vg, thg, st = _run_gpu(sysd, x, v, sig, nsteps, dt)
     dx = xg - xo
@@ -47,6 +47,38 @@ def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
         W, Z = orc.virial(xs, sig, L, 0, C6, 1.0, rp, cols)
         assert thg[row, 4] == pytest.approx(W, rel=1e-8)
         assert thg[row, 5] == pytest.approx(Z, rel=1e-12)
+    # displacement moments, alpha_2 and f_ov since step 0 at every step
+    assert np.allclose(thg[:, 6], obo[:, 0], rtol=1e-8, atol=1e-15)
+    assert np.allclose(thg[:, 7], obo[:, 1], rtol=1e-8, atol=1e-15)
+    assert np.allclose(thg[:, 8], obo[:, 2], rtol=1e-6, atol=1e-9)
+    assert np.abs(thg[:, 9] - obo[:, 3]).max() < 0.5 / len(x)
+    assert obo[-1, 3] < 1.0                  # atoms have left the overlap radius
+
+
+@pytest.mark.parametrize("d,prec", [(3, H.HDMD_FP64), (6, H.HDMD_FP64), (6, H.HDMD_MIXED),
+                                    (8, H.HDMD_FP64)])
+def test_ballistic_displacement_through_the_box(d, prec):
+    """Atoms on a lattice wider than the interaction range, all with one
+    velocity: no force acts, so the unwrapped |dr| = |v| t at every step while
+    each atom crosses the periodic box and the list is rebuilt many times
+    (d = 8 with n_cell = 2 takes the wrapped-coordinate build)."""
+    m, a = (3, 2.0) if d < 8 else (2, 2.0)
+    x, L = inputs.jittered_lattice(d, m, a, 0.0, 0)
+    n = len(x)
+    vel = np.linspace(0.6, 1.4, d) * np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    v = np.tile(vel, (n, 1))
+    nsteps, dt, every = 600, 0.02, 20
+    sysd = H.System(d=d, n=n, box_l=L, cutoff=C6, skin=0.3, sigma_max=1.0, precision=prec)
+    _, _, th, st = _run_gpu(sysd, x, v, np.ones(n), nsteps, dt, every)
+    t = th[:, 0] * dt
+    v2 = float(vel @ vel)
+    assert np.sqrt(v2) * t[-1] > 2 * L and st.builds > 10
+    tol = 1e-10 if prec == H.HDMD_FP64 else 1e-6
+    assert np.allclose(th[:, 6], v2 * t * t, rtol=tol, atol=1e-20)
+    assert np.allclose(th[:, 7], (v2 * t * t) ** 2, rtol=2 * tol, atol=1e-20)
+    assert th[0, 8] == 0.0
+    assert np.allclose(th[1:, 8], d / (d + 2.0) - 1.0, rtol=tol)
+    assert np.array_equal(th[:, 9], (np.sqrt(v2) * t < 0.1 * d).astype(float))
 
 
 @pytest.mark.parametrize("prec,tol", [(H.HDMD_FP64, 1e-9), (H.HDMD_MIXED, 1e-4)])

@@ -1,0 +1,99 @@
+"""Pins of the oracle's displacement observables (CPU only): the moments of
+the unwrapped displacement, the non-Gaussian parameter alpha_2 of eq. ngp and
+the overlap function f_ov of eq. fov (Sec. II.E), and the unwrapping itself."""
+import numpy as np
+import pytest
+
+from paper_2112_12271_amd import inputs
+
+C6 = 2.0 ** (1.0 / 6.0)
+
+
+@pytest.mark.parametrize("d", [2, 3, 6, 10])
+def test_equal_lengths(orc, d):
+    """Every |dr| = r: <|dr|^2> = r^2, <|dr|^4> = r^4 and alpha_2 = d/(d+2) - 1
+    (the 3-d expression 3/5 - 1 at d = 3); f_ov is 1 below the overlap length
+    0.1 d and 0 above it."""
+    g = np.random.default_rng(d)
+    u = g.normal(size=(500, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    for r in (0.05 * d, 0.15 * d):
+        m2, m4, a2, fov = orc.disp_moments(r * u)
+        assert m2 == pytest.approx(r * r, rel=1e-13)
+        assert m4 == pytest.approx(r ** 4, rel=1e-13)
+        assert a2 == pytest.approx(d / (d + 2.0) - 1.0, rel=1e-12)
+        assert fov == (1.0 if r < 0.1 * d else 0.0)
+
+
+@pytest.mark.parametrize("d,p", [(3, 0.25), (6, 0.5), (8, 0.1)])
+def test_two_populations(orc, d, p):
+    """A fraction p of the atoms moved by r, the rest not at all:
+    alpha_2 = d / ((d+2) p) - 1 and f_ov = 1 - p when r > 0.1 d."""
+    n = 1000
+    k = int(p * n)
+    dr = np.zeros((n, d))
+    dr[:k, 0] = 0.2 * d
+    m2, m4, a2, fov = orc.disp_moments(dr)
+    assert a2 == pytest.approx(d / ((d + 2.0) * p) - 1.0, rel=1e-12)
+    assert fov == pytest.approx(1.0 - p, abs=0)
+
+
+@pytest.mark.parametrize("d", [3, 6])
+def test_gaussian_displacements_have_zero_alpha2(orc, d):
+    """For isotropic Gaussian displacements <|dr|^4> = (1 + 2/d) <|dr|^2>^2,
+    so alpha_2 vanishes in every d (the reason for the d-dependent factor):
+    the sample value lies within five standard errors of 0."""
+    n = 400000
+    dr = np.random.default_rng(10 + d).normal(0.0, 0.3, size=(n, d))
+    m2, m4, a2, fov = orc.disp_moments(dr)
+    assert m2 == pytest.approx(d * 0.09, rel=0.01)
+    assert abs(a2) < 0.02
+    # f_ov is the chi distribution's CDF at 0.1 d / 0.3 (here checked by counting)
+    assert fov == np.mean(np.linalg.norm(dr, axis=1) < 0.1 * d)
+
+
+def test_nothing_moved(orc):
+    m2, m4, a2, fov = orc.disp_moments(np.zeros((10, 4)))
+    assert (m2, m4, a2, fov) == (0.0, 0.0, 0.0, 1.0)
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_ballistic_flight_through_the_box(orc, d):
+    """Atoms on a lattice wider than the interaction range, all with one
+    velocity: no force ever acts, so |dr| = |v| t at every step while every
+    atom crosses the periodic box several times."""
+    m, a = 3, 2.0
+    x, L = inputs.jittered_lattice(d, m, a, 0.0, 0)
+    n = len(x)
+    vel = np.linspace(0.6, 1.4, d) * np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    v = np.tile(vel, (n, 1))
+    nsteps, dt = 600, 0.02
+    xo, vo, th, b, ob = orc.vv(x, v, np.ones(n), L, 0, C6, 0.3, 1.0, nsteps, dt, obs=True)
+    t = np.arange(nsteps + 1) * dt
+    v2 = float(vel @ vel)
+    assert np.sqrt(v2) * t[-1] > 2 * L
+    assert b > 10
+    assert np.allclose(ob[:, 0], v2 * t * t, rtol=1e-12, atol=1e-24)
+    assert np.allclose(ob[:, 1], (v2 * t * t) ** 2, rtol=1e-12, atol=1e-24)
+    assert np.allclose(ob[1:, 2], d / (d + 2.0) - 1.0, rtol=1e-10)
+    assert ob[0, 2] == 0.0
+    assert np.array_equal(ob[:, 3], (np.sqrt(v2) * t < 0.1 * d).astype(float))
+
+
+def test_short_times_match_minimum_image(orc):
+    """In an interacting liquid, while every displacement is below L/2 the
+    unwrapped displacement is the minimum image of x(t) - x(0)."""
+    x, L = inputs.jittered_lattice(4, 5, 1.15, 0.15, 3)
+    n = len(x)
+    sig = inputs.bidisperse(n, 1.0, 1.1, 3)
+    v = inputs.gaussian_velocities(n, 4, 0.5, 4)
+    xo, _, _, b, ob = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 150, 0.003, obs=True)
+    assert b >= 2
+    dr = xo - x
+    dr -= L * np.round(dr / L)
+    assert np.abs(dr).max() < 0.4 * L
+    ref = orc.disp_moments(dr)
+    assert ob[-1, 0] == pytest.approx(ref[0], rel=1e-11)
+    assert ob[-1, 1] == pytest.approx(ref[1], rel=1e-11)
+    assert ob[-1, 2] == pytest.approx(ref[2], rel=1e-9, abs=1e-12)
+    assert ob[-1, 3] == ref[3]
