@@ -79,6 +79,13 @@ typedef struct {
   double epsilon;
   double sigma_max;
   double morse_a;
+  /* Berendsen thermostat of the MD calls (Sec. II.B, II.E): with
+   * thermostat_tau > 0 every velocity kick that completes a full step is
+   * followed by the rescaling v *= lambda, lambda^2 = 1 + (dt/tau)(T_t/T - 1),
+   * T = 2 KE / (d (n-1)) of the previous full step (1 when that KE is 0);
+   * tau must be >= dt.  thermostat_tau = 0: NVE.  Unused by FIRE. */
+  double thermostat_tau;
+  double target_temp;
 } hdmd_system;
 
 /* FIRE 2.0 controls (Sec. II.B cites FIRE 2.0 with the semi-implicit Euler
@@ -172,6 +179,20 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
 int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
               size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
               hdmd_step_stats* stats, void* stream);
+
+/* Self part of the van Hove function (eq. VGC, Sec. II.E) after an
+ * hdmd_step call that returned HDMD_OK on this workspace (no other call on it
+ * since): with dr_i the unwrapped displacement of atom i from that call's
+ * step 0 to its last step,
+ *   hist[b] = #{i : b w <= |dr_i| < (b+1) w},  b < nbins, hist[nbins] = the
+ *   atoms with |dr_i| >= nbins w, so G_s(r_b) = hist[b] / (n w);
+ *   disp = dr in caller order ([n][d] FP64).
+ * hist (nbins + 1 int64, device) and disp (device) are optional (not both
+ * NULL); w = bin_width > 0 and nbins >= 1 when hist is given.  Errors:
+ * HDMD_ERR_ARG, HDMD_ERR_WORKSPACE, HDMD_ERR_STATE (the workspace holds no
+ * completed MD run of this system).  Synchronises. */
+int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbins,
+                  double bin_width, int64_t* hist, double* disp, void* stream);
 
 /* FIRE 2.0 energy minimisation with the semi-implicit Euler update (Sec.
  * II.B), unit masses, global norms: pos ([n][d] FP64, device) in and out.

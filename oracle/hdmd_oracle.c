@@ -468,16 +468,39 @@ void orc_disp_moments(int d, int64_t n, const double* dr, double* out) {
   out[3] = ov / (double)n;
 }
 
-/* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B with unit masses
- * and no thermostat (NVE): per step v += dt/2 F; x += dt v; wrap; rebuild if
- * needed; F = F(x); v += dt/2 F.  The first list is built at step 0.
+/* Self part of the van Hove function (eq. VGC, Sec. II.E) as a histogram of
+ * the displacement lengths: hist[b] = #{i : b w <= |dr_i| < (b+1) w} for
+ * b < nbins and hist[nbins] = #{i : |dr_i| >= nbins w}; G_s(r_b) is
+ * hist[b] / (n w). */
+void orc_van_hove(int d, int64_t n, const double* dr, int32_t nbins, double w, int64_t* hist) {
+  for (int32_t b = 0; b <= nbins; b++) hist[b] = 0;
+  for (int64_t i = 0; i < n; i++) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; k++) r2 += dr[i * d + k] * dr[i * d + k];
+    const double r = sqrt(r2);
+    int32_t b = nbins;
+    for (int32_t c = 0; c < nbins; c++)
+      if (r >= c * w && r < (c + 1) * w) { b = c; break; }
+    hist[b]++;
+  }
+}
+
+/* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B with unit masses:
+ * per step v += dt/2 F; x += dt v; wrap; rebuild if needed; F = F(x);
+ * v += dt/2 F.  The first list is built at step 0.
+ * With tau > 0 the second kick carries the Berendsen thermostat (the paper
+ * folds it into that kick, Sec. II.B and II.E): v = lambda (v + dt/2 F) with
+ * lambda^2 = 1 + (dt/tau)(T0/T - 1), T = 2 KE / (d (n-1)) at the previous
+ * full step (reading: a single pass over the atoms knows only that T; lambda
+ * is 1 when that KE is 0).  tau = 0: NVE.
  * thermo (optional) receives nsteps+1 rows of (KE, PE) at the full steps;
  * obs (optional) nsteps+1 rows of orc_disp_moments of the unwrapped
  * displacement since step 0, which advances by dt v with every drift (the
- * wrap only relabels the image).  Returns the number of list builds. */
+ * wrap only relabels the image); dr_out (optional, [n*d]) that displacement
+ * at the end.  Returns the number of list builds. */
 int64_t orc_vv(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
-               double* v, const double* sig, int64_t nsteps, double dt, double* thermo,
-               double* obs) {
+               double* v, const double* sig, int64_t nsteps, double dt, double tau, double T0,
+               double* thermo, double* obs, double* dr_out) {
   orc_sys S = {d, n, L, pot, c, s, eps};
   int64_t m = n * d;
   orc_nlstate st = {0};
@@ -487,9 +510,15 @@ int64_t orc_vv(int d, int64_t n, double L, int pot, double c, double s, double e
   for (int64_t a = 0; a < m; a++) x[a] = orc_wrap1(x[a], L);
   rebuild(&S, x, sig, &st);
   double pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
-  if (thermo) { thermo[0] = kinetic(m, v); thermo[1] = pe; }
+  double ke = kinetic(m, v);
+  if (thermo) { thermo[0] = ke; thermo[1] = pe; }
   if (obs) orc_disp_moments(d, n, dr, obs);
   for (int64_t t = 1; t <= nsteps; t++) {
+    double lam = 1.0;
+    if (tau > 0.0 && ke > 0.0) {
+      const double T = 2.0 * ke / ((double)d * (double)(n - 1));
+      lam = sqrt(1.0 + dt / tau * (T0 / T - 1.0));
+    }
     for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
     for (int64_t a = 0; a < m; a++) {
       x[a] = orc_wrap1(x[a] + dt * v[a], L);
@@ -497,11 +526,13 @@ int64_t orc_vv(int d, int64_t n, double L, int pot, double c, double s, double e
     }
     if (needs_rebuild(&S, x, &st)) rebuild(&S, x, sig, &st);
     pe = orc_forces(d, n, L, x, sig, pot, c, eps, st.nl->row_ptr, st.nl->cols, F, NULL);
-    for (int64_t a = 0; a < m; a++) v[a] += 0.5 * dt * F[a];
-    if (thermo) { thermo[2 * t] = kinetic(m, v); thermo[2 * t + 1] = pe; }
+    for (int64_t a = 0; a < m; a++) v[a] = lam * (v[a] + 0.5 * dt * F[a]);
+    ke = kinetic(m, v);
+    if (thermo) { thermo[2 * t] = ke; thermo[2 * t + 1] = pe; }
     if (obs) orc_disp_moments(d, n, dr, obs + 4 * t);
   }
   int64_t b = st.builds;
+  if (dr_out) memcpy(dr_out, dr, (size_t)m * sizeof(double));
   orc_list_free(st.nl);
   free(st.xref);
   free(F);

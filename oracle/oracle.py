@@ -107,8 +107,10 @@ def lib():
                                     C.c_double, C.c_double, C.c_int64, _dp]
         L.orc_vv.restype = C.c_int64
         L.orc_vv.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
-                             C.c_double, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_void_p,
-                             C.c_void_p]
+                             C.c_double, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
+                             C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_van_hove.restype = None
+        L.orc_van_hove.argtypes = [C.c_int, C.c_int64, _dp, C.c_int32, C.c_double, _i64p]
         L.orc_disp_moments.restype = None
         L.orc_disp_moments.argtypes = [C.c_int, C.c_int64, _dp, _dp]
         L.orc_fire.restype = None
@@ -208,19 +210,32 @@ def force_one(x, sig, L, pot, c, eps, i):
     return Fi, ei
 
 
-def vv(x, v, sig, L, pot, c, s, eps, nsteps, dt, obs=False):
-    """Run NVE velocity Verlet; returns (x, v, thermo[nsteps+1, 2] = (KE, PE), builds)
-    and, with obs, also the displacement observables [nsteps+1, 4] =
-    (<|dr|^2>, <|dr|^4>, alpha_2, f_ov) since step 0 (Sec. II.E)."""
+def vv(x, v, sig, L, pot, c, s, eps, nsteps, dt, obs=False, tau=0.0, T0=0.0):
+    """Run velocity Verlet (NVE, or with the Berendsen thermostat when tau > 0);
+    returns (x, v, thermo[nsteps+1, 2] = (KE, PE), builds) and, with obs, also
+    the displacement observables [nsteps+1, 4] = (<|dr|^2>, <|dr|^4>, alpha_2,
+    f_ov) since step 0 and the final unwrapped displacements dr[n, d] (Sec. II.E)."""
     x = _f64(x).copy()
     v = _f64(v).copy()
     n, d = x.shape
     th = np.zeros((nsteps + 1, 2))
     ob = np.zeros((nsteps + 1, 4)) if obs else None
-    b = lib().orc_vv(d, n, L, pot, c, s, eps, x, v, _f64(sig), nsteps, dt,
+    dr = np.zeros((n, d)) if obs else None
+    b = lib().orc_vv(d, n, L, pot, c, s, eps, x, v, _f64(sig), nsteps, dt, tau, T0,
                      th.ctypes.data_as(C.c_void_p),
-                     ob.ctypes.data_as(C.c_void_p) if obs else None)
-    return (x, v, th, b, ob) if obs else (x, v, th, b)
+                     ob.ctypes.data_as(C.c_void_p) if obs else None,
+                     dr.ctypes.data_as(C.c_void_p) if obs else None)
+    return (x, v, th, b, ob, dr) if obs else (x, v, th, b)
+
+
+def van_hove(dr, nbins, w):
+    """Displacement-length histogram behind G_s(r) (eq. VGC): nbins + 1 counts,
+    the last one for |dr| >= nbins * w."""
+    dr = _f64(dr)
+    n, d = dr.shape
+    h = np.zeros(nbins + 1, dtype=np.int64)
+    lib().orc_van_hove(d, n, dr, nbins, w, h)
+    return h
 
 
 def disp_moments(dr):

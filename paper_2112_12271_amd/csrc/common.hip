@@ -182,6 +182,13 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
         s->pe = pe;
         s->ke = ke;
         if (!isfinite(pe + ke)) s->err |= ERR_RUN_NAN;
+        // Berendsen factor for the next full-step kick, from this step's T
+        if (s->tau_t > 0.0 && ke > 0.0) {
+          const double T = 2.0 * ke / ((double)s->d * (double)(s->n - 1));
+          s->vscale = sqrt(1.0 + s->dt / s->tau_t * (s->temp_t / T - 1.0));
+        } else {
+          s->vscale = 1.0;
+        }
         if (rec) {
           double* r = s->thermo + kThermoCols * (s->step / s->thermo_every);
           r[0] = (double)s->step;

@@ -20,6 +20,8 @@ struct DKernels {
   void (*force)(bool mix, int lpa, bool morse, const KArgs& a, int grid, int fire, hipStream_t st);
   void (*step)(bool mix, int lpa, bool morse, const KArgs& a, int grid, hipStream_t st);
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
+  void (*vanhove)(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
+                  unsigned long long* hist, double* disp);
 };
 
 const DKernels* dkernels(int d);

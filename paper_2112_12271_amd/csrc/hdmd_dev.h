@@ -83,6 +83,7 @@ struct SysDev {
   double fxinv;          // L / 2^32
   double qmarg;          // sqrt(d)/2 with slack: half the quantisation error bound
   double morse_a;        // Morse stiffness (potential 2)
+  double tau_t, temp_t;  // Berendsen time constant (0: NVE) and target temperature
   float rl2f, lscf, Lf, pad3;
   int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
                          // (squared quantised units)
@@ -123,6 +124,7 @@ struct SysDev {
   int64_t step, builds, iters;
   double ke, pe;
   double fdt, falpha, fmax, c_dt, c_keep, c_mix;
+  double vscale;  // Berendsen factor of the next full-step kick (1: none)
   int32_t npos, nneg, c_zero, pad2;
 };
 

@@ -84,8 +84,12 @@ void l_fire_update(bool mix, const KArgs& a, int grid, hipStream_t st) {
   if (mix) k_fire_update<D, true><<<grid, kTile, 0, st>>>(a);
   else k_fire_update<D, false><<<grid, kTile, 0, st>>>(a);
 }
+void l_vanhove(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
+               unsigned long long* hist, double* disp) {
+  k_vanhove<D><<<grid, kTile, 0, st>>>(s, nbins, w, hist, disp);
+}
 const DKernels table = {l_load, l_unload, l_bin, l_cellsort, l_build, l_force, l_step,
-                        l_fire_update};
+                        l_fire_update, l_vanhove};
 }  // namespace
 
 #define HDMD_CAT2(a, b) a##b

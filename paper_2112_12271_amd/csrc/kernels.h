@@ -10,6 +10,7 @@
 //  k_step        fused velocity-Verlet step + rebuild trigger (Sec. II.B/II.C)
 //  k_fire_update semi-implicit Euler FIRE update
 //  k_unload      internal -> caller order
+//  k_vanhove     unwrapped displacements and the self van Hove histogram
 #pragma once
 #include <type_traits>
 
@@ -95,6 +96,37 @@ __global__ __launch_bounds__(kTile) void k_unload(const SysDev* s, double* __res
     const VT* f = reinterpret_cast<const VT*>(s->f);
 #pragma unroll
     for (int k = 0; k < D; k++) force[(size_t)a * D + k] = double(f[(size_t)k * npad + p]);
+  }
+}
+
+// Unwrapped displacement of every atom since the MD call's step 0 (the
+// displacement up to the last build plus the minimum image of x - x_ref),
+// written in caller order to disp ([n][d], optional), and the histogram of
+// |dr| behind the self part of the van Hove function (eq. VGC, Sec. II.E):
+// hist[b] counts b w <= |dr| < (b+1) w, hist[nbins] the atoms beyond.
+template <int D>
+__global__ __launch_bounds__(kTile) void k_vanhove(const SysDev* s, int nbins, double w,
+                                                   unsigned long long* __restrict__ hist,
+                                                   double* __restrict__ disp) {
+  const int p = blockIdx.x * kTile + threadIdx.x;
+  if (p >= s->n) return;
+  const int pc = s->pcur, npad = s->npad;
+  const double L = s->L, h = s->hL;
+  double x[D];
+  load_x<D>(s->x[s->xcur], p, x);
+  const int a = s->oid[pc][p];
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    const size_t o = (size_t)k * npad + p;
+    const double dk = s->disp[pc][o] + min_image(x[k] - s->xref[o], L, h);
+    if (disp) disp[(size_t)a * D + k] = dk;
+    r2 = __builtin_fma(dk, dk, r2);
+  }
+  if (hist) {
+    const double q = floor(sqrt(r2) / w);
+    const int b = q < (double)nbins ? (int)q : nbins;
+    atomicAdd(hist + b, 1ull);
   }
 }
 
@@ -1296,8 +1328,10 @@ __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
 }
 
 // Fused velocity-Verlet step (kick-drift-kick leapfrog, Sec. II.B):
-//   F = F(x^n); v^n = v^(n-1/2) + dt/2 F (skipped at step 0, where v is the
-//   full-step velocity); record KE(v^n), PE(x^n); v^(n+1/2) = v^n + dt/2 F;
+//   F = F(x^n); v^n = lambda (v^(n-1/2) + dt/2 F) (skipped at step 0, where v
+//   is the full-step velocity; lambda is the Berendsen factor from the
+//   previous full step's temperature, 1 without a thermostat: the paper folds
+//   the thermostat into this kick); record KE(v^n), PE(x^n); v^(n+1/2) = v^n + dt/2 F;
 //   x^(n+1) = wrap(x^n + dt v^(n+1/2)) into the other record buffer;
 //   max_i |x^(n+1)_i - x_ref,i|^2 for the rebuild trigger (skin/2).
 // At the closing step (n == nsteps) only the second kick is applied.
@@ -1332,16 +1366,26 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     for (int p = 0; p < kPart; p++) vals[p] = 0.0;
     if (vi && sub == 0) {
       VT* v = reinterpret_cast<VT*>(s->v[pc]);
+      const VT lam = VT(s->vscale);
+      const double L = s->L, h = s->hL;
+      double m2 = 0.0;
+      if (rec) {
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          const size_t o = (size_t)k * npad + i;
+          const double dd = s->disp[pc][o] + min_image(me.x[k] - s->xref[o], L, h);
+          m2 = __builtin_fma(dd, dd, m2);
+        }
+      }
       VT vk[D];
       double xn[D], ke = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         vk[k] = v[(size_t)k * npad + i];
-        if (!first) vk[k] += VT(hdt) * F[k];
+        if (!first) vk[k] = lam * (vk[k] + VT(hdt) * F[k]);
         ke += (double)vk[k] * (double)vk[k];
       }
-      const double L = s->L, h = s->hL;
-      double r2 = 0.0, m2 = 0.0;
+      double r2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; k++) {
         if (!close) {
@@ -1351,13 +1395,8 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
           xn[k] = me.x[k];
         }
         v[(size_t)k * npad + i] = vk[k];
-        const double xr = s->xref[(size_t)k * npad + i];
-        const double dx = min_image(xn[k] - xr, L, h);
+        const double dx = min_image(xn[k] - s->xref[(size_t)k * npad + i], L, h);
         r2 = __builtin_fma(dx, dx, r2);
-        if (rec) {
-          const double dd = s->disp[pc][(size_t)k * npad + i] + min_image(me.x[k] - xr, L, h);
-          m2 = __builtin_fma(dd, dd, m2);
-        }
       }
       store_rec<D>(s->x[cur ^ 1], i, xn, me.sg);
       if (MIX) store_q<D>(s->q[cur ^ 1], i, xn, me.sg, h, s->fxscale);

@@ -91,6 +91,9 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   if (s->potential == HDMD_MORSE && !(s->morse_a > 0.0 && std::isfinite(s->morse_a)))
     return fail(HDMD_ERR_ARG, "morse_a must be positive");
   if (s->precision != HDMD_FP64 && s->precision != HDMD_MIXED) return fail(HDMD_ERR_ARG, "bad precision");
+  if (!(s->thermostat_tau >= 0) || !std::isfinite(s->thermostat_tau) || !(s->target_temp >= 0) ||
+      !std::isfinite(s->target_temp))
+    return fail(HDMD_ERR_ARG, "thermostat_tau and target_temp must be >= 0");
   if (s->max_neighbors < 1 || s->max_neighbors > (1 << 20)) return fail(HDMD_ERR_ARG, "max_neighbors must be in [1, 2^20]");
   if (s->box_l < 2.0 * s->cutoff * s->sigma_max)
     return fail(HDMD_ERR_BOX, "box_l < 2 * cutoff * sigma_max: minimum image is ambiguous");
@@ -157,6 +160,9 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.d = p.d;
   h.potential = s->potential;
   h.morse_a = s->potential == HDMD_MORSE ? s->morse_a : 0.0;
+  h.tau_t = s->thermostat_tau;
+  h.temp_t = s->target_temp;
+  h.vscale = 1.0;
   h.precision = s->precision;
   h.n = p.n;
   h.npad = p.npad;
@@ -601,6 +607,8 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
   if (rc) return rc;
   if (!vel) return fail(HDMD_ERR_ARG, "null velocity pointer");
   if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HDMD_ERR_ARG, "need nsteps >= 0 and dt > 0");
+  if (sys->thermostat_tau > 0 && sys->thermostat_tau < dt)
+    return fail(HDMD_ERR_ARG, "thermostat_tau must be >= dt");
   hipStream_t st = S(stream);
   int blk = 0;
   rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
@@ -692,6 +700,32 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
   rc = err_to_status(h.err, "hdmd_step");
   if (rc) return rc;  // caller arrays untouched
   dkernels(p.d)->unload(p.mix, dev, p.ntiles, st, pos, vel, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return HDMD_OK;
+}
+
+int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbins,
+                  double bin_width, int64_t* hist, double* disp, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!ws) return fail(HDMD_ERR_ARG, "null workspace");
+  if (ws_bytes < p.bytes) return fail(HDMD_ERR_WORKSPACE, "workspace too small");
+  if (!hist && !disp) return fail(HDMD_ERR_ARG, "neither hist nor disp given");
+  if (hist && (nbins < 1 || !(bin_width > 0) || !std::isfinite(bin_width)))
+    return fail(HDMD_ERR_ARG, "need nbins >= 1 and bin_width > 0");
+  hipStream_t st = S(stream);
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  if (h.n != p.n || h.d != p.d) return fail(HDMD_ERR_STATE, "workspace holds another system");
+  if (h.mode != MODE_MD || h.err != 0)
+    return fail(HDMD_ERR_STATE, "the workspace holds no completed hdmd_step run");
+  if (hist) launch_fill_i32(reinterpret_cast<int32_t*>(hist), 2 * ((int64_t)nbins + 1), 0, st);
+  dkernels(p.d)->vanhove(dev, p.ntiles, st, nbins, bin_width,
+                         reinterpret_cast<unsigned long long*>(hist), disp);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return HDMD_OK;
@@ -1118,6 +1152,8 @@ static int batch_add(void* table_ws, int32_t slot, const hdmd_system* sys, const
     if (rc) return rc;
   } else {
     if (nsteps < 0 || !(dt > 0)) return fail(HDMD_ERR_ARG, "need nsteps >= 0 and dt > 0");
+    if (sys->thermostat_tau > 0 && sys->thermostat_tau < dt)
+      return fail(HDMD_ERR_ARG, "thermostat_tau must be >= dt");
     if (!vel) return fail(HDMD_ERR_ARG, "null velocity pointer");
     rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
     if (rc) return rc;

@@ -50,7 +50,8 @@ class hdmd_system(C.Structure):
     _fields_ = [("d", C.c_int32), ("potential", C.c_int32), ("precision", C.c_int32),
                 ("max_neighbors", C.c_int32), ("n", C.c_int64), ("box_l", C.c_double),
                 ("cutoff", C.c_double), ("skin", C.c_double), ("epsilon", C.c_double),
-                ("sigma_max", C.c_double), ("morse_a", C.c_double)]
+                ("sigma_max", C.c_double), ("morse_a", C.c_double),
+                ("thermostat_tau", C.c_double), ("target_temp", C.c_double)]
 
 
 class hdmd_fire_params(C.Structure):
@@ -87,6 +88,8 @@ _SIGS = {
     "hdmd_forces": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp]),
     "hdmd_step": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, C.c_size_t, C.c_int64,
                             C.c_double, C.c_int64, _vp, C.POINTER(hdmd_step_stats), _vp]),
+    "hdmd_van_hove": (C.c_int, [C.POINTER(hdmd_system), _vp, C.c_size_t, C.c_int32, C.c_double,
+                                _vp, _vp, _vp]),
     "hdmd_fire_minimize": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t,
                                      C.POINTER(hdmd_fire_params), C.POINTER(hdmd_fire_result), _vp]),
     "hdmd_batch_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int64]),
@@ -163,11 +166,13 @@ class System:
     precision: int = HDMD_FP64
     max_neighbors: int = 64
     morse_a: float = MORSE_A
+    thermostat_tau: float = 0.0   # Berendsen time constant of MD runs (0: NVE)
+    target_temp: float = 0.0
 
     def c(self) -> hdmd_system:
         return hdmd_system(self.d, self.potential, self.precision, self.max_neighbors, self.n,
                            self.box_l, self.cutoff, self.skin, self.epsilon, self.sigma_max,
-                           self.morse_a)
+                           self.morse_a, self.thermostat_tau, self.target_temp)
 
 
 def hdmd_fire_defaults(dt0: float = 0.05, f_tol: float = 1e-10,
@@ -258,6 +263,19 @@ def hdmd_step(sys: System, pos, vel, diam, ws, nsteps: int, dt: float, thermo_ev
                          thermo_every, _ptr(th), C.byref(st), _stream(stream))
     _check(rc, "hdmd_step")
     return st, th
+
+
+def hdmd_van_hove(sys: System, ws, nbins: int, bin_width: float, disp: bool = False,
+                  stream=None):
+    """Histogram of |dr| (nbins + 1 counts, the last one beyond nbins * bin_width)
+    of the unwrapped displacements of the hdmd_step call last run on ws, and
+    with disp also dr itself in caller order (n, d); G_s(r_b) = hist[b] / (n w)."""
+    hist = torch.empty(nbins + 1, dtype=torch.int64, device=ws.device)
+    dr = torch.empty((sys.n, sys.d), dtype=torch.float64, device=ws.device) if disp else None
+    rc = lib().hdmd_van_hove(C.byref(sys.c()), _ptr(ws), ws.numel(), nbins, bin_width,
+                             _ptr(hist), _ptr(dr), _stream(stream))
+    _check(rc, "hdmd_van_hove")
+    return hist, dr
 
 
 def step_auto(sys: System, pos, vel, diam, nsteps: int, dt: float, thermo_every: int = 0,

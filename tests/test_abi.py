@@ -11,7 +11,7 @@ from paper_2112_12271_amd import hdmd as H
 
 def test_library_exports_every_header_symbol():
     names = H.header_symbols()
-    assert len(names) == 16
+    assert len(names) == 17
     raw = ctypes.CDLL(H.LIB_PATH)
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
@@ -62,7 +62,8 @@ def test_cells_per_axis_rejects_tiny_box():
 
 
 @pytest.mark.parametrize("bad", [dict(d=1), dict(d=11), dict(n=0), dict(skin=-0.1),
-                                 dict(max_neighbors=0), dict(box_l=float("nan"))])
+                                 dict(max_neighbors=0), dict(box_l=float("nan")),
+                                 dict(thermostat_tau=-1.0), dict(target_temp=float("inf"))])
 def test_invalid_system_has_no_workspace(bad):
     assert H.lib().hdmd_workspace_bytes(ctypes.byref(_sys(**bad).c())) == 0
     with pytest.raises(H.HdmdError):

@@ -30,7 +30,7 @@ def _run_gpu(sysd, x, v, sig, nsteps, dt, every=1):
 def test_short_trajectory_matches_oracle(orc, d, m, a, skin):
     x, v, sig, L = _state(d, m, a, 3 * d)
     nsteps, dt = 100, 0.004
-    xo, vo, tho, bo, obo = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt, obs=True)
+    xo, vo, tho, bo, obo, dro = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt, obs=True)
     sysd = H.System(d=d, n=len(x), box_l=L, cutoff=C6, skin=skin, sigma_max=1.2)
     xg, vg, thg, st = _run_gpu(sysd, x, v, sig, nsteps, dt)
     dx = xg - xo
@@ -144,3 +144,96 @@ def test_c1_energy_conservation():
     assert np.isfinite(e).all()
     assert np.abs(e - e[0]).max() < 1e-3 * max(1.0, abs(e[0]))
     assert st.builds >= 1
+
+
+@pytest.mark.parametrize("d,m,a", [(3, 8, 1.12), (6, 4, 1.05)])
+def test_berendsen_trajectory_matches_oracle(orc, d, m, a):
+    """The Berendsen thermostat folded into the full-step kick (Sec. II.B),
+    against the oracle over 100 steps from T = 1 towards T0 = 0.3."""
+    x, v, sig, L = _state(d, m, a, 5 * d)
+    nsteps, dt, tau, T0 = 100, 0.004, 0.05, 0.3
+    xo, vo, tho, _ = orc.vv(x, v, sig, L, 0, C6, 0.25, 1.0, nsteps, dt, tau=tau, T0=T0)
+    sysd = H.System(d=d, n=len(x), box_l=L, cutoff=C6, skin=0.25, sigma_max=1.2,
+                    thermostat_tau=tau, target_temp=T0)
+    xg, vg, thg, _ = _run_gpu(sysd, x, v, sig, nsteps, dt)
+    dx = xg - xo
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-8
+    assert np.allclose(thg[:, 1], tho[:, 0], rtol=1e-10, atol=1e-12)
+    assert np.allclose(thg[:, 2], tho[:, 1], rtol=1e-10, atol=1e-12)
+    assert tho[-1, 0] < 0.7 * tho[0, 0]      # the thermostat has drawn heat out
+
+
+@pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
+def test_berendsen_free_atoms_relax_geometrically(prec):
+    """No force acts on a wide lattice with one common velocity, so
+    T_t - T0 = (1 - dt/tau)^t (T_0 - T0) with T = 2 KE / (d (n-1))."""
+    d, m, a = 6, 3, 2.0
+    x, L = inputs.jittered_lattice(d, m, a, 0.0, 0)
+    n = len(x)
+    vel = np.linspace(0.6, 1.4, d) * np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    v = np.tile(vel, (n, 1))
+    dt, tau, T0, nsteps = 0.01, 0.1, 0.25, 200
+    sysd = H.System(d=d, n=n, box_l=L, cutoff=C6, skin=0.3, sigma_max=1.0, precision=prec,
+                    thermostat_tau=tau, target_temp=T0)
+    _, _, th, _ = _run_gpu(sysd, x, v, np.ones(n), nsteps, dt)
+    T = 2.0 * th[:, 1] / (d * (n - 1))
+    ref = T0 + (1.0 - dt / tau) ** np.arange(nsteps + 1) * (T[0] - T0)
+    # mixed: FP32 velocities and factor, errors damped by the contraction (~10 ulp)
+    tol = 1e-12 if prec == H.HDMD_FP64 else 1e-5
+    assert np.allclose(T, ref, rtol=tol, atol=1e-15)
+
+
+def test_thermostat_time_constant_below_step_is_rejected():
+    x, v, sig, L = _state(3, 4, 1.12, 1)
+    sysd = H.System(d=3, n=len(x), box_l=L, cutoff=C6, skin=0.3, sigma_max=1.2,
+                    thermostat_tau=0.001, target_temp=1.0)
+    ws = H.workspace(sysd)
+    with pytest.raises(H.HdmdError) as e:
+        H.hdmd_step(sysd, dev(x), dev(v), dev(sig), ws, 10, 0.004)
+    assert e.value.status == H.HDMD_ERR_ARG
+
+
+@pytest.mark.parametrize("d,m,a,skin,prec", [(3, 8, 1.12, 0.3, H.HDMD_FP64),
+                                             (6, 4, 1.05, 0.25, H.HDMD_FP64),
+                                             (6, 4, 1.05, 0.25, H.HDMD_MIXED),
+                                             (8, 3, 1.0, 0.25, H.HDMD_FP64)])
+def test_van_hove_matches_oracle(orc, d, m, a, skin, prec):
+    """Unwrapped displacements after 100 steps (element by element) and the
+    histogram behind G_s (eq. VGC), bit-exact up to atoms within 1e-8 of a
+    bin edge; d = 8 with n_cell = 2 takes the wrapped build."""
+    x, v, sig, L = _state(d, m, a, 3 * d)
+    nsteps, dt = 100, 0.004
+    _, _, _, _, _, dro = orc.vv(x, v, sig, L, 0, C6, skin, 1.0, nsteps, dt, obs=True)
+    sysd = H.System(d=d, n=len(x), box_l=L, cutoff=C6, skin=skin, sigma_max=1.2, precision=prec)
+    sysw, _, _ = H.step_auto(sysd, dev(x), dev(v), dev(sig), nsteps, dt)   # final row width
+    ws = H.workspace(sysw)
+    H.hdmd_step(sysw, dev(x), dev(v), dev(sig), ws, nsteps, dt)
+    nb, w = 40, 0.1
+    hist, dr = H.hdmd_van_hove(sysw, ws, nb, w, disp=True)
+    hist, dr = hist.cpu().numpy(), dr.cpu().numpy()
+    tol = 1e-9 if prec == H.HDMD_FP64 else 1e-4
+    assert np.abs(dr - dro).max() < tol
+    ho = orc.van_hove(dro, nb, w)
+    r = np.linalg.norm(dro, axis=1)
+    amb = int(np.sum(np.abs(r / w - np.round(r / w)) * w < 10 * tol))
+    assert hist.sum() == len(x)
+    assert np.abs(hist - ho).sum() <= 2 * amb
+    hist2, none = H.hdmd_van_hove(sysw, ws, nb, w)
+    assert none is None and np.array_equal(hist2.cpu().numpy(), hist)
+
+
+def test_van_hove_needs_a_completed_run():
+    x, v, sig, L = _state(3, 5, 1.12, 2)
+    sysd = H.System(d=3, n=len(x), box_l=L, cutoff=C6, skin=0.3, sigma_max=1.2)
+    sysd, ws = H.build_with_width(sysd, dev(x), dev(sig))
+    with pytest.raises(H.HdmdError) as e:
+        H.hdmd_van_hove(sysd, ws, 10, 0.1)
+    assert e.value.status == H.HDMD_ERR_STATE
+    H.hdmd_step(sysd, dev(x), dev(v), dev(sig), ws, 5, 0.004)
+    with pytest.raises(H.HdmdError) as e:
+        H.hdmd_van_hove(sysd, ws, 0, 0.1)
+    assert e.value.status == H.HDMD_ERR_ARG
+    hist, _ = H.hdmd_van_hove(sysd, ws, 10, 0.1)
+    assert int(hist.sum()) == len(x)

@@ -77,3 +77,42 @@ def test_fire_jammed_converges_with_positive_energy(orc):
     F, _, E = orc.forces(x1, sig, L, 1, 1.0, 1.0, rp, cols)
     assert np.sqrt((F * F).sum(axis=1)).max() < 1e-10
     assert E == pytest.approx(res.energy, rel=1e-12)
+
+
+def _free_lattice(d, m=3, a=2.0):
+    """Atoms on a lattice wider than the WCA range, all with one velocity: no
+    force acts at any step."""
+    x, L = inputs.jittered_lattice(d, m, a, 0.0, 0)
+    n = len(x)
+    vel = np.linspace(0.6, 1.4, d) * np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    return x, np.tile(vel, (n, 1)), np.ones(n), L
+
+
+@pytest.mark.parametrize("d,tau_steps", [(3, 10.0), (4, 1.0), (5, 37.5)])
+def test_berendsen_relaxes_free_atoms_geometrically(orc, d, tau_steps):
+    """Without forces each step rescales v by lambda, so
+    T_t - T0 = (1 - dt/tau)^t (T_0 - T0) exactly (tau = dt reaches T0 in one
+    step), T = 2 KE / (d (n-1))."""
+    x, v, sig, L = _free_lattice(d)
+    n = len(x)
+    dt, T0, nsteps = 0.01, 0.25, 200
+    tau = tau_steps * dt
+    _, _, th, _ = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, nsteps, dt, tau=tau, T0=T0)
+    T = 2.0 * th[:, 0] / (d * (n - 1))
+    ref = T0 + (1.0 - dt / tau) ** np.arange(nsteps + 1) * (T[0] - T0)
+    assert np.allclose(T, ref, rtol=1e-12, atol=1e-15)
+    assert np.all(th[:, 1] == 0.0)
+
+
+def test_berendsen_liquid_reaches_target(orc):
+    """An interacting liquid started hot settles at the target temperature
+    (time average over the second half within 3 %); tau = 0 is NVE bit for bit."""
+    x, v, sig, L = _fluid(d=3, m=5, a=1.12, seed=7, T=1.5)
+    n = len(x)
+    dt, T0 = 0.004, 0.5
+    _, _, th, _ = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 1500, dt, tau=0.1, T0=T0)
+    T = 2.0 * th[:, 0] / (3 * (n - 1))
+    assert abs(T[750:].mean() / T0 - 1.0) < 0.03
+    a = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 50, dt)
+    b = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 50, dt, tau=0.0, T0=T0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])

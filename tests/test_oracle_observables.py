@@ -68,7 +68,7 @@ def test_ballistic_flight_through_the_box(orc, d):
     vel = np.linspace(0.6, 1.4, d) * np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
     v = np.tile(vel, (n, 1))
     nsteps, dt = 600, 0.02
-    xo, vo, th, b, ob = orc.vv(x, v, np.ones(n), L, 0, C6, 0.3, 1.0, nsteps, dt, obs=True)
+    xo, vo, th, b, ob, dr = orc.vv(x, v, np.ones(n), L, 0, C6, 0.3, 1.0, nsteps, dt, obs=True)
     t = np.arange(nsteps + 1) * dt
     v2 = float(vel @ vel)
     assert np.sqrt(v2) * t[-1] > 2 * L
@@ -78,6 +78,10 @@ def test_ballistic_flight_through_the_box(orc, d):
     assert np.allclose(ob[1:, 2], d / (d + 2.0) - 1.0, rtol=1e-10)
     assert ob[0, 2] == 0.0
     assert np.array_equal(ob[:, 3], (np.sqrt(v2) * t < 0.1 * d).astype(float))
+    # every atom's unwrapped displacement is v t, and all land in one bin of G_s
+    assert np.allclose(dr, vel * t[-1], rtol=1e-12, atol=1e-12)
+    h = orc.van_hove(dr, 100, 0.5)
+    assert h[int(np.sqrt(v2) * t[-1] / 0.5)] == n and h.sum() == n
 
 
 def test_short_times_match_minimum_image(orc):
@@ -87,7 +91,7 @@ def test_short_times_match_minimum_image(orc):
     n = len(x)
     sig = inputs.bidisperse(n, 1.0, 1.1, 3)
     v = inputs.gaussian_velocities(n, 4, 0.5, 4)
-    xo, _, _, b, ob = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 150, 0.003, obs=True)
+    xo, _, _, b, ob, drr = orc.vv(x, v, sig, L, 0, C6, 0.3, 1.0, 150, 0.003, obs=True)
     assert b >= 2
     dr = xo - x
     dr -= L * np.round(dr / L)
@@ -97,3 +101,31 @@ def test_short_times_match_minimum_image(orc):
     assert ob[-1, 1] == pytest.approx(ref[1], rel=1e-11)
     assert ob[-1, 2] == pytest.approx(ref[2], rel=1e-9, abs=1e-12)
     assert ob[-1, 3] == ref[3]
+    assert np.allclose(drr, dr, rtol=0, atol=1e-11)
+
+
+def test_van_hove_bins(orc):
+    """Half-open bins [b w, (b+1) w), the last count for |dr| >= nbins w."""
+    dr = np.zeros((7, 3))
+    dr[:, 0] = [0.0, 0.2499, 0.25, 0.5, 0.74, 0.75, 9.0]
+    assert orc.van_hove(dr, 3, 0.25).tolist() == [2, 1, 2, 2]
+    dr[:, 0] = 0.0
+    dr[:, 1] = [0.0, 0.2499, 0.25, 0.5, 0.74, 0.75, 9.0]    # any axis, any sign
+    dr[:, 1] *= -1
+    assert orc.van_hove(dr, 3, 0.25).tolist() == [2, 1, 2, 2]
+
+
+@pytest.mark.parametrize("d", [3, 6])
+def test_van_hove_of_gaussian_displacements(orc, d):
+    """For isotropic Gaussian displacements of width s, G_s is the chi
+    distribution with d degrees of freedom scaled by s: every bin's count
+    within five binomial standard deviations of n times its probability."""
+    from scipy.stats import chi
+    n, sd, w, nb = 200000, 0.3, 0.05, 40
+    dr = np.random.default_rng(20 + d).normal(0.0, sd, size=(n, d))
+    h = orc.van_hove(dr, nb, w)
+    edges = np.arange(nb + 1) * w
+    p = np.diff(chi.cdf(edges, d, scale=sd))
+    p = np.append(p, chi.sf(edges[-1], d, scale=sd))
+    assert h.sum() == n
+    assert np.all(np.abs(h - n * p) <= 5 * np.sqrt(n * p * (1 - p)) + 1)
