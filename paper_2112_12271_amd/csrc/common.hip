@@ -136,8 +136,16 @@ __global__ __launch_bounds__(kTile) void k_scatter(KArgs a) {
     if (!running(s) || !need_rebuild(s)) continue;
     const int i = tile * kTile + threadIdx.x;
     if (i >= s->n) continue;
-    const int slot = cell_start(s, s->cell_of[i]) + s->rank[i];
-    s->key[slot] = s->oid[s->pcur][i];
+    const int c = s->cell_of[i];
+    const int slot = cell_start(s, c) + s->rank[i];
+    int key = s->oid[s->pcur][i];
+    if (s->ysort) {
+      // the offset along the last axis exactly as the subcell sort quantises
+      // it (caller ids below 2^23)
+      const double xl = s->x[s->xcur ^ 1][(size_t)i * rec_stride(s->d) + s->d - 1];
+      key |= (quant8(xl - last_centre(s, c), s->qinv) + 128) << 23;
+    }
+    s->key[slot] = key;
     s->src[slot] = i;
   }
 }

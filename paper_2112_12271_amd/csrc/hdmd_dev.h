@@ -87,6 +87,7 @@ struct SysDev {
   float rl2f, lscf, Lf, pad3;
   int32_t tq, tcull;     // int8 prefilter threshold; row-culling threshold
                          // (squared quantised units)
+  int32_t ysort, pad5;   // 1: subcells ordered by last-axis offset, then caller id
   double* x[2];
   int32_t* q[2];
   void* v[2];
@@ -259,9 +260,11 @@ __device__ inline double min_image(double dx, double L, double h) {
   return dx - sh;
 }
 
+__host__ __device__ constexpr int rec_stride(int d) { return d <= 3 ? 4 : (d <= 7 ? 8 : 16); }
+
 template <int D>
 struct Dims {
-  static constexpr int DR = D <= 3 ? 4 : (D <= 7 ? 8 : 16);  // FP64 record stride (doubles)
+  static constexpr int DR = rec_stride(D);                    // FP64 record stride (doubles)
   static constexpr int NR = (D + 2) / 2;                      // double2 loads per record
   static constexpr int SQ = (D + 1) & ~1;                     // FP64 sigma slot (in ints)
   static constexpr int DQ = D <= 2 ? 4 : (D <= 6 ? 8 : 16);  // fixed-point record stride (ints)
@@ -269,6 +272,27 @@ struct Dims {
   static constexpr int DY = (D + 3) & ~3;                     // FP32 offset stride
   static constexpr int QW = (D + 3) / 4;                      // int8x4 words of the offsets
 };
+
+// int8 offset from the subcell centre in units of L_sc / 250; |y| <= L_sc/2
+// up to binning rounding, so |q| <= 125 and the clamp never bites.
+__device__ inline int quant8(double y, double qinv) {
+  int q = (int)rint(y * qinv);
+  return q < -127 ? -127 : (q > 127 ? 127 : q);
+}
+
+// Centre of subcell c along the last axis (the fastest-varying digit).
+__device__ inline double last_centre(const SysDev* s, int c) {
+  return ((double)(c % s->ncell) + 0.5) * s->lsc - s->hL;
+}
+
+// An atom's share T of the candidate-lane prefilter threshold (squared
+// quantised units): a = (c sigma + s)/2, alpha = a/Delta + sqrt(d)/2 (with
+// slack), T = floor(2 alpha^2) + 1; non-decreasing in sigma.
+__device__ inline int thresh_share(const SysDev* s, double sg) {
+  const double ai = 0.5 * (s->cutoff * sg + s->skin);
+  const double al = ai * s->qinv + s->qmarg;
+  return (int)floor(2.0 * al * al) + 1;
+}
 
 // Device arrays are global memory: accessing them through the global
 // address space gives global_load/store instead of flat ones.

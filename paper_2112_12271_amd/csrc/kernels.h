@@ -216,15 +216,10 @@ __device__ inline void bitonic_sort(int* keys, int* vals, int cnt) {
 
 __device__ inline int sext8(int w, int k) { return (int)(signed char)((w >> (8 * k)) & 0xff); }
 
-// int8 offset from the subcell centre in units of L_sc / 250; |y| <= L_sc/2
-// up to binning rounding, so |q| <= 125 and the clamp never bites.
-__device__ inline int quant8(double y, double qinv) {
-  int q = (int)rint(y * qinv);
-  return q < -127 ? -127 : (q > 127 ? 127 : q);
-}
-
 // One subcell of a system that rebuilds (a block of 256 threads): its atoms
-// sorted by caller id, then every per-atom array permuted into subcell order.
+// sorted by their keys (caller id, or, with ysort, the quantised offset along
+// the last axis and then caller id), then every per-atom array permuted into
+// subcell order.
 template <int D, typename VT>
 __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
   constexpr int DY = Dims<D>::DY, QW = Dims<D>::QW;
@@ -258,7 +253,7 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
     int u = c;
 #pragma unroll
     for (int k = D - 1; k >= 0; k--) {
-      cen[k] = ((double)(u % nc) + 0.5) * s->lsc - s->hL;
+      cen[k] = k == D - 1 ? last_centre(s, c) : ((double)(u % nc) + 0.5) * s->lsc - s->hL;
       u /= nc;
     }
   }
@@ -329,9 +324,8 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
         p16[k / 2] |= (qv & 0xffff) << (16 * (k % 2));
         B += qv * qv;
       }
+      const int T = thresh_share(s, sg);
       const double ai = 0.5 * (s->cutoff * sg + s->skin);
-      const double al = ai * s->qinv + s->qmarg;
-      const int T = (int)floor(2.0 * al * al) + 1;
       const double reach = (ai + 0.5 * s->rlmax) * s->qinv;
       p16[(D + 1) / 2 < 4 ? 3 : 7] = B - T;
       p16[5] = (int)ceil(reach * reach);
@@ -340,7 +334,7 @@ __device__ inline void cellsort_tile(SysDev* s, int c, int* sk, int* sv) {
       pp[0] = make_int4(p16[0], p16[1], p16[2], p16[3]);
       pp[1] = make_int4(p16[4], p16[5], p16[6], p16[7]);
     }
-    s->oid[pn][dst] = keys[q];
+    s->oid[pn][dst] = s->ysort ? keys[q] & ((1 << 23) - 1) : keys[q];
   }
   __syncthreads();
 }

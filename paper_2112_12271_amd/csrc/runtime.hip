@@ -190,6 +190,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.fxinv = s->box_l / 4294967296.0;
   h.qinv = (double)kQScale / h.lsc;
   h.qmarg = 0.5 * std::sqrt((double)p.d) * (1.0 + 1e-6);
+  h.ysort = p.n < (1 << 23) ? 1 : 0;
   if (p.wrap) {
     // n_cell <= 2: prefilter on 16-bit wrapped coordinates, unit Delta = L/2^16;
     // |u_j - u_i|^2 < tq keeps every pair within r_l,max (each axis is off by
