@@ -653,7 +653,9 @@ __device__ inline void wave_lds_sync() {
 // One home subcell of a system that rebuilds, split over G waves: gw (< G)
 // selects this wave's share of the home atoms; msk/cand are the wave's LDS
 // arrays.
-template <int D, int G, bool WR>
+// SP: sparse systems take CB rows per round (costs registers; off where the
+// body is inlined with others)
+template <int D, int G, bool WR, bool SP = true>
 __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long long* msk, int* cand) {
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
   constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
@@ -676,6 +678,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   if (h0 >= h1) return;
   const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
   const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
+  // sparse subcells (n_cell >= 3): three of them never hold more than one chunk
+  const bool sparse = SP && !WR && 3 * uniform_int(s->max_cell) <= 64;
   const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
   const int* __restrict__ qc16 = uniform_ptr(s->qc16);
   HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
@@ -896,97 +900,184 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       }
     };
 
-    for (int row = 0; row < nrow; row++) {
-      // A SIMD issues for its oldest waves first, so without this the waves
-      // of a launch finish one by one and the last ones run alone, their
-      // latencies exposed.  A wave's priority falls as it gets through its
-      // rows: the waves that lag get the issue slots, and those of a SIMD
-      // finish together.
-      set_prio_by_progress(row, nrow);
-      int Dp[HW], og[D - 1];
-      const int P = row_base(row, Dp, og);
-      // home atoms that can reach this row: gap to the neighbouring faces
-      // along the first d-1 axes, one quantisation unit short per axis
-      unsigned long long keep0, keep1;
-      {
-        int S0 = 0, S1 = 0;
+    // home atoms that can reach a row: gap to the neighbouring faces along
+    // the first d-1 axes, one quantisation unit short per axis
+    auto row_keep = [&](const int (&og)[D - 1], unsigned long long& keep0,
+                        unsigned long long& keep1) {
+      int S0 = 0, S1 = 0;
 #pragma unroll
-        for (int k = 0; k < D - 1; k++) {
-          const int o = og[k];
-          int g0, g1;
-          if (WR) {
-            g0 = o ? qh0[k] : 0;
-            g1 = o ? qh1[k] : 0;
-          } else {
-            g0 = (kQScale / 2) - o * qh0[k] - 1;
-            g1 = (kQScale / 2) - o * qh1[k] - 1;
-            g0 = (o == 0 || g0 < 0) ? 0 : g0;
-            g1 = (o == 0 || g1 < 0) ? 0 : g1;
-          }
-          S0 += g0 * g0;
-          S1 += g1 * g1;
+      for (int k = 0; k < D - 1; k++) {
+        const int o = og[k];
+        int g0, g1;
+        if (WR) {
+          g0 = o ? qh0[k] : 0;
+          g1 = o ? qh1[k] : 0;
+        } else {
+          g0 = (kQScale / 2) - o * qh0[k] - 1;
+          g1 = (kQScale / 2) - o * qh1[k] - 1;
+          g0 = (o == 0 || g0 < 0) ? 0 : g0;
+          g1 = (o == 0 || g1 < 0) ? 0 : g1;
         }
-        keep0 = __ballot(v0 && S0 < tc0);
-        keep1 = __ballot(v1 && S1 < tc1);
+        S0 += g0 * g0;
+        S1 += g1 * g1;
       }
-      if ((keep0 | keep1) == 0) continue;
-      // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
-      const int st0 = flat[P + lm];
-      const int n0 = flat[P + lm + 1] - st0;
-      const int c1 = WR ? lp : cl;
-      const int st1 = (WR && R < 2) ? 0 : flat[P + c1];
-      const int n1 = (WR && R < 2) ? 0 : flat[P + c1 + 1] - st1;
-      const int st2 = WR ? 0 : flat[P + lp];
-      const int n2 = WR ? 0 : flat[P + lp + 1] - st2;
-      const int T = n0 + n1 + n2;
-      for (int k0 = 0; k0 < T; k0 += CB * 64) {
-        const int nch = min(CB, (T - k0 + 63) / 64);
+      keep0 = __ballot(v0 && S0 < tc0);
+      keep1 = __ballot(v1 && S1 < tc1);
+    };
+    // candidate tt of a row whose subcells (stencil order) hold n0, n1 and
+    // the rest of its T atoms from st0, st1, st2: its record (an in-range
+    // atom for an empty lane) shifted by the subcell offset as packed int16
+    // adds; returns the atom, or -1 for an empty lane
+    auto cand_words = [&](int tt, int T, int st0, int n0, int st1, int n1, int st2,
+                          const int (&Dp)[HW], int (&cwc)[HW], int& tAc) -> int {
+      const bool valid = tt < T;
+      const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
+      const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
+      const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
+      const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
+      if (WR) {
+#pragma unroll
+        for (int k = 0; k < HW; k++) cwc[k] = src[k];
+        tAc = valid ? tq : -1;  // the lane's threshold; none for an empty lane
+      } else {
+        int A = 0;
+#pragma unroll
+        for (int k = 0; k < HW; k++) {
+          const short2v q2 = __builtin_bit_cast(short2v, src[k]);
+          const short2v o2 = __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
+          const short2v r2 = q2 + o2;
+          A = __builtin_amdgcn_sdot2(r2, r2, A, false);
+          cwc[k] = __builtin_bit_cast(int, r2 + r2);
+        }
+        tAc = valid ? src[6] - A : -0x3fffffff;  // never passes for an empty lane
+      }
+      return valid ? j : -1;
+    };
+    // (T_j - A_j) + q_i.(2 q'_j) > |q_i|^2 - T_i  <=>  |q'_j - q_i|^2 < T_i + T_j
+    // for the kept home atoms of both sets against nch chunks (LDS slots nb..)
+    auto test_chunks = [&](unsigned long long keep0, unsigned long long keep1, int nch,
+                           const int (&cw)[CB][HW], const int (&tA)[CB]) {
+      unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
+#pragma unroll
+      for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
+      test_set(keep0, ow0, hb, nch, cw, tA, m0lo, m0hi);
+      test_set(keep1, ow1, hb + 64, nch, cw, tA, m1lo, m1hi);
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        if (c < nch) {
+          msk[(nb + c) * 128 + lane] = ((unsigned long long)m0hi[c] << 32) | m0lo[c];
+          msk[(nb + c) * 128 + 64 + lane] = ((unsigned long long)m1hi[c] << 32) | m1lo[c];
+        }
+      }
+      nb += nch;
+    };
+
+    if (sparse) {
+      // every row fits one chunk: CB consecutive rows share a round of
+      // candidate loads and tests (the loads of all CB rows are in flight
+      // together), tested against the home atoms kept by any of them; the
+      // chunks stay in row order, so the lists and their order are those of
+      // the row-by-row walk
+      for (int row = 0; row < nrow; row += CB) {
+        set_prio_by_progress(row, nrow);
         if (nb + CB > NB) exact_pass();
-        // candidates of up to CB chunks: records (an in-range atom for the
-        // empty lanes) shifted by the subcell offset as packed int16 adds
+        // in phases, so that the scalar loads of all CB rows and then their
+        // candidate loads are issued before any of them is waited for
+        int P[CB], Dps[CB][HW];
+        unsigned long long k0m = 0, k1m = 0;
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          const bool rv = row + c < nrow;
+          int og[D - 1];
+          P[c] = row_base(rv ? row + c : row, Dps[c], og);
+          unsigned long long kp0, kp1;
+          row_keep(og, kp0, kp1);
+          k0m |= rv ? kp0 : 0ull;
+          k1m |= rv ? kp1 : 0ull;
+        }
+        if ((k0m | k1m) == 0) continue;
+        int fl[CB][6];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          fl[c][0] = flat[P[c] + lm];
+          fl[c][1] = flat[P[c] + lm + 1];
+          fl[c][2] = flat[P[c] + cl];
+          fl[c][3] = flat[P[c] + cl + 1];
+          fl[c][4] = flat[P[c] + lp];
+          fl[c][5] = flat[P[c] + lp + 1];
+        }
+        int rw[CB][HW + 1];  // the candidate's offset words and its threshold share
+        int jj[CB], lv[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          const int n0 = fl[c][1] - fl[c][0], n1 = fl[c][3] - fl[c][2];
+          const int T = row + c < nrow ? n0 + n1 + fl[c][5] - fl[c][4] : 0;
+          const bool s1 = lane >= n0, s2 = lane >= n0 + n1;
+          const int j = (s2 ? fl[c][4] - n0 - n1 : (s1 ? fl[c][2] - n0 : fl[c][0])) + lane;
+          lv[c] = s2 ? lastpp : (s1 ? 0 : lastm);
+          jj[c] = lane < T ? j : -1;
+          const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(lane < T ? j : hb) * 8);
+#pragma unroll
+          for (int k = 0; k < HW; k++) rw[c][k] = src[k];
+          rw[c][HW] = src[6];
+        }
         int cw[CB][HW], tA[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) {
-          if (c >= nch) continue;
-          const int tt = k0 + c * 64 + lane;
-          const bool valid = c < nch && tt < T;
-          const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
-          const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
-          const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
-          const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
-          if (WR) {
+          int A = 0;
 #pragma unroll
-            for (int k = 0; k < HW; k++) cw[c][k] = src[k];
-            tA[c] = valid ? tq : -1;  // the lane's threshold; none for an empty lane
-          } else {
-            int A = 0;
-#pragma unroll
-            for (int k = 0; k < HW; k++) {
-              const short2v q2 = __builtin_bit_cast(short2v, src[k]);
-              const short2v o2 =
-                  __builtin_bit_cast(short2v, Dp[k] + (k == (D - 1) / 2 ? lastv : 0));
-              const short2v r2 = q2 + o2;
-              A = __builtin_amdgcn_sdot2(r2, r2, A, false);
-              cw[c][k] = __builtin_bit_cast(int, r2 + r2);
-            }
-            tA[c] = valid ? src[6] - A : -0x3fffffff;  // never passes for an empty lane
+          for (int k = 0; k < HW; k++) {
+            const short2v q2 = __builtin_bit_cast(short2v, rw[c][k]);
+            const short2v o2 =
+                __builtin_bit_cast(short2v, Dps[c][k] + (k == (D - 1) / 2 ? lv[c] : 0));
+            const short2v r2 = q2 + o2;
+            A = __builtin_amdgcn_sdot2(r2, r2, A, false);
+            cw[c][k] = __builtin_bit_cast(int, r2 + r2);
           }
-          cand[(nb + c) * 64 + lane] = valid ? j : -1;
+          tA[c] = jj[c] >= 0 ? rw[c][HW] - A : -0x3fffffff;  // never passes for an empty lane
+          cand[(nb + c) * 64 + lane] = jj[c];
         }
-        // (T_j - A_j) + q_i.(2 q'_j) > |q_i|^2 - T_i  <=>  |q'_j - q_i|^2 < T_i + T_j
-        unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
+        test_chunks(k0m, k1m, CB, cw, tA);
+      }
+    } else {
+      for (int row = 0; row < nrow; row++) {
+        // A SIMD issues for its oldest waves first, so without this the waves
+        // of a launch finish one by one and the last ones run alone, their
+        // latencies exposed.  A wave's priority falls as it gets through its
+        // rows: the waves that lag get the issue slots, and those of a SIMD
+        // finish together.
+        set_prio_by_progress(row, nrow);
+        int Dp[HW], og[D - 1];
+        const int P = row_base(row, Dp, og);
+        unsigned long long keep0, keep1;
+        row_keep(og, keep0, keep1);
+        if ((keep0 | keep1) == 0) continue;
+        // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
+        // (all six scalar loads issued before the first is used)
+        const int c1 = WR ? lp : cl;
+        int f[6];
+        f[0] = flat[P + lm];
+        f[1] = flat[P + lm + 1];
+        f[2] = (WR && R < 2) ? 0 : flat[P + c1];
+        f[3] = (WR && R < 2) ? 0 : flat[P + c1 + 1];
+        f[4] = WR ? 0 : flat[P + lp];
+        f[5] = WR ? 0 : flat[P + lp + 1];
+        const int st0 = f[0], n0 = f[1] - f[0];
+        const int st1 = f[2], n1 = f[3] - f[2];
+        const int st2 = f[4], n2 = f[5] - f[4];
+        const int T = n0 + n1 + n2;
+        for (int k0 = 0; k0 < T; k0 += CB * 64) {
+          const int nch = min(CB, (T - k0 + 63) / 64);
+          if (nb + CB > NB) exact_pass();
+          int cw[CB][HW], tA[CB];
 #pragma unroll
-        for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
-        test_set(keep0, ow0, hb, nch, cw, tA, m0lo, m0hi);
-        test_set(keep1, ow1, hb + 64, nch, cw, tA, m1lo, m1hi);
-#pragma unroll
-        for (int c = 0; c < CB; c++) {
-          if (c < nch) {
-            msk[(nb + c) * 128 + lane] = ((unsigned long long)m0hi[c] << 32) | m0lo[c];
-            msk[(nb + c) * 128 + 64 + lane] = ((unsigned long long)m1hi[c] << 32) | m1lo[c];
+          for (int c = 0; c < CB; c++) {
+            if (c >= nch) continue;
+            cand[(nb + c) * 64 + lane] =
+                cand_words(k0 + c * 64 + lane, T, st0, n0, st1, n1, st2, Dp, cw[c], tA[c]);
           }
+          test_chunks(keep0, keep1, nch, cw, tA);
         }
-        nb += nch;
       }
     }
     exact_pass();
