@@ -169,9 +169,9 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
         const double* pw = s->part + (size_t)w * kPart;
         pe += pw[P_PE];
         ke += pw[P_KE];
-        vir += pw[P_VIR];
-        nc += pw[P_NC];
         if (rec) {
+          vir += pw[P_VIR];
+          nc += pw[P_NC];
           m2 += pw[P_M2];
           m4 += pw[P_M4];
           ov += pw[P_OV];
@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
       }
       pe = block_sum<256>(pe, sh);
       ke = block_sum<256>(ke, sh);
-      vir = block_sum<256>(vir, sh);
-      nc = block_sum<256>(nc, sh);
       if (rec) {
+        vir = block_sum<256>(vir, sh);
+        nc = block_sum<256>(nc, sh);
         m2 = block_sum<256>(m2, sh);
         m4 = block_sum<256>(m4, sh);
         ov = block_sum<256>(ov, sh);

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
 #define HDMD_CASE(DD)                                                          \
   case DD:                                                                     \
     if (wr) build_t_tile<DD, 4, true>(s, hc, wv, msk_all[wv], cand_all[wv]);   \
-    else build_t_tile<DD, 1, false, false>(s, hc, 0, msk_all[wv], cand_all[wv]); \
+    else build_t_tile<DD, 1, false>(s, hc, 0, msk_all[wv], cand_all[wv]);      \
     break;
           HDMD_BUILD_D(HDMD_CASE)
 #undef HDMD_CASE

@@ -653,9 +653,7 @@ __device__ inline void wave_lds_sync() {
 // One home subcell of a system that rebuilds, split over G waves: gw (< G)
 // selects this wave's share of the home atoms; msk/cand are the wave's LDS
 // arrays.
-// SP: sparse systems take CB rows per round (costs registers; off where the
-// body is inlined with others)
-template <int D, int G, bool WR, bool SP = true>
+template <int D, int G, bool WR>
 __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long long* msk, int* cand) {
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
   constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
@@ -678,8 +676,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   if (h0 >= h1) return;
   const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
   const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
-  // sparse subcells (n_cell >= 3): three of them never hold more than one chunk
-  const bool sparse = SP && !WR && 3 * uniform_int(s->max_cell) <= 64;
+  // sparse subcells (n_cell >= 3): three of them hold 48 atoms or fewer on average
+  const bool sparse = !WR && 3 * uniform_int(s->n) <= 48 * uniform_int(s->ncells);
   const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
   const int* __restrict__ qc16 = uniform_ptr(s->qc16);
   HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
@@ -972,12 +970,53 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       nb += nch;
     };
 
+    // one row of linked subcells, walked chunk by chunk
+    auto do_row = [&](int row) {
+      // A SIMD issues for its oldest waves first, so without this the waves
+      // of a launch finish one by one and the last ones run alone, their
+      // latencies exposed.  A wave's priority falls as it gets through its
+      // rows: the waves that lag get the issue slots, and those of a SIMD
+      // finish together.
+      set_prio_by_progress(row, nrow);
+      int Dp[HW], og[D - 1];
+      const int P = row_base(row, Dp, og);
+      unsigned long long keep0, keep1;
+      row_keep(og, keep0, keep1);
+      if ((keep0 | keep1) == 0) return;
+      // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
+      // (all six scalar loads issued before the first is used)
+      const int c1 = WR ? lp : cl;
+      int f[6];
+      f[0] = flat[P + lm];
+      f[1] = flat[P + lm + 1];
+      f[2] = (WR && R < 2) ? 0 : flat[P + c1];
+      f[3] = (WR && R < 2) ? 0 : flat[P + c1 + 1];
+      f[4] = WR ? 0 : flat[P + lp];
+      f[5] = WR ? 0 : flat[P + lp + 1];
+      const int st0 = f[0], n0 = f[1] - f[0];
+      const int st1 = f[2], n1 = f[3] - f[2];
+      const int st2 = f[4], n2 = f[5] - f[4];
+      const int T = n0 + n1 + n2;
+      for (int k0 = 0; k0 < T; k0 += CB * 64) {
+        const int nch = min(CB, (T - k0 + 63) / 64);
+        if (nb + CB > NB) exact_pass();
+        int cw[CB][HW], tA[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          if (c >= nch) continue;
+          cand[(nb + c) * 64 + lane] =
+              cand_words(k0 + c * 64 + lane, T, st0, n0, st1, n1, st2, Dp, cw[c], tA[c]);
+        }
+        test_chunks(keep0, keep1, nch, cw, tA);
+      }
+    };
+
     if (sparse) {
-      // every row fits one chunk: CB consecutive rows share a round of
+      // CB consecutive rows that each fit one chunk share a round of
       // candidate loads and tests (the loads of all CB rows are in flight
       // together), tested against the home atoms kept by any of them; the
       // chunks stay in row order, so the lists and their order are those of
-      // the row-by-row walk
+      // the row-by-row walk, which a group with a longer row takes instead
       for (int row = 0; row < nrow; row += CB) {
         set_prio_by_progress(row, nrow);
         if (nb + CB > NB) exact_pass();
@@ -1005,6 +1044,14 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           fl[c][3] = flat[P[c] + cl + 1];
           fl[c][4] = flat[P[c] + lp];
           fl[c][5] = flat[P[c] + lp + 1];
+        }
+        int tmx = 0;
+#pragma unroll
+        for (int c = 0; c < CB; c++) tmx = max(tmx, fl[c][1] - fl[c][0] + fl[c][3] - fl[c][2] + fl[c][5] - fl[c][4]);
+        if (tmx > 64) {
+#pragma unroll 1
+          for (int c = 0; c < CB && row + c < nrow; c++) do_row(row + c);
+          continue;
         }
         int rw[CB][HW + 1];  // the candidate's offset words and its threshold share
         int jj[CB], lv[CB];
@@ -1040,45 +1087,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         test_chunks(k0m, k1m, CB, cw, tA);
       }
     } else {
-      for (int row = 0; row < nrow; row++) {
-        // A SIMD issues for its oldest waves first, so without this the waves
-        // of a launch finish one by one and the last ones run alone, their
-        // latencies exposed.  A wave's priority falls as it gets through its
-        // rows: the waves that lag get the issue slots, and those of a SIMD
-        // finish together.
-        set_prio_by_progress(row, nrow);
-        int Dp[HW], og[D - 1];
-        const int P = row_base(row, Dp, og);
-        unsigned long long keep0, keep1;
-        row_keep(og, keep0, keep1);
-        if ((keep0 | keep1) == 0) continue;
-        // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
-        // (all six scalar loads issued before the first is used)
-        const int c1 = WR ? lp : cl;
-        int f[6];
-        f[0] = flat[P + lm];
-        f[1] = flat[P + lm + 1];
-        f[2] = (WR && R < 2) ? 0 : flat[P + c1];
-        f[3] = (WR && R < 2) ? 0 : flat[P + c1 + 1];
-        f[4] = WR ? 0 : flat[P + lp];
-        f[5] = WR ? 0 : flat[P + lp + 1];
-        const int st0 = f[0], n0 = f[1] - f[0];
-        const int st1 = f[2], n1 = f[3] - f[2];
-        const int st2 = f[4], n2 = f[5] - f[4];
-        const int T = n0 + n1 + n2;
-        for (int k0 = 0; k0 < T; k0 += CB * 64) {
-          const int nch = min(CB, (T - k0 + 63) / 64);
-          if (nb + CB > NB) exact_pass();
-          int cw[CB][HW], tA[CB];
-#pragma unroll
-          for (int c = 0; c < CB; c++) {
-            if (c >= nch) continue;
-            cand[(nb + c) * 64 + lane] =
-                cand_words(k0 + c * 64 + lane, T, st0, n0, st1, n1, st2, Dp, cw[c], tA[c]);
-          }
-          test_chunks(keep0, keep1, nch, cw, tA);
-        }
-      }
+      for (int row = 0; row < nrow; row++) do_row(row);
     }
     exact_pass();
     if (v0) {
