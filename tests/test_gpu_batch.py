@@ -95,21 +95,22 @@ def test_fire_mix_equals_alone(prec):
 
 def test_md_mix_equals_alone():
     """Classes holding systems of both precision forms (d = 4) and of both
-    potential classes (d = 3) take one step launch per kind."""
+    potential classes (d = 3) take one step launch per kind; a slot with the
+    Berendsen thermostat (d = 5) runs as it does alone."""
     W, M = H.HDMD_WCA, H.HDMD_MORSE
-    cases = [(3, 8, 1.12, 1, H.HDMD_FP64, W), (4, 5, 1.1, 2, H.HDMD_FP64, W),
-             (6, 4, 1.05, 3, H.HDMD_FP64, W), (4, 5, 1.12, 4, H.HDMD_MIXED, W),
-             (3, 8, 1.15, 5, H.HDMD_FP64, M)]
+    cases = [(3, 8, 1.12, 1, H.HDMD_FP64, W, 0.0), (4, 5, 1.1, 2, H.HDMD_FP64, W, 0.0),
+             (6, 4, 1.05, 3, H.HDMD_FP64, W, 0.0), (4, 5, 1.12, 4, H.HDMD_MIXED, W, 0.0),
+             (3, 8, 1.15, 5, H.HDMD_FP64, M, 0.0), (5, 4, 1.1, 6, H.HDMD_FP64, W, 0.05)]
     nsteps, dt = 60, 0.003
     alone, states = [], []
-    for d, m, a, seed, prec, pot in cases:
+    for d, m, a, seed, prec, pot, tau in cases:
         x, L = inputs.jittered_lattice(d, m, a, (0.12 if pot == W else 0.02) * a, seed)
         n = len(x)
         sig = inputs.bidisperse(n, 1.0, 1.2 if pot == W else 1.1, seed)
         v = inputs.gaussian_velocities(n, d, 1.0 if pot == W else 0.25, seed + 1)
         sysd = H.System(d=d, n=n, box_l=L, potential=pot,
                         cutoff=inputs.WCA_CUT if pot == W else 1.0, skin=0.3, sigma_max=1.2,
-                        precision=prec, max_neighbors=64)
+                        precision=prec, max_neighbors=64, thermostat_tau=tau, target_temp=0.4)
         sysd, _ = H.build_with_width(sysd, dev(x), dev(sig), slack=2.0)
         ws = H.workspace(sysd)
         X, V = dev(x), dev(v)
