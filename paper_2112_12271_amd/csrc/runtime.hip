@@ -331,11 +331,15 @@ static KArgs single_args(SysDev* dev, int d) {
 static void chain_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
   const DKernels* K = dkernels(p.d);
   KArgs a = single_args(dev, p.d);
-  K->bin(a, p.ntiles, st);
+  // the binning, placement and subcell-sort grids stride over their tiles:
+  // at most 1024 workgroups, so that the launches of steps without a rebuild
+  // (which exit at once) dispatch few of them
+  const int gt = std::min(p.ntiles, 1024), gc = std::min(p.ncells, 1024);
+  K->bin(a, gt, st);
   launch_scan1(a, p.nchunks, st);
   launch_scan2(a, 1, st);
-  launch_scatter(a, p.ntiles, st);
-  K->cellsort(p.mix, a, p.ncells, st);
+  launch_scatter(a, gt, st);
+  K->cellsort(p.mix, a, gc, st);
   K->build(p.wrap, blk, a, p.ncells, st);
 }
 
