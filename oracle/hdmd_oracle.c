@@ -352,6 +352,61 @@ double orc_forces(int d, int64_t n, double L, const double* x, const double* sig
   return etot;
 }
 
+/* Energy of atom i with every other atom (brute force over all n), with i
+ * given diameter si and the atoms a and b given diameters sa and sb instead
+ * of their own (a, b < 0: none): sum_k U(r_ik, (si + s_k)/2) inside the
+ * cutoff c (si + s_k)/2. */
+static double swap_energy(int d, int64_t n, double L, const double* x, const double* sig, int pot,
+                          double c, double eps, int64_t i, double si, int64_t a, double sa,
+                          int64_t b, double sb) {
+  double e = 0.0;
+  for (int64_t k = 0; k < n; k++) {
+    if (k == i) continue;
+    const double sk = k == a ? sa : (k == b ? sb : sig[k]);
+    const double sij = 0.5 * (si + sk);
+    const double rc = c * sij;
+    const double r2 = dist2(d, x + i * d, x + k * d, L);
+    if (!(r2 < rc * rc)) continue;
+    double fc;
+    e += pair(pot, r2, sij, eps, &fc);
+  }
+  return e;
+}
+
+/* SWAP Monte Carlo (Sec. II.D): attempts k = 0 .. n_att-1 in order, each
+ * exchanging the diameters of atoms i = pairs[2k] and j = pairs[2k+1] with
+ * the diameters left by the earlier attempts.  The energy of the
+ * interactions that involve i or j is summed before (eq. ebefore, E_b) and
+ * after (E_a) the exchange, each sum over i's partners plus j's partners;
+ * the pair i-j itself keeps its diameter sigma_ij and cancels.  The swap is
+ * kept on the Metropolis rule: dE = E_a - E_b <= 0, or u_k < exp(-dE / T).
+ * Unit masses: the kinetic energy is unchanged and no velocity is rescaled.
+ * sig is updated in place; accepted[k] (optional) gets 1 or 0 and dE[k]
+ * (optional) the energy change.  Returns the number of accepted swaps. */
+int64_t orc_swap(int d, int64_t n, double L, const double* x, double* sig, int pot, double c,
+                 double eps, int64_t n_att, const int32_t* pairs, const double* u, double T,
+                 int32_t* accepted, double* dE) {
+  int64_t nacc = 0;
+  for (int64_t k = 0; k < n_att; k++) {
+    const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+    const double si = sig[i], sj = sig[j];
+    const double eb = swap_energy(d, n, L, x, sig, pot, c, eps, i, si, -1, 0.0, -1, 0.0) +
+                      swap_energy(d, n, L, x, sig, pot, c, eps, j, sj, -1, 0.0, -1, 0.0);
+    const double ea = swap_energy(d, n, L, x, sig, pot, c, eps, i, sj, j, si, -1, 0.0) +
+                      swap_energy(d, n, L, x, sig, pot, c, eps, j, si, i, sj, -1, 0.0);
+    const double de = i == j ? 0.0 : ea - eb;
+    const int acc = de <= 0.0 || u[k] < exp(-de / T);
+    if (acc) {
+      sig[i] = sj;
+      sig[j] = si;
+      nacc++;
+    }
+    if (accepted) accepted[k] = acc;
+    if (dE) dE[k] = de;
+  }
+  return nacc;
+}
+
 /* The virial and the coordination number of getthermo (Sec. II.E) from a
  * full CSR list: out[0] = W = sum over pairs i<j inside the cutoff of
  * r_ij . F_ij = fcoef r^2 (so that P = (2 KE + W) / (d V)); out[1] = Z, the

@@ -109,6 +109,9 @@ def lib():
         L.orc_vv.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
                              C.c_double, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
                              C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_swap.restype = C.c_int64
+        L.orc_swap.argtypes = [C.c_int, C.c_int64, C.c_double, _dp, _dp, C.c_int, C.c_double,
+                               C.c_double, C.c_int64, _i32p, _dp, C.c_double, _i32p, _dp]
         L.orc_van_hove.restype = None
         L.orc_van_hove.argtypes = [C.c_int, C.c_int64, _dp, C.c_int32, C.c_double, _i64p]
         L.orc_disp_moments.restype = None
@@ -226,6 +229,20 @@ def vv(x, v, sig, L, pot, c, s, eps, nsteps, dt, obs=False, tau=0.0, T0=0.0):
                      ob.ctypes.data_as(C.c_void_p) if obs else None,
                      dr.ctypes.data_as(C.c_void_p) if obs else None)
     return (x, v, th, b, ob, dr) if obs else (x, v, th, b)
+
+
+def swap(x, sig, L, pot, c, eps, pairs, u, T):
+    """SWAP Monte Carlo attempts in order (Sec. II.D); returns (new diameters,
+    accepted flags, energy changes dE, number accepted)."""
+    x = _f64(x)
+    n, d = x.shape
+    sig = _f64(sig).copy()
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    m = len(pairs)
+    acc = np.zeros(m, dtype=np.int32)
+    de = np.zeros(m)
+    na = lib().orc_swap(d, n, L, x, sig, pot, c, eps, m, pairs.ravel(), _f64(u), T, acc, de)
+    return sig, acc, de, na
 
 
 def van_hove(dr, nbins, w):
