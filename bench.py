@@ -262,6 +262,28 @@ def fire_record(res, wall):
     return rec
 
 
+def swap_leg(H, torch, cfg, x, sig, L, m):
+    """SWAP Monte Carlo (Sec. II.D) on the relaxed MD state: m attempts on
+    seeded random pairs at the run's temperature, serial as the method
+    defines them (one wave walks them in order); attempts per second."""
+    g = np.random.default_rng(7)
+    pairs = torch.as_tensor(g.integers(0, cfg.n, size=(m, 2)).astype(np.int32), device="cuda")
+    u = torch.as_tensor(g.uniform(size=m), dtype=torch.float64, device="cuda")
+    X = torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    s = H.System(d=cfg.d, n=cfg.n, box_l=L, potential=cfg.potential, cutoff=cfg.cutoff,
+                 skin=cfg.skin, sigma_max=float(sig.max()))
+    s, ws = H.build_with_width(s, X, torch.as_tensor(sig, dtype=torch.float64, device="cuda"))
+    D = torch.as_tensor(sig, dtype=torch.float64, device="cuda")
+    H.hdmd_swap(s, X, D.clone(), ws, pairs[:16], u[:16], cfg.T)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, na = H.hdmd_swap(s, X, D, ws, pairs, u, cfg.T)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    return {"attempts": m, "accepted": na, "seconds": sec, "attempts_per_s": m / sec,
+            "temperature": cfg.T, "note": "wall time of hdmd_swap, including its list build"}
+
+
 def fire_serving(H, torch, args):
     """Batched mixed-precision FIRE over the whole request stream through the
     continuous-batching server, then the comparison at equal final |F|max on a
@@ -320,6 +342,8 @@ def main():
     ap.add_argument("--fire-budget-gb", type=float, default=64.0)
     ap.add_argument("--fire-chunk", type=int, default=50)
     ap.add_argument("--no-md", action="store_true", help="skip the MD legs (FIRE serving only)")
+    ap.add_argument("--swap-attempts", type=int, default=2000,
+                    help="SWAP Monte Carlo attempts timed on the relaxed MD state (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (scales the HBM "
                          "byte counters of a profiler to bytes)")
@@ -388,6 +412,9 @@ def main():
                            share_build_kernel=st.build_kernel_ms / (1e3 * r["seconds"]))
             out[name] = rec
             log(name, json.dumps(rec))
+        if args.swap_attempts > 0:
+            out["swap"] = swap_leg(H, torch, cfg, xr, sig, L, args.swap_attempts)
+            log("swap", json.dumps(out["swap"]))
     fire = None
     if not args.no_fire:
         fire = fire_serving(H, torch, args)
@@ -441,6 +468,7 @@ def main():
         "drift_difference_mixed_minus_fp64": (out["mixed"]["drift_per_tau"] - f["drift_per_tau"])
         if "mixed" in out and f else None,
         "fire_serving": fire,
+        "swap": out.get("swap"),
     }
     print(json.dumps(line), flush=True)
 

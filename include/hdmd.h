@@ -194,6 +194,23 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
 int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbins,
                   double bin_width, int64_t* hist, double* disp, void* stream);
 
+/* SWAP Monte Carlo (Sec. II.D): n_att attempts, in order, each exchanging
+ * the diameters of atoms pairs[2k] and pairs[2k+1] (caller ids, int32,
+ * device).  With the diameters the earlier attempts left, dE = E_a - E_b is
+ * the change of the energy of every pair that involves either atom (eq.
+ * ebefore; their mutual pair keeps its diameter and cancels), and the swap is
+ * kept when dE <= 0 or u[k] < exp(-dE / temperature) (Metropolis; u: n_att
+ * uniforms in [0, 1), FP64, device, drawn by the caller).  Masses are 1, so
+ * velocities need no rescaling.  pos ([n][d] FP64, device) is read; diam
+ * ([n] FP64, device) is updated in place; accepted (n_att int32, device,
+ * optional) receives 1 or 0 per attempt and *n_accepted (host) the count.
+ * The attempts run serially on one wave, as the paper runs them on one
+ * thread.  Errors: HDMD_ERR_ARG (an id outside [0, n), temperature <= 0, ...),
+ * HDMD_ERR_WORKSPACE and the load errors of hdmd_build_nlist.  Synchronises. */
+int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
+              int64_t n_att, const int32_t* pairs, const double* u, double temperature,
+              int32_t* accepted, int64_t* n_accepted, void* stream);
+
 /* FIRE 2.0 energy minimisation with the semi-implicit Euler update (Sec.
  * II.B), unit masses, global norms: pos ([n][d] FP64, device) in and out.
  * Synchronises. */

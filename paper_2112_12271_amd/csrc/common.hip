@@ -395,6 +395,16 @@ void launch_finalize(const KArgs& a, int grid, hipStream_t st) {
 void launch_fire_ctrl(const KArgs& a, int grid, hipStream_t st) {
   k_fire_ctrl<<<grid, 256, 0, st>>>(a);
 }
+// slot_of[caller id] = position in subcell order
+__global__ __launch_bounds__(256) void k_slot_of(const SysDev* s, int32_t* slot_of) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < s->n) slot_of[s->oid[s->pcur][p]] = p;
+}
+
+void launch_slot_of(const SysDev* s, int n, int32_t* slot_of, hipStream_t st) {
+  k_slot_of<<<(n + 255) / 256, 256, 0, st>>>(s, slot_of);
+}
+
 void launch_reduce_pe(const SysDev* s, double* out, hipStream_t st) {
   k_reduce_pe<<<1, 256, 0, st>>>(s, out);
 }

@@ -22,6 +22,8 @@ struct DKernels {
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
   void (*vanhove)(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
                   unsigned long long* hist, double* disp);
+  void (*swap)(SysDev* s, hipStream_t st, int n_att, const int32_t* pairs, const double* u,
+               double T, const int32_t* slot_of, int32_t* acc, double* diam, long long* nacc);
 };
 
 const DKernels* dkernels(int d);
@@ -46,6 +48,7 @@ void launch_scatter(const KArgs& a, int grid, hipStream_t st);
 void launch_finalize(const KArgs& a, int grid, hipStream_t st);
 void launch_fire_ctrl(const KArgs& a, int grid, hipStream_t st);
 void launch_reduce_pe(const SysDev* s, double* out, hipStream_t st);
+void launch_slot_of(const SysDev* s, int n, int32_t* slot_of, hipStream_t st);
 void launch_export(const SysDev* s, int n, int64_t* row_ptr, int32_t* cols, hipStream_t st,
                    int phase);
 void launch_set_status(SysDev* s, int32_t status, hipStream_t st);

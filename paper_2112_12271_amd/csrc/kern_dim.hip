@@ -88,8 +88,12 @@ void l_vanhove(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
                unsigned long long* hist, double* disp) {
   k_vanhove<D><<<grid, kTile, 0, st>>>(s, nbins, w, hist, disp);
 }
+void l_swap(SysDev* s, hipStream_t st, int n_att, const int32_t* pairs, const double* u, double T,
+            const int32_t* slot_of, int32_t* acc, double* diam, long long* nacc) {
+  k_swap<D><<<1, 1024, 0, st>>>(s, n_att, pairs, u, T, slot_of, acc, diam, nacc);
+}
 const DKernels table = {l_load, l_unload, l_bin, l_cellsort, l_build, l_force, l_step,
-                        l_fire_update, l_vanhove};
+                        l_fire_update, l_vanhove, l_swap};
 }  // namespace
 
 #define HDMD_CAT2(a, b) a##b

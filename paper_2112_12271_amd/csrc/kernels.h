@@ -11,6 +11,7 @@
 //  k_fire_update semi-implicit Euler FIRE update
 //  k_unload      internal -> caller order
 //  k_vanhove     unwrapped displacements and the self van Hove histogram
+//  k_swap        SWAP Monte Carlo attempts in order (Sec. II.D)
 #pragma once
 #include <type_traits>
 
@@ -1173,6 +1174,148 @@ __device__ inline void pair_f64(int pot, double eps, double ma, double r2, doubl
     fc = eps * g * is * ir;
     u = 0.5 * eps * g * g;
   }
+}
+
+// SWAP Monte Carlo (Sec. II.D): the attempts in their order, by one
+// workgroup (each attempt sees the diameters the earlier ones left).  Attempt k
+// exchanges the diameters of the atoms with caller ids pairs[2k] and
+// pairs[2k+1]; the energies before and after (eq. ebefore) sum the pair
+// terms of both atoms with every partner inside the cutoff, found in the
+// linked subcells of each atom's subcell (all subcells when n_cell <= 2),
+// shared by the waves, the lanes striding over a subcell's atoms, and summed
+// in a fixed order; the pair of the two atoms keeps
+// its diameter and cancels.  Kept on the Metropolis rule dE <= 0 or
+// u_k < exp(-dE/T).  Diameters live in the records (read past the L1, as a
+// kept swap rewrites them) and are written to diam (caller order).
+__device__ inline double sig_get(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void sig_put(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void k_swap(SysDev* s, int n_att, const int32_t* __restrict__ pairs,
+                                               const double* __restrict__ u, double T,
+                                               const int32_t* __restrict__ slot_of,
+                                               int32_t* __restrict__ acc, double* __restrict__ diam,
+                                               long long* __restrict__ nacc) {
+  constexpr int DR = Dims<D>::DR;
+  __shared__ double red[2][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int nc = s->ncell;
+  const double L = s->L, h = s->hL, cut = s->cutoff, eps = s->eps, ma = s->morse_a;
+  const int pot = s->potential;
+  const bool morse = pot == kPotMorse;
+  double* xb = s->x[s->xcur];
+  const int* flat = s->cell_flat;
+  int nst = 1;
+  for (int k = 0; k < D; k++) nst *= nc <= 2 ? nc : 3;
+  long long kept = 0;
+  for (int k = 0; k < n_att; k++) {
+    const int ci = pairs[2 * k], cj = pairs[2 * k + 1];
+    const int pi = slot_of[ci], pj = slot_of[cj];
+    const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
+    double eb = 0.0, ea = 0.0;
+    if (pi != pj) {
+      for (int side = 0; side < 2; side++) {
+        const int p = side ? pj : pi, o = side ? pi : pj;
+        const double sa = side ? sj : si, sb = side ? si : sj;  // p's diameter before, after
+        double xp[D];
+        load_x<D>(xb, p, xp);
+        int cd[D];
+        {
+          int r = flat_cell<D>(s, xp);
+          for (int a = D - 1; a >= 0; a--) {
+            cd[a] = r % nc;
+            r /= nc;
+          }
+        }
+        // the waves take groups of 64 linked subcells; a group's bounds are
+        // loaded by its lanes at once, then its subcells are walked in turn
+        for (int t0 = wv * 64; t0 < nst; t0 += 64 * nwv) {
+          int cs = 0, ce = 0;
+          const int t = t0 + lane;
+          if (t < nst) {
+            int cell = 0, r = t, mult = 1;
+            for (int a = D - 1; a >= 0; a--) {
+              int ca;
+              if (nc <= 2) {
+                ca = r % nc;
+                r /= nc;
+              } else {
+                ca = cd[a] + r % 3 - 1;
+                r /= 3;
+                ca = ca < 0 ? ca + nc : (ca >= nc ? ca - nc : ca);
+              }
+              cell += ca * mult;
+              mult *= nc;
+            }
+            cs = flat[cell];
+            ce = flat[cell + 1];
+          }
+          const int ng = min(64, nst - t0);
+          for (int g = 0; g < ng; g++) {
+            const int q1 = __builtin_amdgcn_readlane(ce, g);
+            for (int q = __builtin_amdgcn_readlane(cs, g) + lane; q < q1; q += 64) {
+              if (q == p) continue;
+              double xq[D];
+              load_x<D>(xb, q, xq);
+              const double sq = sig_get(xb + (size_t)q * DR + D);
+              double r2 = 0.0;
+              for (int a = 0; a < D; a++) {
+                const double dx = min_image(xq[a] - xp[a], L, h);
+                r2 = __builtin_fma(dx, dx, r2);
+              }
+              double fc, uu;
+              const double s_b = 0.5 * (sa + sq);
+              if (r2 < (cut * s_b) * (cut * s_b)) {
+                if (morse) pair_f64<true>(pot, eps, ma, r2, s_b, fc, uu);
+                else pair_f64<false>(pot, eps, ma, r2, s_b, fc, uu);
+                eb += uu;
+              }
+              // after the exchange the partner carries p's old diameter
+              const double s_a = 0.5 * (sb + (q == o ? sa : sq));
+              if (r2 < (cut * s_a) * (cut * s_a)) {
+                if (morse) pair_f64<true>(pot, eps, ma, r2, s_a, fc, uu);
+                else pair_f64<false>(pot, eps, ma, r2, s_a, fc, uu);
+                ea += uu;
+              }
+            }
+          }
+        }
+      }
+    }
+    // wave sums, then the waves' sums in wave order (deterministic)
+    eb = wave_sum(eb);
+    ea = wave_sum(ea);
+    if (lane == 0) {
+      red[0][wv] = eb;
+      red[1][wv] = ea;
+    }
+    __syncthreads();
+    eb = 0.0;
+    ea = 0.0;
+    for (int w = 0; w < nwv; w++) {
+      eb += red[0][w];
+      ea += red[1][w];
+    }
+    const double de = pi == pj ? 0.0 : ea - eb;
+    const bool ok = de <= 0.0 || u[k] < exp(-de / T);
+    if (ok) kept++;
+    if (threadIdx.x == 0) {
+      if (ok) {
+        sig_put(xb + (size_t)pi * DR + D, sj);
+        sig_put(xb + (size_t)pj * DR + D, si);
+        diam[ci] = sj;
+        diam[cj] = si;
+      }
+      if (acc) acc[k] = ok ? 1 : 0;
+      __threadfence();  // the new diameters reach L2 before the next attempt
+    }
+    __syncthreads();  // every wave has read red[] and sees the new diameters
+  }
+  if (threadIdx.x == 0) *nacc = kept;
 }
 
 // Own atom's data as the force loop needs it.

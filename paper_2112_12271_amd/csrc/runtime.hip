@@ -736,6 +736,48 @@ int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbi
   return HDMD_OK;
 }
 
+int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
+              int64_t n_att, const int32_t* pairs, const double* u, double temperature,
+              int32_t* accepted, int64_t* n_accepted, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!pos || !diam || !n_accepted) return fail(HDMD_ERR_ARG, "null pointer");
+  if (n_att < 0 || n_att > INT32_MAX) return fail(HDMD_ERR_ARG, "n_att out of range");
+  if (n_att > 0 && (!pairs || !u)) return fail(HDMD_ERR_ARG, "null pairs or uniforms");
+  if (!(temperature > 0) || !std::isfinite(temperature))
+    return fail(HDMD_ERR_ARG, "temperature must be > 0");
+  hipStream_t st = S(stream);
+  // every attempt names two atoms of the system (checked before any launch)
+  std::vector<int32_t> hp((size_t)n_att * 2);
+  if (n_att > 0) {
+    HIPCHK(hipMemcpyAsync(hp.data(), pairs, hp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int32_t v : hp)
+      if (v < 0 || v >= p.n) return fail(HDMD_ERR_ARG, "swap pair names an atom outside [0, n)");
+  }
+  rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr);
+  if (rc) return rc;
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  SysDev h;
+  rc = read_desc(dev, &h, st);
+  if (rc) return rc;
+  rc = err_to_status(h.err, "hdmd_swap");
+  if (rc) return rc;
+  *n_accepted = 0;
+  if (n_att == 0) return HDMD_OK;
+  int32_t* slot_of = at<int32_t>(ws, p.off_src);   // free outside a rebuild
+  long long* nacc = at<long long>(ws, p.off_part);  // free outside a step
+  launch_slot_of(dev, p.n, slot_of, st);
+  dkernels(p.d)->swap(dev, st, (int)n_att, pairs, u, temperature, slot_of, accepted, diam, nacc);
+  HIPCHK(hipGetLastError());
+  long long k = 0;
+  HIPCHK(hipMemcpyAsync(&k, nacc, sizeof(k), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *n_accepted = k;
+  return HDMD_OK;
+}
+
 static void set_fire(SysDev& h, const hdmd_fire_params* fp) {
   h.mode = MODE_FIRE;
   h.fc.dt0 = fp->dt0;

@@ -90,6 +90,8 @@ _SIGS = {
                             C.c_double, C.c_int64, _vp, C.POINTER(hdmd_step_stats), _vp]),
     "hdmd_van_hove": (C.c_int, [C.POINTER(hdmd_system), _vp, C.c_size_t, C.c_int32, C.c_double,
                                 _vp, _vp, _vp]),
+    "hdmd_swap": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t, C.c_int64, _vp, _vp,
+                            C.c_double, _vp, C.POINTER(C.c_int64), _vp]),
     "hdmd_fire_minimize": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t,
                                      C.POINTER(hdmd_fire_params), C.POINTER(hdmd_fire_result), _vp]),
     "hdmd_batch_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int64]),
@@ -276,6 +278,23 @@ def hdmd_van_hove(sys: System, ws, nbins: int, bin_width: float, disp: bool = Fa
                              _ptr(hist), _ptr(dr), _stream(stream))
     _check(rc, "hdmd_van_hove")
     return hist, dr
+
+
+def hdmd_swap(sys: System, pos, diam, ws, pairs, u, temperature: float, stream=None):
+    """SWAP Monte Carlo attempts in order on the device (diam updated in place).
+    pairs: (m, 2) int32 caller ids, u: m uniforms (device tensors).
+    Returns (accepted flags (m,) int32, number accepted)."""
+    m = int(pairs.shape[0]) if pairs is not None else 0
+    acc = torch.zeros(m, dtype=torch.int32, device=ws.device)
+    na = C.c_int64(0)
+    if m:
+        assert pairs.dtype == torch.int32 and pairs.is_contiguous() and pairs.shape[1] == 2
+    rc = lib().hdmd_swap(C.byref(sys.c()), _ptr(_dev_f64(pos, "pos")), _ptr(_dev_f64(diam, "diam")),
+                         _ptr(ws), ws.numel(), m, _ptr(pairs) if m else None,
+                         _ptr(_dev_f64(u, "u")) if m else None, temperature, _ptr(acc) if m else None,
+                         C.byref(na), _stream(stream))
+    _check(rc, "hdmd_swap")
+    return acc, int(na.value)
 
 
 def step_auto(sys: System, pos, vel, diam, nsteps: int, dt: float, thermo_every: int = 0,
