@@ -264,8 +264,9 @@ def fire_record(res, wall):
 
 def swap_leg(H, torch, cfg, x, sig, L, m):
     """SWAP Monte Carlo (Sec. II.D) on the relaxed MD state: m attempts on
-    seeded random pairs at the run's temperature, serial as the method
-    defines them (one wave walks them in order); attempts per second."""
+    seeded random pairs at the run's temperature, with the outcome of the
+    serial walk the method defines (batches of attempts, settled in order);
+    attempts per second."""
     g = np.random.default_rng(7)
     pairs = torch.as_tensor(g.integers(0, cfg.n, size=(m, 2)).astype(np.int32), device="cuda")
     u = torch.as_tensor(g.uniform(size=m), dtype=torch.float64, device="cuda")
@@ -342,7 +343,7 @@ def main():
     ap.add_argument("--fire-budget-gb", type=float, default=64.0)
     ap.add_argument("--fire-chunk", type=int, default=50)
     ap.add_argument("--no-md", action="store_true", help="skip the MD legs (FIRE serving only)")
-    ap.add_argument("--swap-attempts", type=int, default=2000,
+    ap.add_argument("--swap-attempts", type=int, default=20000,
                     help="SWAP Monte Carlo attempts timed on the relaxed MD state (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (scales the HBM "

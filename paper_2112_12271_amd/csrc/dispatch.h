@@ -22,8 +22,13 @@ struct DKernels {
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
   void (*vanhove)(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
                   unsigned long long* hist, double* disp);
-  void (*swap)(SysDev* s, hipStream_t st, int n_att, const int32_t* pairs, const double* u,
-               double T, const int32_t* slot_of, int32_t* acc, double* diam, long long* nacc);
+  // SWAP Monte Carlo: dE of a batch, then its settlement (kernels.h)
+  void (*swap_de)(const SysDev* s, hipStream_t st, const int32_t* todo, int nb, const int32_t* pairs,
+                  const int32_t* slot_of, double* de);
+  void (*swap_settle)(SysDev* s, hipStream_t st, const int32_t* todo_in, int n_todo, int nb,
+                      int32_t* todo_out, const int32_t* pairs, const double* u, double T,
+                      const int32_t* slot_of, const double* de, int32_t* acc, double* diam,
+                      long long* ctl);
 };
 
 const DKernels* dkernels(int d);

@@ -45,6 +45,7 @@ constexpr int kPart = 11;       // doubles per wave in the partial-sum array
 constexpr int kThermoCols = 10;
 constexpr int kMaxSlots = 1024;
 constexpr int kQCap = 16;       // per-lane prefilter queue of the build
+constexpr int kSwapBatch = 256;   // SWAP attempts per batch (a multiple of 64)
 constexpr int kPotMorse = 2;     // hdmd_system.potential of the Morse form
 constexpr int kQScale = 250;    // int8 quantisation: subcell side = 250 units
 

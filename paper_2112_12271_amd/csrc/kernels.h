@@ -11,7 +11,7 @@
 //  k_fire_update semi-implicit Euler FIRE update
 //  k_unload      internal -> caller order
 //  k_vanhove     unwrapped displacements and the self van Hove histogram
-//  k_swap        SWAP Monte Carlo attempts in order (Sec. II.D)
+//  k_swap_de, k_swap_settle  SWAP Monte Carlo in batches (Sec. II.D)
 #pragma once
 #include <type_traits>
 
@@ -1176,17 +1176,22 @@ __device__ inline void pair_f64(int pot, double eps, double ma, double r2, doubl
   }
 }
 
-// SWAP Monte Carlo (Sec. II.D): the attempts in their order, by one
-// workgroup (each attempt sees the diameters the earlier ones left).  Attempt k
-// exchanges the diameters of the atoms with caller ids pairs[2k] and
-// pairs[2k+1]; the energies before and after (eq. ebefore) sum the pair
-// terms of both atoms with every partner inside the cutoff, found in the
-// linked subcells of each atom's subcell (all subcells when n_cell <= 2),
-// shared by the waves, the lanes striding over a subcell's atoms, and summed
-// in a fixed order; the pair of the two atoms keeps
-// its diameter and cancels.  Kept on the Metropolis rule dE <= 0 or
-// u_k < exp(-dE/T).  Diameters live in the records (read past the L1, as a
-// kept swap rewrites them) and are written to diam (caller order).
+// SWAP Monte Carlo (Sec. II.D).  Attempt k exchanges the diameters of the
+// atoms with caller ids pairs[2k] and pairs[2k+1]; the energies before and
+// after (eq. ebefore) sum the pair terms of both atoms with every partner
+// inside the cutoff; the pair of the two atoms keeps its diameter and
+// cancels.  Kept on the Metropolis rule dE <= 0 or u_k < exp(-dE/T).
+// The attempts keep their serial meaning (each sees the diameters the
+// earlier ones left) but run in batches: every attempt of a batch gets its
+// dE from the diameters at the batch's start (one workgroup each), then one
+// workgroup walks the batch in order and settles an attempt unless an
+// earlier attempt of the batch that was kept or put off involves an atom
+// within the interaction range c sigma_max of one of its atoms (then its dE
+// could differ: it is put off to the next batch, ahead of the unbatched
+// ones).  Settled attempts commute with the put-off ones they do not touch,
+// so the outcome is that of the serial walk.  Diameters live in the records
+// (read past the L1, as a kept swap rewrites them) and in diam (caller
+// order).
 __device__ inline double sig_get(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1194,14 +1199,15 @@ __device__ inline void sig_put(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// dE of exchanging the diameters of the atoms in slots pi and pj, with the
+// current diameters, by a whole workgroup of up to 16 waves: the linked
+// subcells of each atom's subcell (all subcells when n_cell <= 2) in groups
+// of 64 per wave (a group's bounds loaded by its lanes at once), the lanes
+// striding over a subcell's atoms, the wave sums added in wave order.
+// Every thread returns the same value.
 template <int D>
-__global__ __launch_bounds__(1024) void k_swap(SysDev* s, int n_att, const int32_t* __restrict__ pairs,
-                                               const double* __restrict__ u, double T,
-                                               const int32_t* __restrict__ slot_of,
-                                               int32_t* __restrict__ acc, double* __restrict__ diam,
-                                               long long* __restrict__ nacc) {
+__device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[16]) {
   constexpr int DR = Dims<D>::DR;
-  __shared__ double red[2][16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int nc = s->ncell;
   const double L = s->L, h = s->hL, cut = s->cutoff, eps = s->eps, ma = s->morse_a;
@@ -1211,111 +1217,194 @@ __global__ __launch_bounds__(1024) void k_swap(SysDev* s, int n_att, const int32
   const int* flat = s->cell_flat;
   int nst = 1;
   for (int k = 0; k < D; k++) nst *= nc <= 2 ? nc : 3;
-  long long kept = 0;
-  for (int k = 0; k < n_att; k++) {
-    const int ci = pairs[2 * k], cj = pairs[2 * k + 1];
-    const int pi = slot_of[ci], pj = slot_of[cj];
-    const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
-    double eb = 0.0, ea = 0.0;
-    if (pi != pj) {
-      for (int side = 0; side < 2; side++) {
-        const int p = side ? pj : pi, o = side ? pi : pj;
-        const double sa = side ? sj : si, sb = side ? si : sj;  // p's diameter before, after
-        double xp[D];
-        load_x<D>(xb, p, xp);
-        int cd[D];
-        {
-          int r = flat_cell<D>(s, xp);
-          for (int a = D - 1; a >= 0; a--) {
-            cd[a] = r % nc;
-            r /= nc;
-          }
+  const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
+  double eb = 0.0, ea = 0.0;
+  if (pi != pj) {
+    for (int side = 0; side < 2; side++) {
+      const int p = side ? pj : pi, o = side ? pi : pj;
+      const double sa = side ? sj : si, sb = side ? si : sj;  // p's diameter before, after
+      double xp[D];
+      load_x<D>(xb, p, xp);
+      int cd[D];
+      {
+        int r = flat_cell<D>(s, xp);
+        for (int a = D - 1; a >= 0; a--) {
+          cd[a] = r % nc;
+          r /= nc;
         }
-        // the waves take groups of 64 linked subcells; a group's bounds are
-        // loaded by its lanes at once, then its subcells are walked in turn
-        for (int t0 = wv * 64; t0 < nst; t0 += 64 * nwv) {
-          int cs = 0, ce = 0;
-          const int t = t0 + lane;
-          if (t < nst) {
-            int cell = 0, r = t, mult = 1;
-            for (int a = D - 1; a >= 0; a--) {
-              int ca;
-              if (nc <= 2) {
-                ca = r % nc;
-                r /= nc;
-              } else {
-                ca = cd[a] + r % 3 - 1;
-                r /= 3;
-                ca = ca < 0 ? ca + nc : (ca >= nc ? ca - nc : ca);
-              }
-              cell += ca * mult;
-              mult *= nc;
+      }
+      for (int t0 = wv * 64; t0 < nst; t0 += 64 * nwv) {
+        int cs = 0, ce = 0;
+        const int t = t0 + lane;
+        if (t < nst) {
+          int cell = 0, r = t, mult = 1;
+          for (int a = D - 1; a >= 0; a--) {
+            int ca;
+            if (nc <= 2) {
+              ca = r % nc;
+              r /= nc;
+            } else {
+              ca = cd[a] + r % 3 - 1;
+              r /= 3;
+              ca = ca < 0 ? ca + nc : (ca >= nc ? ca - nc : ca);
             }
-            cs = flat[cell];
-            ce = flat[cell + 1];
+            cell += ca * mult;
+            mult *= nc;
           }
-          const int ng = min(64, nst - t0);
-          for (int g = 0; g < ng; g++) {
-            const int q1 = __builtin_amdgcn_readlane(ce, g);
-            for (int q = __builtin_amdgcn_readlane(cs, g) + lane; q < q1; q += 64) {
-              if (q == p) continue;
-              double xq[D];
-              load_x<D>(xb, q, xq);
-              const double sq = sig_get(xb + (size_t)q * DR + D);
-              double r2 = 0.0;
-              for (int a = 0; a < D; a++) {
-                const double dx = min_image(xq[a] - xp[a], L, h);
-                r2 = __builtin_fma(dx, dx, r2);
-              }
-              double fc, uu;
-              const double s_b = 0.5 * (sa + sq);
-              if (r2 < (cut * s_b) * (cut * s_b)) {
-                if (morse) pair_f64<true>(pot, eps, ma, r2, s_b, fc, uu);
-                else pair_f64<false>(pot, eps, ma, r2, s_b, fc, uu);
-                eb += uu;
-              }
-              // after the exchange the partner carries p's old diameter
-              const double s_a = 0.5 * (sb + (q == o ? sa : sq));
-              if (r2 < (cut * s_a) * (cut * s_a)) {
-                if (morse) pair_f64<true>(pot, eps, ma, r2, s_a, fc, uu);
-                else pair_f64<false>(pot, eps, ma, r2, s_a, fc, uu);
-                ea += uu;
-              }
+          cs = flat[cell];
+          ce = flat[cell + 1];
+        }
+        const int ng = min(64, nst - t0);
+        for (int g = 0; g < ng; g++) {
+          const int q1 = __builtin_amdgcn_readlane(ce, g);
+          for (int q = __builtin_amdgcn_readlane(cs, g) + lane; q < q1; q += 64) {
+            if (q == p) continue;
+            double xq[D];
+            load_x<D>(xb, q, xq);
+            const double sq = sig_get(xb + (size_t)q * DR + D);
+            double r2 = 0.0;
+            for (int a = 0; a < D; a++) {
+              const double dx = min_image(xq[a] - xp[a], L, h);
+              r2 = __builtin_fma(dx, dx, r2);
+            }
+            double fc, uu;
+            const double s_b = 0.5 * (sa + sq);
+            if (r2 < (cut * s_b) * (cut * s_b)) {
+              if (morse) pair_f64<true>(pot, eps, ma, r2, s_b, fc, uu);
+              else pair_f64<false>(pot, eps, ma, r2, s_b, fc, uu);
+              eb += uu;
+            }
+            // after the exchange the partner carries p's old diameter
+            const double s_a = 0.5 * (sb + (q == o ? sa : sq));
+            if (r2 < (cut * s_a) * (cut * s_a)) {
+              if (morse) pair_f64<true>(pot, eps, ma, r2, s_a, fc, uu);
+              else pair_f64<false>(pot, eps, ma, r2, s_a, fc, uu);
+              ea += uu;
             }
           }
         }
       }
     }
-    // wave sums, then the waves' sums in wave order (deterministic)
-    eb = wave_sum(eb);
-    ea = wave_sum(ea);
-    if (lane == 0) {
-      red[0][wv] = eb;
-      red[1][wv] = ea;
+  }
+  eb = wave_sum(eb);
+  ea = wave_sum(ea);
+  if (lane == 0) {
+    red[0][wv] = eb;
+    red[1][wv] = ea;
+  }
+  __syncthreads();
+  eb = 0.0;
+  ea = 0.0;
+  for (int w = 0; w < nwv; w++) {
+    eb += red[0][w];
+    ea += red[1][w];
+  }
+  __syncthreads();  // red[] is free again
+  return pi == pj ? 0.0 : ea - eb;
+}
+
+// dE of the batch's attempts todo[0 .. nb), one workgroup each
+template <int D>
+__global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const int32_t* __restrict__ todo,
+                                                  int nb, const int32_t* __restrict__ pairs,
+                                                  const int32_t* __restrict__ slot_of,
+                                                  double* __restrict__ de) {
+  __shared__ double red[2][16];
+  const int b = blockIdx.x;
+  if (b >= nb) return;
+  const int k = todo[b];
+  const double d = swap_de<D>(s, slot_of[pairs[2 * k]], slot_of[pairs[2 * k + 1]], red);
+  if (threadIdx.x == 0) de[b] = d;
+}
+
+// Settles the batch todo_in[0 .. nb) in order (see above), applies the kept
+// exchanges, and writes the attempts still to run (put off ones first) to
+// todo_out; ctl[0] = their number, ctl[1] += exchanges kept.
+template <int D>
+__global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, const int32_t* __restrict__ todo_in,
+                                                      int n_todo, int nb,
+                                                      int32_t* __restrict__ todo_out,
+                                                      const int32_t* __restrict__ pairs,
+                                                      const double* __restrict__ u, double T,
+                                                      const int32_t* __restrict__ slot_of,
+                                                      const double* __restrict__ de,
+                                                      int32_t* __restrict__ acc,
+                                                      double* __restrict__ diam,
+                                                      long long* __restrict__ ctl) {
+  constexpr int DR = Dims<D>::DR, NW = kSwapBatch / 64;
+  __shared__ double px[kSwapBatch][2][D];
+  __shared__ unsigned long long conf[kSwapBatch][NW];
+  __shared__ int put_off[kSwapBatch];
+  __shared__ int n_off;
+  const int tid = threadIdx.x;
+  double* xb = s->x[s->xcur];
+  const double L = s->L, h = s->hL;
+  const double rr = s->cutoff * s->sigma_max, r2max = rr * rr * (1.0 + 1e-12);
+  for (int t = tid; t < 2 * nb; t += blockDim.x) {
+    double x[D];
+    load_x<D>(xb, slot_of[pairs[2 * todo_in[t >> 1] + (t & 1)]], x);
+    for (int a = 0; a < D; a++) px[t >> 1][t & 1][a] = x[a];
+  }
+  __syncthreads();
+  // conf[b][w] bit c: attempt 64 w + c (< b) has an atom within c sigma_max
+  // of an atom of attempt b
+  for (int t = tid; t < nb * NW; t += blockDim.x) {
+    const int b = t / NW, w = t % NW;
+    unsigned long long m = 0;
+    for (int c = 0; c < 64; c++) {
+      const int b2 = 64 * w + c;
+      if (b2 >= b) break;
+      bool near = false;
+      for (int e = 0; e < 4; e++) {
+        double r2 = 0.0;
+        for (int a = 0; a < D; a++) {
+          const double dx = min_image(px[b][e >> 1][a] - px[b2][e & 1][a], L, h);
+          r2 += dx * dx;
+        }
+        near = near || r2 <= r2max;
+      }
+      if (near) m |= 1ull << c;
     }
-    __syncthreads();
-    eb = 0.0;
-    ea = 0.0;
-    for (int w = 0; w < nwv; w++) {
-      eb += red[0][w];
-      ea += red[1][w];
-    }
-    const double de = pi == pj ? 0.0 : ea - eb;
-    const bool ok = de <= 0.0 || u[k] < exp(-de / T);
-    if (ok) kept++;
-    if (threadIdx.x == 0) {
+    conf[b][w] = m;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long blk[NW];
+    for (int w = 0; w < NW; w++) blk[w] = 0;
+    int noff = 0;
+    long long kept = 0;
+    for (int b = 0; b < nb; b++) {
+      bool hit = false;
+      for (int w = 0; w < NW; w++) hit = hit || (conf[b][w] & blk[w]) != 0;
+      const int k = todo_in[b];
+      if (hit) {
+        put_off[noff++] = k;
+        blk[b >> 6] |= 1ull << (b & 63);
+        continue;
+      }
+      const double d = de[b];
+      const bool ok = d <= 0.0 || u[k] < exp(-d / T);
+      if (acc) acc[k] = ok ? 1 : 0;
       if (ok) {
+        const int ci = pairs[2 * k], cj = pairs[2 * k + 1];
+        const int pi = slot_of[ci], pj = slot_of[cj];
+        const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
         sig_put(xb + (size_t)pi * DR + D, sj);
         sig_put(xb + (size_t)pj * DR + D, si);
         diam[ci] = sj;
         diam[cj] = si;
+        kept++;
+        blk[b >> 6] |= 1ull << (b & 63);
       }
-      if (acc) acc[k] = ok ? 1 : 0;
-      __threadfence();  // the new diameters reach L2 before the next attempt
     }
-    __syncthreads();  // every wave has read red[] and sees the new diameters
+    n_off = noff;
+    ctl[0] = noff + (n_todo - nb);
+    ctl[1] += kept;
   }
-  if (threadIdx.x == 0) *nacc = kept;
+  __syncthreads();
+  const int noff = n_off;
+  for (int t = tid; t < noff; t += blockDim.x) todo_out[t] = put_off[t];
+  for (int t = nb + tid; t < n_todo; t += blockDim.x) todo_out[noff + t - nb] = todo_in[t];
 }
 
 // Own atom's data as the force loop needs it.

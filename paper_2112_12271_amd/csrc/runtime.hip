@@ -766,15 +766,58 @@ int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws,
   if (rc) return rc;
   *n_accepted = 0;
   if (n_att == 0) return HDMD_OK;
-  int32_t* slot_of = at<int32_t>(ws, p.off_src);   // free outside a rebuild
-  long long* nacc = at<long long>(ws, p.off_part);  // free outside a step
+  int32_t* slot_of = at<int32_t>(ws, p.off_src);  // free outside a rebuild
   launch_slot_of(dev, p.n, slot_of, st);
-  dkernels(p.d)->swap(dev, st, (int)n_att, pairs, u, temperature, slot_of, accepted, diam, nacc);
-  HIPCHK(hipGetLastError());
-  long long k = 0;
-  HIPCHK(hipMemcpyAsync(&k, nacc, sizeof(k), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  *n_accepted = k;
+  // the attempts still to run (two buffers, in turn), a batch's dE and the
+  // settlement counters
+  int32_t* todo[2] = {nullptr, nullptr};
+  double* de = nullptr;
+  long long* ctl = nullptr;
+  auto release = [&]() {
+    hipFree(todo[0]);
+    hipFree(todo[1]);
+    hipFree(de);
+    hipFree(ctl);
+  };
+  if (hipMalloc(&todo[0], (size_t)n_att * 4) != hipSuccess ||
+      hipMalloc(&todo[1], (size_t)n_att * 4) != hipSuccess ||
+      hipMalloc(&de, kSwapBatch * sizeof(double)) != hipSuccess ||
+      hipMalloc(&ctl, 2 * sizeof(long long)) != hipSuccess) {
+    release();
+    return fail(HDMD_ERR_HIP, "hdmd_swap: device allocation failed");
+  }
+  std::vector<int32_t> order((size_t)n_att);
+  for (int64_t k = 0; k < n_att; k++) order[(size_t)k] = (int32_t)k;
+  long long hc[2] = {n_att, 0};
+  int rc2 = HDMD_OK;
+  if (hipMemcpyAsync(todo[0], order.data(), order.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(ctl, hc, sizeof(hc), hipMemcpyHostToDevice, st) != hipSuccess)
+    rc2 = fail(HDMD_ERR_HIP, "hdmd_swap: copy failed");
+  const DKernels* K = dkernels(p.d);
+  int64_t n_todo = n_att, rounds = 0;
+  int cur = 0;
+  while (rc2 == HDMD_OK && n_todo > 0) {
+    // the first attempt of a batch is always settled, so every round makes progress
+    if (++rounds > n_att) {
+      rc2 = fail(HDMD_ERR_STATE, "hdmd_swap: no progress");
+      break;
+    }
+    const int nb = (int)std::min<int64_t>(kSwapBatch, n_todo);
+    K->swap_de(dev, st, todo[cur], nb, pairs, slot_of, de);
+    K->swap_settle(dev, st, todo[cur], (int)n_todo, nb, todo[cur ^ 1], pairs, u, temperature,
+                   slot_of, de, accepted, diam, ctl);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc2 = fail(HDMD_ERR_HIP, "hdmd_swap: launch failed");
+      break;
+    }
+    n_todo = hc[0];
+    cur ^= 1;
+  }
+  release();
+  if (rc2 != HDMD_OK) return rc2;
+  *n_accepted = hc[1];
   return HDMD_OK;
 }
 
