@@ -65,3 +65,25 @@ def test_swap_rejects_bad_input():
     D = dev(sig)
     acc, na = H.hdmd_swap(sysd, dev(x), D, ws, ok[:0], u[:0], 0.5)   # nothing to attempt
     assert na == 0 and np.array_equal(D.cpu().numpy(), sig)
+
+
+def test_swap_chain_of_interfering_attempts(orc):
+    """Every attempt exchanges atom 0 with another atom, so each one depends on
+    the one before: the batches settle one attempt at a time and still give
+    the serial outcome."""
+    x, sig, L = _case(3, 6, 1.4, 31, 1.4)
+    n = len(x)
+    g = np.random.default_rng(32)
+    m = 300
+    pairs = np.stack([np.zeros(m, dtype=np.int32), g.integers(1, n, size=m).astype(np.int32)], 1)
+    u = g.uniform(size=m)
+    sig_o, acc_o, de_o, na_o = orc.swap(x, sig, L, H.HDMD_WCA, C6, 1.0, pairs, u, 2.0)
+    thr = np.where(de_o <= 0, 2.0, np.exp(-np.maximum(de_o, 0) / 2.0))
+    assert np.all((de_o <= 0) | (np.abs(u - thr) > 1e-9))
+    sysd = H.System(d=3, n=n, box_l=L, cutoff=C6, skin=0.25, sigma_max=1.4)
+    sysd, ws = H.build_with_width(sysd, dev(x), dev(sig))
+    D = dev(sig)
+    acc, na = H.hdmd_swap(sysd, dev(x), D, ws, torch.as_tensor(pairs, device="cuda"), dev(u), 2.0)
+    assert na == na_o and 0 < na < m
+    assert np.array_equal(acc.cpu().numpy(), acc_o)
+    assert np.array_equal(D.cpu().numpy(), sig_o)
