@@ -204,9 +204,13 @@ int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbi
  * velocities need no rescaling.  pos ([n][d] FP64, device) is read; diam
  * ([n] FP64, device) is updated in place; accepted (n_att int32, device,
  * optional) receives 1 or 0 per attempt and *n_accepted (host) the count.
- * The attempts run serially on one wave, as the paper runs them on one
- * thread.  Errors: HDMD_ERR_ARG (an id outside [0, n), temperature <= 0, ...),
- * HDMD_ERR_WORKSPACE and the load errors of hdmd_build_nlist.  Synchronises. */
+ * The outcome is that of the serial walk the paper runs on one thread; the
+ * attempts are evaluated in batches and settled in order (an attempt waits
+ * for the next batch when an earlier kept or waiting attempt of its batch
+ * has an atom within cutoff * sigma_max of one of its atoms).  Allocates and
+ * frees 8 n_att + 2 KiB bytes of device scratch.  Errors: HDMD_ERR_ARG (an
+ * id outside [0, n), temperature <= 0, ...), HDMD_ERR_WORKSPACE, HDMD_ERR_HIP
+ * and the load errors of hdmd_build_nlist.  Synchronises. */
 int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
               int64_t n_att, const int32_t* pairs, const double* u, double temperature,
               int32_t* accepted, int64_t* n_accepted, void* stream);
