@@ -14,8 +14,8 @@ mixed form (FP32 forces/velocities, FP64 positions and sums).
 
 Prints one JSON line.  `value` is atom-steps/s of the FP64 run with inputs
 resident in HBM.  `roofline` is the fused-step kernel's algorithmic bytes per
-launch (SURVEY-defined per-atom bytes times N) over its mean
-duration measured with HIP events inside the timed region.  `cpu_baseline` is
+launch (the compulsory per-atom bytes of a step, step_bytes_per_atom, times N)
+over its mean duration measured with HIP events inside the timed region.  `cpu_baseline` is
 the plain oracle on the host, on a bounded sample described in the line.
 """
 from __future__ import annotations
@@ -361,8 +361,8 @@ def main():
                           "launches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(the design notes say how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
