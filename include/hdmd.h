@@ -161,9 +161,10 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
 
 #define HDMD_THERMO_COLS 10
 
-/* NVE velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B: per step
+/* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B: per step
  * v += dt/2 F; x += dt v (wrapped); rebuild the list when the largest
- * displacement since the last build exceeds skin/2; F = F(x); v += dt/2 F.
+ * displacement since the last build exceeds skin/2; F = F(x); v += dt/2 F
+ * (times the Berendsen factor when sys->thermostat_tau > 0; NVE otherwise).
  * pos and vel ([n][d] FP64, device) are read on entry and written on exit.
  * thermo (device, may be NULL) receives floor(nsteps/thermo_every)+1 rows of
  * HDMD_THERMO_COLS FP64 at steps 0, thermo_every, ...:
