@@ -242,7 +242,8 @@ int hdmd_batch_init(void* table_ws, size_t table_bytes, int32_t max_slots, int64
 int hdmd_batch_add_fire(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
                         const double* diam, void* ws, size_t ws_bytes,
                         const hdmd_fire_params* params, void* stream);
-/* Loads an NVE run of nsteps velocity-Verlet steps of size dt into slot. */
+/* Loads a run of nsteps velocity-Verlet steps of size dt into slot (NVE, or
+ * with the Berendsen thermostat of sys, as hdmd_step). */
 int hdmd_batch_add_md(void* table_ws, int32_t slot, const hdmd_system* sys, const double* pos,
                       const double* vel, const double* diam, void* ws, size_t ws_bytes,
                       int64_t nsteps, double dt, void* stream);
