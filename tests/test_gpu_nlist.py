@@ -202,3 +202,23 @@ def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
             os.environ.pop("HDMD_BUILD_BLK", None)
         else:
             os.environ["HDMD_BUILD_BLK"] = old
+
+
+@pytest.mark.parametrize("d,n,L", [(3, 1600, 13.0), (5, 1500, 7.0)])
+@pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
+def test_sparse_system_with_one_crowded_subcell(orc, d, n, L, prec):
+    """A sparse system (few atoms per subcell on average, so the candidate-lane
+    build takes four rows per round) with 90 atoms packed into one subcell:
+    the rounds whose rows reach that subcell exceed one chunk and fall back
+    to the row-by-row walk; the lists still match brute force."""
+    g = np.random.default_rng(50 + d)
+    x = inputs.uniform_positions(n, d, L, 40 + d)
+    rl = 1.4 + 0.3
+    lsc = L / orc.ncell(L, rl)
+    x[:90] = -L / 2 + g.uniform(0.05, 0.95, size=(90, d)) * lsc
+    sig = inputs.bidisperse(n, 1.0, 1.4, 60 + d)
+    ref = orc.nlist_brute(x, sig, L, 1.0, 0.3)
+    sysd = H.System(d=d, n=n, box_l=L, potential=H.HDMD_HARMONIC, cutoff=1.0, skin=0.3,
+                    sigma_max=1.4, precision=prec, max_neighbors=128)
+    got, _, _ = gpu_list(sysd, x, sig)
+    assert csr_equal(got, ref)
