@@ -24,11 +24,11 @@ struct DKernels {
                   unsigned long long* hist, double* disp);
   // SWAP Monte Carlo: dE of a batch, then its settlement (kernels.h)
   void (*swap_de)(const SysDev* s, hipStream_t st, const int32_t* todo, int nb, const int32_t* pairs,
-                  const int32_t* slot_of, double* de);
+                  const int32_t* slot_of, double* de, unsigned long long* conf);
   void (*swap_settle)(SysDev* s, hipStream_t st, const int32_t* todo_in, int n_todo, int nb,
                       int32_t* todo_out, const int32_t* pairs, const double* u, double T,
-                      const int32_t* slot_of, const double* de, int32_t* acc, double* diam,
-                      long long* ctl);
+                      const int32_t* slot_of, const double* de, const unsigned long long* conf,
+                      int32_t* acc, double* diam, long long* ctl);
 };
 
 const DKernels* dkernels(int d);

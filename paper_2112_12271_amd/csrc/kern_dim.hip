@@ -89,15 +89,15 @@ void l_vanhove(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
   k_vanhove<D><<<grid, kTile, 0, st>>>(s, nbins, w, hist, disp);
 }
 void l_swap_de(const SysDev* s, hipStream_t st, const int32_t* todo, int nb, const int32_t* pairs,
-               const int32_t* slot_of, double* de) {
-  k_swap_de<D><<<nb, 1024, 0, st>>>(s, todo, nb, pairs, slot_of, de);
+               const int32_t* slot_of, double* de, unsigned long long* conf) {
+  k_swap_de<D><<<nb, 1024, 0, st>>>(s, todo, nb, pairs, slot_of, de, conf);
 }
 void l_swap_settle(SysDev* s, hipStream_t st, const int32_t* todo_in, int n_todo, int nb,
                    int32_t* todo_out, const int32_t* pairs, const double* u, double T,
-                   const int32_t* slot_of, const double* de, int32_t* acc, double* diam,
-                   long long* ctl) {
+                   const int32_t* slot_of, const double* de, const unsigned long long* conf,
+                   int32_t* acc, double* diam, long long* ctl) {
   k_swap_settle<D><<<1, 1024, 0, st>>>(s, todo_in, n_todo, nb, todo_out, pairs, u, T, slot_of, de,
-                                       acc, diam, ctl);
+                                       conf, acc, diam, ctl);
 }
 const DKernels table = {l_load, l_unload, l_bin, l_cellsort, l_build, l_force, l_step,
                         l_fire_update, l_vanhove, l_swap_de, l_swap_settle};

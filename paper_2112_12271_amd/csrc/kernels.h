@@ -1206,7 +1206,8 @@ __device__ inline void sig_put(double* p, double v) {
 // striding over a subcell's atoms, the wave sums added in wave order.
 // Every thread returns the same value.
 template <int D>
-__device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[16]) {
+__device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[16], double& si_out,
+                                 double& sj_out) {
   constexpr int DR = Dims<D>::DR;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int nc = s->ncell;
@@ -1218,6 +1219,8 @@ __device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[
   int nst = 1;
   for (int k = 0; k < D; k++) nst *= nc <= 2 ? nc : 3;
   const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
+  si_out = si;
+  sj_out = sj;
   double eb = 0.0, ea = 0.0;
   if (pi != pj) {
     for (int side = 0; side < 2; side++) {
@@ -1303,18 +1306,52 @@ __device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[
   return pi == pj ? 0.0 : ea - eb;
 }
 
-// dE of the batch's attempts todo[0 .. nb), one workgroup each
+// dE of the batch's attempts todo[0 .. nb), one workgroup each, with the
+// two diameters it was taken with: de[3b] = dE, de[3b+1], de[3b+2] = the
+// diameters of the first and the second atom.  conf[b][w] bit c: attempt
+// b' = 64 w + c < b has an atom within c sigma_max of an atom of attempt b.
 template <int D>
 __global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const int32_t* __restrict__ todo,
                                                   int nb, const int32_t* __restrict__ pairs,
                                                   const int32_t* __restrict__ slot_of,
-                                                  double* __restrict__ de) {
+                                                  double* __restrict__ de,
+                                                  unsigned long long* __restrict__ conf) {
   __shared__ double red[2][16];
   const int b = blockIdx.x;
   if (b >= nb) return;
   const int k = todo[b];
-  const double d = swap_de<D>(s, slot_of[pairs[2 * k]], slot_of[pairs[2 * k + 1]], red);
-  if (threadIdx.x == 0) de[b] = d;
+  const int pi = slot_of[pairs[2 * k]], pj = slot_of[pairs[2 * k + 1]];
+  {
+    const double* xb = s->x[s->xcur];
+    const double L = s->L, h = s->hL;
+    const double rr = s->cutoff * s->sigma_max, r2max = rr * rr * (1.0 + 1e-12);
+    const int t = threadIdx.x;
+    bool near = false;
+    if (t < b) {
+      const int k2 = todo[t];
+      const int q2[2] = {slot_of[pairs[2 * k2]], slot_of[pairs[2 * k2 + 1]]};
+      for (int e = 0; e < 4; e++) {
+        double xa[D], xc[D];
+        load_x<D>(xb, (e >> 1) ? pj : pi, xa);
+        load_x<D>(xb, q2[e & 1], xc);
+        double r2 = 0.0;
+        for (int a = 0; a < D; a++) {
+          const double dx = min_image(xa[a] - xc[a], L, h);
+          r2 += dx * dx;
+        }
+        near = near || r2 <= r2max;
+      }
+    }
+    const unsigned long long m = __ballot(near);
+    if (t < kSwapBatch && (t & 63) == 0) conf[(size_t)b * (kSwapBatch / 64) + (t >> 6)] = m;
+  }
+  double si, sj;
+  const double d = swap_de<D>(s, pi, pj, red, si, sj);
+  if (threadIdx.x == 0) {
+    de[3 * b] = d;
+    de[3 * b + 1] = si;
+    de[3 * b + 2] = sj;
+  }
 }
 
 // Settles the batch todo_in[0 .. nb) in order (see above), applies the kept
@@ -1328,44 +1365,30 @@ __global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, const int32_t* 
                                                       const double* __restrict__ u, double T,
                                                       const int32_t* __restrict__ slot_of,
                                                       const double* __restrict__ de,
+                                                      const unsigned long long* __restrict__ cfg,
                                                       int32_t* __restrict__ acc,
                                                       double* __restrict__ diam,
                                                       long long* __restrict__ ctl) {
   constexpr int DR = Dims<D>::DR, NW = kSwapBatch / 64;
-  __shared__ double px[kSwapBatch][2][D];
   __shared__ unsigned long long conf[kSwapBatch][NW];
   __shared__ int put_off[kSwapBatch];
+  __shared__ int att[kSwapBatch], cid[kSwapBatch][2], slot[kSwapBatch][2];
+  __shared__ double thr[kSwapBatch];  // u_k, then the Metropolis decision as 0 / 1
   __shared__ int n_off;
   const int tid = threadIdx.x;
   double* xb = s->x[s->xcur];
-  const double L = s->L, h = s->hL;
-  const double rr = s->cutoff * s->sigma_max, r2max = rr * rr * (1.0 + 1e-12);
+  for (int t = tid; t < nb * NW; t += blockDim.x) conf[t / NW][t % NW] = cfg[t];
   for (int t = tid; t < 2 * nb; t += blockDim.x) {
-    double x[D];
-    load_x<D>(xb, slot_of[pairs[2 * todo_in[t >> 1] + (t & 1)]], x);
-    for (int a = 0; a < D; a++) px[t >> 1][t & 1][a] = x[a];
-  }
-  __syncthreads();
-  // conf[b][w] bit c: attempt 64 w + c (< b) has an atom within c sigma_max
-  // of an atom of attempt b
-  for (int t = tid; t < nb * NW; t += blockDim.x) {
-    const int b = t / NW, w = t % NW;
-    unsigned long long m = 0;
-    for (int c = 0; c < 64; c++) {
-      const int b2 = 64 * w + c;
-      if (b2 >= b) break;
-      bool near = false;
-      for (int e = 0; e < 4; e++) {
-        double r2 = 0.0;
-        for (int a = 0; a < D; a++) {
-          const double dx = min_image(px[b][e >> 1][a] - px[b2][e & 1][a], L, h);
-          r2 += dx * dx;
-        }
-        near = near || r2 <= r2max;
-      }
-      if (near) m |= 1ull << c;
+    const int b = t >> 1, e = t & 1, k = todo_in[b];
+    const int c = pairs[2 * k + e], q = slot_of[c];
+    cid[b][e] = c;
+    slot[b][e] = q;
+    if (e == 0) {
+      att[b] = k;
+      // the decision of an attempt that settles (its dE stands)
+      const double d = de[3 * b];
+      thr[b] = (d <= 0.0 || u[k] < exp(-d / T)) ? 1.0 : 0.0;
     }
-    conf[b][w] = m;
   }
   __syncthreads();
   if (tid == 0) {
@@ -1376,23 +1399,22 @@ __global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, const int32_t* 
     for (int b = 0; b < nb; b++) {
       bool hit = false;
       for (int w = 0; w < NW; w++) hit = hit || (conf[b][w] & blk[w]) != 0;
-      const int k = todo_in[b];
+      const int k = att[b];
       if (hit) {
         put_off[noff++] = k;
         blk[b >> 6] |= 1ull << (b & 63);
         continue;
       }
-      const double d = de[b];
-      const bool ok = d <= 0.0 || u[k] < exp(-d / T);
+      const bool ok = thr[b] != 0.0;
       if (acc) acc[k] = ok ? 1 : 0;
       if (ok) {
-        const int ci = pairs[2 * k], cj = pairs[2 * k + 1];
-        const int pi = slot_of[ci], pj = slot_of[cj];
-        const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
-        sig_put(xb + (size_t)pi * DR + D, sj);
-        sig_put(xb + (size_t)pj * DR + D, si);
-        diam[ci] = sj;
-        diam[cj] = si;
+        // a settled attempt's atoms were not touched earlier in the batch, so
+        // their diameters are the ones its dE was taken with
+        const double si = de[3 * b + 1], sj = de[3 * b + 2];
+        sig_put(xb + (size_t)slot[b][0] * DR + D, sj);
+        sig_put(xb + (size_t)slot[b][1] * DR + D, si);
+        diam[cid[b][0]] = sj;
+        diam[cid[b][1]] = si;
         kept++;
         blk[b >> 6] |= 1ull << (b & 63);
       }

@@ -772,16 +772,19 @@ int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws,
   // settlement counters
   int32_t* todo[2] = {nullptr, nullptr};
   double* de = nullptr;
+  unsigned long long* conf = nullptr;
   long long* ctl = nullptr;
   auto release = [&]() {
     hipFree(todo[0]);
     hipFree(todo[1]);
     hipFree(de);
+    hipFree(conf);
     hipFree(ctl);
   };
   if (hipMalloc(&todo[0], (size_t)n_att * 4) != hipSuccess ||
       hipMalloc(&todo[1], (size_t)n_att * 4) != hipSuccess ||
-      hipMalloc(&de, kSwapBatch * sizeof(double)) != hipSuccess ||
+      hipMalloc(&de, 3 * kSwapBatch * sizeof(double)) != hipSuccess ||
+      hipMalloc(&conf, (size_t)kSwapBatch * (kSwapBatch / 64) * 8) != hipSuccess ||
       hipMalloc(&ctl, 2 * sizeof(long long)) != hipSuccess) {
     release();
     return fail(HDMD_ERR_HIP, "hdmd_swap: device allocation failed");
@@ -803,9 +806,9 @@ int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws,
       break;
     }
     const int nb = (int)std::min<int64_t>(kSwapBatch, n_todo);
-    K->swap_de(dev, st, todo[cur], nb, pairs, slot_of, de);
+    K->swap_de(dev, st, todo[cur], nb, pairs, slot_of, de, conf);
     K->swap_settle(dev, st, todo[cur], (int)n_todo, nb, todo[cur ^ 1], pairs, u, temperature,
-                   slot_of, de, accepted, diam, ctl);
+                   slot_of, de, conf, accepted, diam, ctl);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
