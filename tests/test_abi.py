@@ -86,3 +86,13 @@ def test_batch_bytes_host_only():
     assert L.hdmd_batch_bytes(4, 1 << 16, 1 << 12) > 0
     assert L.hdmd_batch_bytes(8, 1 << 16, 1 << 12) >= L.hdmd_batch_bytes(4, 1 << 16, 1 << 12)
     assert L.hdmd_batch_bytes(1025, 10, 10) == 0
+
+
+def test_binding_constants_match_the_header():
+    """The binding's thermo-row width and potential codes are the header's."""
+    import re
+    hdr = open(H.HEADER).read()
+    assert int(re.search(r"#define HDMD_THERMO_COLS (\d+)", hdr).group(1)) == H.THERMO_COLS
+    for name in ("HDMD_WCA", "HDMD_HARMONIC", "HDMD_MORSE", "HDMD_FP64", "HDMD_MIXED"):
+        m = re.search(name + r"\s*=\s*(\d+)", hdr)
+        assert m and int(m.group(1)) == getattr(H, name), name
