@@ -621,9 +621,15 @@ typedef struct {
  * inside the initial delay), step back x -= dt/2 v and zero v; then
  * v += dt F, mix v = (1-alpha) v + alpha |v| F/|F| with norms over all dN
  * components, x += dt v, wrap, rebuild if needed, recompute F.
- * Convergence is checked on the fresh force before each iteration. */
-void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
-              const double* sig, const orc_fire_params* p, orc_fire_result* res) {
+ * Convergence is checked on the fresh force before each iteration.
+ * trace (optional, trace_cap rows of ORC_FIRE_TRACE doubles) receives one
+ * row per iteration: P, the dt and alpha the update used, the counts of
+ * consecutive P > 0 and P <= 0 iterations after the control step, and 1 when
+ * the iteration stepped back and zeroed v (else 0). */
+#define ORC_FIRE_TRACE 6
+void orc_fire_traced(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
+                     const double* sig, const orc_fire_params* p, orc_fire_result* res,
+                     double* trace, int64_t trace_cap) {
   orc_sys S = {d, n, L, pot, c, s, eps};
   int64_t m = n * d;
   orc_nlstate st = {0};
@@ -648,6 +654,7 @@ void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double ep
     if (it >= p->maxiter) break;
     double P = 0.0;
     for (int64_t a = 0; a < m; a++) P += F[a] * v[a];
+    int back = 0;
     if (P > 0.0) {
       npos++;
       nneg = 0;
@@ -665,6 +672,16 @@ void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double ep
       }
       for (int64_t a = 0; a < m; a++) x[a] = x[a] - 0.5 * dt * v[a];
       for (int64_t a = 0; a < m; a++) v[a] = 0.0;
+      back = 1;
+    }
+    if (trace && it < trace_cap) {
+      double* row = trace + it * ORC_FIRE_TRACE;
+      row[0] = P;
+      row[1] = dt;
+      row[2] = alpha;
+      row[3] = (double)npos;
+      row[4] = (double)nneg;
+      row[5] = (double)back;
     }
     for (int64_t a = 0; a < m; a++) v[a] += dt * F[a];
     double vv = 0.0, ff = 0.0;
@@ -688,4 +705,9 @@ void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double ep
   free(st.xref);
   free(F);
   free(v);
+}
+
+void orc_fire(int d, int64_t n, double L, int pot, double c, double s, double eps, double* x,
+              const double* sig, const orc_fire_params* p, orc_fire_result* res) {
+  orc_fire_traced(d, n, L, pot, c, s, eps, x, sig, p, res, NULL, 0);
 }

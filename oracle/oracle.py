@@ -120,6 +120,10 @@ def lib():
         L.orc_fire.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
                                C.c_double, _dp, _dp, C.POINTER(FireParams),
                                C.POINTER(FireResult)]
+        L.orc_fire_traced.restype = None
+        L.orc_fire_traced.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, _dp, _dp, C.POINTER(FireParams),
+                                      C.POINTER(FireResult), C.c_void_p, C.c_int64]
         _lib = L
     return _lib
 
@@ -265,9 +269,22 @@ def disp_moments(dr):
     return out
 
 
-def fire(x, sig, L, pot, c, s, eps, params: FireParams):
+FIRE_TRACE_COLS = ("P", "dt", "alpha", "npos", "nneg", "back")
+
+
+def fire(x, sig, L, pot, c, s, eps, params: FireParams, trace: bool = False):
+    """FIRE 2.0 minimisation (Sec. II.B).  Returns (x, result) and, with trace,
+    also one row per iteration of FIRE_TRACE_COLS: the power P = F.v, the dt
+    and alpha the update used, the P > 0 / P <= 0 run counts after the control
+    step and 1 where the iteration stepped back and zeroed v."""
     x = _f64(x).copy()
     n, d = x.shape
     res = FireResult()
-    lib().orc_fire(d, n, L, pot, c, s, eps, x, _f64(sig), C.byref(params), C.byref(res))
-    return x, res
+    if not trace:
+        lib().orc_fire(d, n, L, pot, c, s, eps, x, _f64(sig), C.byref(params), C.byref(res))
+        return x, res
+    cap = int(params.maxiter)
+    tr = np.zeros((max(cap, 1), len(FIRE_TRACE_COLS)))
+    lib().orc_fire_traced(d, n, L, pot, c, s, eps, x, _f64(sig), C.byref(params), C.byref(res),
+                          tr.ctypes.data_as(C.c_void_p), cap)
+    return x, res, tr[:min(int(res.iters), cap)]
