@@ -7,16 +7,25 @@ largest displacement since the last build exceeds skin/2, the subcell binning,
 counting sort and Verlet-list rebuild.
 
 Workload (default): d=6, N=262144, 50:50 WCA mixture sigma 1.0/1.2 at packing
-fraction 0.42, dt=0.002, skin 0.25, T=1.0.  Seeded uniform positions are relaxed
-by FIRE on harmonic soft spheres (on the GPU, untimed), Gaussian velocities at
-T=1 are drawn, then W warm-up steps and K timed steps run, in FP64 and in the
-mixed form (FP32 forces/velocities, FP64 positions and sums).
+fraction 0.42, dt=0.002, skin 0.25, T=1.0.  Untimed set-up: seeded uniform
+positions relaxed by FIRE on harmonic soft spheres, Gaussian velocities at
+T=1, then --equil-steps FP64 steps, so that the timed steps see the liquid the
+10^4-step run spends its time in rather than the heating right after the
+relaxation.  Then, in FP64 and in the mixed form: one call of W warm-up steps
+(it loads the state and builds the list) and three windows of exactly K steps,
+each a resumed call (no reload, no extra list build), in the same launch mode
+as the warm-up: kernels launched one by one with HIP events around every
+fused-step and list-build kernel.  The window with the median time is
+reported.  A separate --long-steps run per precision (captured-graph replay,
+the library's production mode) gives the 10^4-step figures and the energy
+drift.
 
-Prints one JSON line.  `value` is atom-steps/s of the FP64 run with inputs
-resident in HBM.  `roofline` is the fused-step kernel's algorithmic bytes per
-launch (the compulsory per-atom bytes of a step, step_bytes_per_atom, times N)
-over its mean duration measured with HIP events inside the timed region.  `cpu_baseline` is
-the plain oracle on the host, on a bounded sample described in the line.
+Prints one JSON line.  `value` is atom-steps/s of the FP64 median window with
+inputs resident in HBM.  `roofline` is the fused-step kernel's algorithmic
+bytes per launch (the compulsory per-atom bytes of a step, step_bytes_per_atom,
+times N) over its mean duration measured with HIP events inside that window.
+`cpu_baseline` is the oracle built with OpenMP on the host's threads, on a
+bounded sample described in the line.
 """
 from __future__ import annotations
 
@@ -107,53 +116,146 @@ def drift(th: np.ndarray, n: int, dt: float) -> tuple[float, float]:
     return slope, float(np.std(e))
 
 
-def run_md(H, torch, cfg, x0, v0, sig, L, prec, steps, warmup, every, profile):
-    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-    sysd = H.System(d=cfg.d, n=cfg.n, box_l=L, potential=cfg.potential, cutoff=cfg.cutoff,
-                    skin=cfg.skin,
-                    sigma_max=float(sig.max()), precision=prec, max_neighbors=64)
-    X, V, SIG = dev(x0), dev(v0), dev(sig)
-    sysd, _, _ = H.step_auto(sysd, X, V, SIG, max(warmup, 1), cfg.dt)   # warm-up (sizes the rows)
-    ws = H.workspace(sysd)
+def md_system(H, cfg, L, sig, prec, width=64, tau=0.0):
+    return H.System(d=cfg.d, n=cfg.n, box_l=L, potential=cfg.potential, cutoff=cfg.cutoff,
+                    skin=cfg.skin, sigma_max=float(sig.max()), precision=prec,
+                    max_neighbors=width, thermostat_tau=tau, target_temp=cfg.T if tau else 0.0)
+
+
+def sized_width(H, torch, sysd, X, V, SIG, dt):
+    """Row capacity for this state: a one-step run on copies (regrown on
+    overflow), with room for the rows to grow along the trajectory."""
+    sysd, _, _ = H.step_auto(sysd, X.clone(), V.clone(), SIG, 1, dt)
+    sysd.max_neighbors = int(sysd.max_neighbors * 1.25) + 16
+    return sysd
+
+
+def run_windows(H, torch, cfg, X0, V0, SIG, L, prec, steps, warmup, windows, every, profile, tau):
+    """One warm-up call (load, list build, W steps) and `windows` resumed calls
+    of exactly `steps` steps, all in the same launch mode; returns the record
+    of each window (wall time around the call, kernel times of the call)."""
+    sysd = sized_width(H, torch, md_system(H, cfg, L, SIG.cpu().numpy(), prec, tau=tau), X0, V0,
+                       SIG, cfg.dt)
     if profile:
         os.environ["HDMD_PROFILE"] = "1"
     else:
         os.environ.pop("HDMD_PROFILE", None)
+    try:
+        for attempt in range(4):
+            X, V = X0.clone(), V0.clone()
+            ws = H.workspace(sysd)
+            out = []
+            try:
+                H.hdmd_step(sysd, X, V, SIG, ws, max(warmup, 1), cfg.dt)
+                for w in range(windows):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st, th = H.hdmd_step(sysd, X, V, SIG, ws, steps, cfg.dt, every, resume=True)
+                    torch.cuda.synchronize()
+                    out.append(dict(seconds=time.perf_counter() - t0, stats=st,
+                                    thermo=th.cpu().numpy() if th is not None else None))
+            except H.HdmdError as e:
+                if e.status != H.HDMD_ERR_NLIST_OVERFLOW:
+                    raise
+                sysd.max_neighbors = int(sysd.max_neighbors * 1.5) + 16
+                continue
+            break
+    finally:
+        os.environ.pop("HDMD_PROFILE", None)
+    rp, cols = H.hdmd_nlist_export(sysd, ws)
+    mean_row = cols.numel() / cfg.n
+    nc = H.hdmd_cells_per_axis(sysd)
+    cand = build_candidates(X.cpu().numpy(), L, nc) if nc >= 3 else None
+    return out, dict(mean_row=mean_row, width=sysd.max_neighbors, candidates=cand)
+
+
+def window_record(cfg, prec_mixed, win, meta, steps):
+    """The median window (by wall time) with its kernel shares."""
+    order = sorted(range(len(win)), key=lambda k: win[k]["seconds"])
+    w = win[order[len(order) // 2]]
+    st = w["stats"]
+    ms = 1e3 * w["seconds"]
+    rec = dict(value=cfg.n * steps / w["seconds"], ms_per_step=ms / steps,
+               windows_ms_per_step=[1e3 * x["seconds"] / steps for x in win],
+               builds=int(st.builds), steps_per_build=steps / max(st.builds, 1),
+               mean_row=meta["mean_row"], max_row=int(st.max_row), width=meta["width"],
+               T_end=2 * st.ke / (cfg.d * (cfg.n - 1)))
+    if st.step_kernels > 0:
+        avg_ms = st.step_kernel_ms / st.step_kernels
+        bpa = step_bytes_per_atom(cfg.d, meta["mean_row"], prec_mixed)
+        ach = cfg.n * bpa / (avg_ms * 1e-3) / 1e9
+        other = ms - st.step_kernel_ms - st.build_kernel_ms
+        rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
+                   step_kernels=int(st.step_kernels),
+                   build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
+                   build_candidates=meta["candidates"],
+                   share_step_kernel=st.step_kernel_ms / ms,
+                   share_build_kernel=st.build_kernel_ms / ms,
+                   other_ms=other, share_other=other / ms)
+    return rec
+
+
+def run_long(H, torch, cfg, X0, V0, SIG, L, prec, steps, every, tau):
+    """A run of `steps` steps in the library's production mode (captured
+    chunks of steps replayed as graphs) after a warm-up call: wall-clock rate,
+    builds, and the energy drift and fluctuation from thermo rows every
+    `every` steps."""
+    sysd = sized_width(H, torch, md_system(H, cfg, L, SIG.cpu().numpy(), prec, tau=tau), X0, V0,
+                       SIG, cfg.dt)
     for attempt in range(4):
-        Xs, Vs = X.clone(), V.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        X, V = X0.clone(), V0.clone()
+        ws = H.workspace(sysd)
         try:
-            st, th = H.hdmd_step(sysd, Xs, Vs, SIG, ws, steps, cfg.dt, every)
+            H.hdmd_step(sysd, X, V, SIG, ws, 50, cfg.dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, th = H.hdmd_step(sysd, X, V, SIG, ws, steps, cfg.dt, every, resume=True)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
         except H.HdmdError as e:
             if e.status != H.HDMD_ERR_NLIST_OVERFLOW:
                 raise
             sysd.max_neighbors = int(sysd.max_neighbors * 1.5) + 16
-            ws = H.workspace(sysd)
             continue
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
         break
-    os.environ.pop("HDMD_PROFILE", None)
-    rp, cols = H.hdmd_nlist_export(sysd, ws)
-    mean_row = cols.numel() / cfg.n
-    nc = H.hdmd_cells_per_axis(sysd)
-    cand = build_candidates(Xs.cpu().numpy(), L, nc) if nc >= 3 else None
-    return dict(seconds=t1 - t0, stats=st, thermo=th.cpu().numpy(), mean_row=mean_row,
-                width=sysd.max_neighbors, candidates=cand)
+    th = th.cpu().numpy()
+    sl, fl = drift(th, cfg.n, cfg.dt)
+    return dict(steps=steps, value=cfg.n * steps / sec, ms_per_step=1e3 * sec / steps,
+                builds=int(st.builds), steps_per_build=steps / max(st.builds, 1),
+                drift_per_tau=sl, rms_fluct=fl, T_end=2 * st.ke / (cfg.d * (cfg.n - 1)),
+                mode="captured graphs, wall clock")
 
 
-def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5):
-    """The oracle (single thread, as it stands) on a bounded sample of the same
+def host_cpu():
+    """Model name and thread counts of the host (lscpu), and the threads the
+    OpenMP oracle uses."""
+    info = {}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket",
+                             "Socket(s)", "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except Exception as e:  # lscpu missing
+        info["error"] = str(e)
+    info["omp_threads"] = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return info
+
+
+def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5, runs: int = 3):
+    """The oracle built with OpenMP (the paper's per-atom force loop and
+    per-subcell list loop on all host threads) on a bounded sample of the same
     workload: `n` atoms at the same density and diameters, in a box of 3
     subcells per axis, so that the subcell path links every subcell and each
-    atom meets n - 1 candidates.  Timed: one list build by the oracle's subcell
-    path and `reps` force evaluations over that list.  The build time per atom
-    is scaled to the candidates per atom of the full box (3^d of its
-    n_cell^d subcells: 46656 atoms for N = 262144 with n_cell = 4) -- the build is one plain loop per candidate --
-    and per step the oracle costs N * (force time per atom) + N * (build time
-    per atom) / steps_per_build, with the rebuild interval the GPU run
-    measured."""
+    atom meets n - 1 candidates.  Timed, median of `runs`: one list build by
+    the oracle's subcell path, and `reps` force evaluations over that list.
+    The build time per atom is scaled to the candidates per atom of the full
+    box (3^d of its n_cell^d subcells: 46656 atoms for N = 262144 with
+    n_cell = 4) -- the build is one plain loop per candidate -- and per step
+    the oracle costs N * (force time per atom) + N * (build time per atom) /
+    steps_per_build, with the rebuild interval the GPU run measured."""
     from oracle import oracle as O
     from paper_2112_12271_amd import inputs
     sig = (inputs.polydisperse(n, cfg.d, cfg.poly_R, 77) if cfg.poly_R > 0
@@ -161,31 +263,37 @@ def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5):
     L = inputs.box_for_packing(cfg.d, sig, cfg.phi)
     x = inputs.uniform_positions(n, cfg.d, L, 78)
     rlmax = cfg.cutoff * float(sig.max()) + cfg.skin
-    O.lib()
+    O.lib_omp()
     if O.ncell(L, rlmax) != 3:
         log("cpu baseline skipped: the %d-atom sample of %s has %d subcells per axis, not 3"
             % (n, cfg.name, O.ncell(L, rlmax)))
         return None
-    t0 = time.perf_counter()
-    rp, cols = O.nlist_cells(x, sig, L, cfg.cutoff, cfg.skin)
-    t_build = time.perf_counter() - t0
-    log("cpu baseline: oracle list build of %d atoms in %.1f s" % (n, t_build))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        O.forces(x, sig, L, cfg.potential, cfg.cutoff, 1.0, rp, cols)
-    t_f = (time.perf_counter() - t0) / reps
+    tb, tf = [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        rp, cols = O.nlist_cells(x, sig, L, cfg.cutoff, cfg.skin, omp=True)
+        tb.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.forces(x, sig, L, cfg.potential, cfg.cutoff, 1.0, rp, cols, omp=True)
+        tf.append((time.perf_counter() - t0) / reps)
+    t_build, t_f = float(np.median(tb)), float(np.median(tf))
+    log("cpu baseline: OpenMP oracle list build of %d atoms in %.2f s, force pass %.3f s"
+        % (n, t_build, t_f))
     nc_full = O.ncell(cfg.box(cfg.diameters()), rlmax)
     cand_full = cfg.n * (3.0 / nc_full) ** cfg.d
     build_per_atom = t_build / n * (cand_full / (n - 1))
     step_s = cfg.n * (t_f / n) + cfg.n * build_per_atom / steps_per_build
-    return dict(value=cfg.n / step_s, unit="atom-steps/s", cores=1, kind="oracle",
-                sample="oracle FP64, 1 thread, %d atoms (d=%d, phi=%.2f, 3 subcells per axis): "
-                       "one subcell-path list build in %.1f s (%d candidates per atom, scaled to "
-                       "the %.0f of N=%d) and %d force passes over it (mean row %.1f) in %.2f s, "
-                       "combined at %.2f steps per build"
-                       % (n, cfg.d, cfg.phi, t_build, n - 1, cand_full, cfg.n, reps,
-                          len(cols) / n, t_f * reps, steps_per_build),
-                build_s_full=cfg.n * build_per_atom, force_s_full=cfg.n * t_f / n)
+    host = host_cpu()
+    return dict(value=cfg.n / step_s, unit="atom-steps/s", cores=host["omp_threads"],
+                kind="oracle",
+                sample="oracle FP64 built with -fopenmp, %d threads, %d atoms (d=%d, phi=%.2f, "
+                       "3 subcells per axis): subcell-path list build %.2f s (%d candidates per "
+                       "atom, scaled to the %.0f of N=%d) and force pass %.3f s (mean row %.1f), "
+                       "medians of %d runs, combined at %.2f steps per build"
+                       % (host["omp_threads"], n, cfg.d, cfg.phi, t_build, n - 1, cand_full,
+                          cfg.n, t_f, len(cols) / n, runs, steps_per_build),
+                build_s_full=cfg.n * build_per_atom, force_s_full=cfg.n * t_f / n, host=host)
 
 
 def fire_stream(count: int, rate: float, seed: int = 4000):
@@ -295,12 +403,14 @@ def fire_serving(H, torch, args):
         % (len(reqs), sum(r.n for r in reqs), reqs[-1].arrival if reqs else 0))
     out = {"f_tol": args.fire_tol, "requests": len(reqs), "arrival_rate_per_s": args.fire_rate}
 
-    def run_batched(rs):
-        res, wall, srv = batched(H, torch, rs, H.HDMD_MIXED, args.fire_tol, args.fire_max_iter,
+    def run_batched(rs, prec=H.HDMD_MIXED, f_tol=args.fire_tol):
+        res, wall, srv = batched(H, torch, rs, prec, f_tol, args.fire_max_iter,
                                  args.fire_slots, args.fire_budget_gb, args.fire_chunk)
         rec = fire_record(res, wall)
-        rec.update(precision="mixed", slots=args.fire_slots, max_active=srv.max_active,
+        rec.update(precision="mixed" if prec == H.HDMD_MIXED else "fp64", f_tol=f_tol,
+                   slots=args.fire_slots, max_active=srv.max_active,
                    peak_workspace_gb=srv.max_in_use / (1 << 30), budget_gb=args.fire_budget_gb,
+                   footprint_gb=stream_footprint(H, rs, prec) / (1 << 30),
                    retries=int(sum(r.retries for r in res)))
         return rec
 
@@ -318,16 +428,43 @@ def fire_serving(H, torch, args):
                           "p99_ratio_per_instance_over_batched":
                               b["latency_p99"] / a["latency_p99"]}
         log("compare", json.dumps(out["compare"]))
+        if args.fire_tight_tol > 0:
+            # the FP64 leg of the workload: |F|max < 1e-10, batched, same prefix
+            out["batched_fp64_tight"] = run_batched(pre, H.HDMD_FP64, args.fire_tight_tol)
+            log("batched fp64 tight", json.dumps(out["batched_fp64_tight"]))
     return out
+
+
+def stream_footprint(H, reqs, prec) -> int:
+    """Device bytes the whole stream would hold at once (every request's
+    workspace at its estimated row capacity, plus its positions): what an
+    HBM budget below it has to ration."""
+    from paper_2112_12271_amd import serve as S
+    tot = 0
+    for r in reqs:
+        w = S.estimate_width(r.d, r.n, r.box_l, r.cutoff * float(r.sig.max()) + r.skin)
+        sysd = H.System(d=r.d, n=r.n, box_l=r.box_l, potential=H.HDMD_HARMONIC, cutoff=1.0,
+                        skin=r.skin, sigma_max=float(r.sig.max()), precision=prec,
+                        max_neighbors=w)
+        tot += H.hdmd_workspace_bytes(sysd) + r.n * (r.d + 1) * 8 * 2
+    return tot
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200, help="K: steps of each timed window")
+    ap.add_argument("--warmup", type=int, default=50, help="W: untimed steps before the windows")
+    ap.add_argument("--windows", type=int, default=3, help="timed windows (median reported)")
     ap.add_argument("--config", default="c3")
     ap.add_argument("--pushoff-iters", type=int, default=1500)
+    ap.add_argument("--equil-steps", type=int, default=1000,
+                    help="untimed FP64 steps after the pushoff and velocity draw")
+    ap.add_argument("--long-steps", type=int, default=10000,
+                    help="steps of the production-mode run per precision (0: skip)")
+    ap.add_argument("--thermostat-tau", type=float, default=None,
+                    help="Berendsen time constant of the MD legs (default: NVE, except 1.0 "
+                         "for the paper's state point p6, NVT at its T)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
@@ -338,9 +475,12 @@ def main():
     ap.add_argument("--fire-requests", type=int, default=512)
     ap.add_argument("--fire-rate", type=float, default=200.0, help="Poisson arrivals per second")
     ap.add_argument("--fire-tol", type=float, default=1e-5, help="|F|max target of both legs")
+    ap.add_argument("--fire-tight-tol", type=float, default=1e-10,
+                    help="|F|max target of the batched FP64 leg on the prefix (0: skip)")
     ap.add_argument("--fire-max-iter", type=int, default=100000)
     ap.add_argument("--fire-slots", type=int, default=512)
-    ap.add_argument("--fire-budget-gb", type=float, default=64.0)
+    ap.add_argument("--fire-budget-gb", type=float, default=0.25,
+                    help="HBM budget of the server's admission (below the stream's footprint)")
     ap.add_argument("--fire-chunk", type=int, default=50)
     ap.add_argument("--no-md", action="store_true", help="skip the MD legs (FIRE serving only)")
     ap.add_argument("--swap-attempts", type=int, default=20000,
@@ -370,6 +510,8 @@ def main():
     from paper_2112_12271_amd import inputs
 
     cfg = inputs.CONFIGS[args.config]
+    tau = args.thermostat_tau if args.thermostat_tau is not None else (
+        1.0 if args.config == "p6" else 0.0)
     torch.cuda.set_device(0)
     H.lib()
     sig = cfg.diameters()
@@ -378,6 +520,7 @@ def main():
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
     out = {}
+    setup = {}
     if not args.no_md:
         # untimed set-up: FIRE pushoff of the overlaps on harmonic soft spheres
         t = time.perf_counter()
@@ -386,31 +529,30 @@ def main():
         X = dev(x0)
         sysh, res = H.fire_auto(sysh, X, dev(sig),
                                 H.hdmd_fire_defaults(0.05, 1e-6, args.pushoff_iters))
-        xr = X.cpu().numpy()
         log("pushoff: %d FIRE iterations, %d builds, E/N=%.4g, |F|max=%.3g, %.1fs"
             % (res.iterations, res.builds, res.energy / cfg.n, res.fmax, time.perf_counter() - t))
-        v0 = cfg.velocities()
+        SIG = dev(sig)
+        V = dev(cfg.velocities())
+        setup["pushoff_iterations"] = int(res.iterations)
+        if args.equil_steps > 0:
+            # untimed equilibration in FP64 (the heating right after the pushoff)
+            t = time.perf_counter()
+            se = md_system(H, cfg, L, sig, H.HDMD_FP64, tau=tau)
+            se, st, _ = H.step_auto(se, X, V, SIG, args.equil_steps, cfg.dt)
+            setup.update(equil_steps=args.equil_steps, equil_builds=int(st.builds),
+                         T_after_equil=2 * st.ke / (cfg.d * (cfg.n - 1)))
+            log("equilibration: %d steps, %d builds, T=%.3f, %.1fs"
+                % (args.equil_steps, st.builds, setup["T_after_equil"], time.perf_counter() - t))
+        xr = X.cpu().numpy()
 
         for prec in ([H.HDMD_FP64] + ([] if args.no_mixed else [H.HDMD_MIXED])):
             name = "fp64" if prec == H.HDMD_FP64 else "mixed"
-            r = run_md(H, torch, cfg, xr, v0, sig, L, prec, args.steps, args.warmup, 10,
-                       not args.no_profile)
-            st = r["stats"]
-            sl, fl = drift(r["thermo"], cfg.n, cfg.dt)
-            rate = cfg.n * args.steps / r["seconds"]
-            rec = dict(value=rate, ms_per_step=1e3 * r["seconds"] / args.steps, builds=int(st.builds),
-                       steps_per_build=args.steps / max(st.builds, 1), mean_row=r["mean_row"],
-                       max_row=int(st.max_row), width=r["width"], drift_per_tau=sl, rms_fluct=fl,
-                       T_end=2 * st.ke / (cfg.d * (cfg.n - 1)))
-            if st.step_kernels > 0:
-                avg_ms = st.step_kernel_ms / st.step_kernels
-                bpa = step_bytes_per_atom(cfg.d, r["mean_row"], prec == H.HDMD_MIXED)
-                ach = cfg.n * bpa / (avg_ms * 1e-3) / 1e9
-                rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
-                           build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
-                           build_candidates=r["candidates"],
-                           share_step_kernel=st.step_kernel_ms / (1e3 * r["seconds"]),
-                           share_build_kernel=st.build_kernel_ms / (1e3 * r["seconds"]))
+            win, meta = run_windows(H, torch, cfg, X, V, SIG, L, prec, args.steps, args.warmup,
+                                    args.windows, 0, not args.no_profile, tau)
+            rec = window_record(cfg, prec == H.HDMD_MIXED, win, meta, args.steps)
+            if args.long_steps > 0:
+                rec["long_run"] = run_long(H, torch, cfg, X, V, SIG, L, prec, args.long_steps,
+                                           10, tau)
             out[name] = rec
             log(name, json.dumps(rec))
         if args.swap_attempts > 0:
@@ -428,7 +570,7 @@ def main():
                 "kernel": "k_step<6,fp64>", "bytes_per_launch": cfg.n * f["step_bytes_per_atom"],
                 "launch_ms": f["step_kernel_ms"]}
     # the list build against the vector ALU peak: every candidate pair of the
-    # subcell stencil (Sec. II.B) costs ceil(d/2) packed int16 dot products
+    # subcell stencil (Sec. II.C) costs ceil(d/2) packed int16 dot products
     # and a compare in the prefilter, one VALU lane-operation each; the peak
     # is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second.
     # (Row culling skips most candidates before any test, so the kernel's own
@@ -444,8 +586,10 @@ def main():
                       "launch_ms": f["build_ms"], "lane_ops_per_candidate": ops}
     cpu = None
     if not args.no_cpu_baseline and not args.no_md:
-        cpu = cpu_baseline(cfg, f["steps_per_build"])
+        spb = f.get("long_run", f)["steps_per_build"]
+        cpu = cpu_baseline(cfg, spb)
         log("cpu baseline", json.dumps(cpu))
+    lr = {k: out[k].get("long_run") for k in ("fp64", "mixed") if k in out}
     line = {
         "metric": "atom-steps/s at d=6,N=262144; batched FIRE solves/s + p50/p99 latency",
         "value": f.get("value"),
@@ -458,16 +602,22 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded uniform positions relaxed by harmonic FIRE, Gaussian T=1)",
-        "config": {"workload": workload_name(cfg),
-                   "precision": "fp64", "timed_with_events": not args.no_profile},
+        "data": "synthetic (seeded uniform positions relaxed by harmonic FIRE, Gaussian T=1, "
+                "untimed equilibration)",
+        "config": {"workload": workload_name(cfg), "precision": "fp64",
+                   "ensemble": "NVT Berendsen tau=%g" % tau if tau > 0 else "NVE",
+                   "timed": "median of %d windows of K steps, kernels launched one by one with "
+                            "HIP events" % args.windows if not args.no_profile else
+                            "median of %d windows of K steps, captured graphs" % args.windows},
+        "setup": setup,
         "roofline": roof,
         "roofline_build": roof_build,
         "cpu_baseline": cpu,
         "fp64": out.get("fp64"),
         "mixed": out.get("mixed"),
-        "drift_difference_mixed_minus_fp64": (out["mixed"]["drift_per_tau"] - f["drift_per_tau"])
-        if "mixed" in out and f else None,
+        "drift_difference_mixed_minus_fp64":
+            (lr["mixed"]["drift_per_tau"] - lr["fp64"]["drift_per_tau"])
+            if lr.get("mixed") and lr.get("fp64") else None,
         "fire_serving": fire,
         "swap": out.get("swap"),
     }

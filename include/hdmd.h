@@ -181,6 +181,22 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
               size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
               hdmd_step_stats* stats, void* stream);
 
+/* Continues the velocity-Verlet run (Sec. II.B, as hdmd_step) that the last
+ * hdmd_step or hdmd_step_resume call left in ws, without reloading the state
+ * or rebuilding the Verlet list: the list, the subcell order and the
+ * reference positions of the rebuild trigger carry over, so a run split into
+ * calls costs no extra list build per call.  pos, vel and diam must be the
+ * arrays that call returned (checked bit for bit on the device; else
+ * HDMD_ERR_STATE, arrays untouched), sys the same system (else
+ * HDMD_ERR_STATE); thermostat_tau and target_temp may change.  The
+ * displacement observables restart from zero at this call's step 0.  The
+ * trajectory equals that of one longer call up to rounding of the force sums
+ * (the atoms' order and the list differ from a fresh build's).  Other
+ * arguments, outputs and errors as hdmd_step.  Synchronises. */
+int hdmd_step_resume(const hdmd_system* sys, double* pos, double* vel, const double* diam,
+                     void* ws, size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every,
+                     double* thermo, hdmd_step_stats* stats, void* stream);
+
 /* Self part of the van Hove function (eq. VGC, Sec. II.E) after an
  * hdmd_step call that returned HDMD_OK on this workspace (no other call on it
  * since): with dr_i the unwrapped displacement of atom i from that call's
@@ -208,10 +224,13 @@ int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbi
  * The outcome is that of the serial walk the paper runs on one thread; the
  * attempts are evaluated in batches and settled in order (an attempt waits
  * for the next batch when an earlier kept or waiting attempt of its batch
- * has an atom within cutoff * sigma_max of one of its atoms).  Allocates and
- * frees 8 n_att + 2 KiB bytes of device scratch.  Errors: HDMD_ERR_ARG (an
- * id outside [0, n), temperature <= 0, ...), HDMD_ERR_WORKSPACE, HDMD_ERR_HIP
- * and the load errors of hdmd_build_nlist.  Synchronises. */
+ * has an atom within cutoff * sigma_max of one of its atoms).  Its scratch
+ * (round counters, the queues of put-off attempts, a batch's dE and
+ * conflict masks: about 16 KiB, whatever n_att) is part of ws; the library
+ * allocates nothing.  The pair ids are checked on the device before any
+ * change.  Errors: HDMD_ERR_ARG (an id outside [0, n), temperature <= 0,
+ * ...), HDMD_ERR_WORKSPACE, HDMD_ERR_HIP and the load errors of
+ * hdmd_build_nlist.  Synchronises. */
 int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
               int64_t n_att, const int32_t* pairs, const double* u, double temperature,
               int32_t* accepted, int64_t* n_accepted, void* stream);

@@ -15,12 +15,22 @@
  *
  * Each function names the passage of the paper it follows.  Where the paper is
  * silent or garbled the reading taken is stated next to the code.
+ *
+ * Built with -fopenmp (a second library, used only to time the CPU baseline),
+ * the per-atom force loop and the per-subcell list loop run on all host
+ * threads: the paper's own parallelisation (per-atom getforce and per-subcell
+ * list build over threads, Sec. II intro).  Rows are sorted and forces summed
+ * per atom in the same order either way; only the total energy's summation
+ * order changes under OpenMP.
  */
 #define _DEFAULT_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_WCA 0
 #define ORC_HARMONIC 1
@@ -224,15 +234,32 @@ orc_list* orc_nlist_cells(int d, int64_t n, double L, const double* x, const dou
   int64_t nstencil = 1;
   for (int k = 0; k < d; k++) nstencil *= radix;
 
-  /* gather hits per atom, then emit sorted rows */
+  /* gather hits per atom (one buffer per thread), then emit sorted rows */
   int64_t* cnt = (int64_t*)calloc((size_t)n, sizeof(int64_t));
-  int64_t hcap = 16 * (n > 0 ? n : 1), nh = 0;
-  int32_t* hi = (int32_t*)malloc((size_t)hcap * sizeof(int32_t));
-  int32_t* hj = (int32_t*)malloc((size_t)hcap * sizeof(int32_t));
-  int* C = (int*)malloc((size_t)d * sizeof(int));
+  int nthr = 1;
+#ifdef _OPENMP
+  nthr = omp_get_max_threads();
+#endif
+  int64_t* hcaps = (int64_t*)malloc((size_t)nthr * sizeof(int64_t));
+  int64_t* nhs = (int64_t*)calloc((size_t)nthr, sizeof(int64_t));
+  int32_t** his = (int32_t**)malloc((size_t)nthr * sizeof(int32_t*));
+  int32_t** hjs = (int32_t**)malloc((size_t)nthr * sizeof(int32_t*));
+  for (int t = 0; t < nthr; t++) {
+    hcaps[t] = 16 * (n > 0 ? n : 1) / nthr + 16;
+    his[t] = (int32_t*)malloc((size_t)hcaps[t] * sizeof(int32_t));
+    hjs[t] = (int32_t*)malloc((size_t)hcaps[t] * sizeof(int32_t));
+  }
 
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
   for (int64_t I = 0; I < ncells; I++) {
     if (start[I] == start[I + 1]) continue; /* no atom i in this subcell */
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    int C[16];
     /* decode I into subcell coordinates, axis 0 most significant */
     int64_t t = I;
     for (int k = d - 1; k >= 0; k--) { C[k] = (int)(t % nc); t /= nc; }
@@ -253,32 +280,40 @@ orc_list* orc_nlist_cells(int d, int64_t n, double L, const double* x, const dou
           if (j == i) continue;
           double r2 = dist2(d, x + i * d, x + j * d, L);
           if (r2 < list_radius2(sig[i], sig[j], c, s)) {
-            if (nh == hcap) {
-              hcap *= 2;
-              hi = (int32_t*)realloc(hi, (size_t)hcap * sizeof(int32_t));
-              hj = (int32_t*)realloc(hj, (size_t)hcap * sizeof(int32_t));
+            if (nhs[tid] == hcaps[tid]) {
+              hcaps[tid] *= 2;
+              his[tid] = (int32_t*)realloc(his[tid], (size_t)hcaps[tid] * sizeof(int32_t));
+              hjs[tid] = (int32_t*)realloc(hjs[tid], (size_t)hcaps[tid] * sizeof(int32_t));
             }
-            hi[nh] = (int32_t)i;
-            hj[nh] = (int32_t)j;
-            nh++;
-            cnt[i]++;
+            his[tid][nhs[tid]] = (int32_t)i;
+            hjs[tid][nhs[tid]] = (int32_t)j;
+            nhs[tid]++;
+            cnt[i]++; /* atom i has one home subcell: one thread counts its row */
           }
         }
       }
     }
   }
+  int64_t nh = 0;
+  for (int t = 0; t < nthr; t++) nh += nhs[t];
   orc_list* l = list_new(n);
   for (int64_t i = 0; i < n; i++) l->row_ptr[i + 1] = l->row_ptr[i] + cnt[i];
   l->cap = nh > 0 ? nh : 1;
   l->cols = (int32_t*)realloc(l->cols, (size_t)l->cap * sizeof(int32_t));
   int64_t* pos = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
   for (int64_t i = 0; i < n; i++) pos[i] = l->row_ptr[i];
-  for (int64_t h = 0; h < nh; h++) l->cols[pos[hi[h]]++] = hj[h];
+  for (int t = 0; t < nthr; t++)
+    for (int64_t h = 0; h < nhs[t]; h++) l->cols[pos[his[t][h]]++] = hjs[t][h];
   l->nnz = nh;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
   for (int64_t i = 0; i < n; i++)
     qsort(l->cols + l->row_ptr[i], (size_t)(l->row_ptr[i + 1] - l->row_ptr[i]), sizeof(int32_t),
           cmp_i32);
-  free(pos); free(C); free(hi); free(hj); free(cnt);
+  for (int t = 0; t < nthr; t++) { free(his[t]); free(hjs[t]); }
+  free(his); free(hjs); free(nhs); free(hcaps);
+  free(pos); free(cnt);
   free(cell_of); free(start); free(members);
   return l;
 }
@@ -329,6 +364,9 @@ double orc_forces(int d, int64_t n, double L, const double* x, const double* sig
                   double eps, const int64_t* row_ptr, const int32_t* cols, double* F,
                   double* e_atom) {
   double etot = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(+ : etot)
+#endif
   for (int64_t i = 0; i < n; i++) {
     double ei = 0.0;
     for (int k = 0; k < d; k++) F[i * d + k] = 0.0;

@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hdmd_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")  # the same source with -fopenmp (CPU baseline)
 
 WCA = 0
 HARMONIC = 1
@@ -25,14 +26,20 @@ MORSE_A = 30.0
 WCA_CUT = 2.0 ** (1.0 / 6.0)
 
 
+def _compile(out: str, extra: list[str]) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(
+        ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
+         *extra, "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2 -ffp-contract=off, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
-             "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2 -ffp-contract=off, no fast-math), and
+    the same source with -fopenmp for the all-core CPU baseline."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            _compile(out, extra)
     return LIB
 
 
@@ -61,6 +68,7 @@ def fire_params(dt0=0.05, ftol=1e-10, maxiter=100000, etol=0.0, **kw) -> FirePar
 
 
 _lib = None
+_lib_omp = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -71,7 +79,23 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build(force=True)
-        L = C.CDLL(LIB)
+        _lib = _configure(C.CDLL(LIB))
+    return _lib
+
+
+def lib_omp():
+    """The OpenMP build (per-atom forces and per-subcell list build on all
+    threads); only the CPU baseline uses it."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(LIB_OMP) or os.path.getmtime(LIB_OMP) < os.path.getmtime(SRC):
+            build(force=True)
+        _lib_omp = _configure(C.CDLL(LIB_OMP))
+    return _lib_omp
+
+
+def _configure(L):
+    if True:
         L.orc_sphere_volume.restype = C.c_double
         L.orc_sphere_volume.argtypes = [C.c_int, C.c_double]
         L.orc_set_morse_a.restype = None
@@ -124,8 +148,7 @@ def lib():
         L.orc_fire_traced.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, _dp, _dp, C.POINTER(FireParams),
                                       C.POINTER(FireResult), C.c_void_p, C.c_int64]
-        _lib = L
-    return _lib
+    return L
 
 
 def _f64(a):
@@ -151,8 +174,8 @@ def wrap(x, L):
     return np.vectorize(lambda t: w(float(t), L))(x) if x.size else x.copy()
 
 
-def _take_list(h, n):
-    L = lib()
+def _take_list(h, n, L=None):
+    L = L or lib()
     nnz = L.orc_list_nnz(h)
     rp = np.zeros(n + 1, dtype=np.int64)
     cols = np.zeros(max(nnz, 1), dtype=np.int32)
@@ -168,11 +191,13 @@ def nlist_brute(x, sig, L, c, s):
     return _take_list(lib().orc_nlist_brute(d, n, L, x, _f64(sig), c, s), n)
 
 
-def nlist_cells(x, sig, L, c, s, ncell_override=0):
-    """The paper's subcell algorithm; canonical CSR (rows ascending)."""
+def nlist_cells(x, sig, L, c, s, ncell_override=0, omp=False):
+    """The paper's subcell algorithm; canonical CSR (rows ascending).  omp:
+    the OpenMP build (same rows)."""
     x = _f64(x)
     n, d = x.shape
-    return _take_list(lib().orc_nlist_cells(d, n, L, x, _f64(sig), c, s, ncell_override), n)
+    lb = lib_omp() if omp else lib()
+    return _take_list(lb.orc_nlist_cells(d, n, L, x, _f64(sig), c, s, ncell_override), n, lb)
 
 
 def nlist_row(x, sig, L, c, s, i):
@@ -188,13 +213,14 @@ def nlist_row(x, sig, L, c, s, i):
         cap = int(m)
 
 
-def forces(x, sig, L, pot, c, eps, rp, cols):
-    """(F (n,d), per-atom energy (n,), total energy) from a CSR list."""
+def forces(x, sig, L, pot, c, eps, rp, cols, omp=False):
+    """(F (n,d), per-atom energy (n,), total energy) from a CSR list.  omp: the
+    OpenMP build (same forces; the total energy summed in another order)."""
     x = _f64(x)
     n, d = x.shape
     F = np.zeros((n, d))
     e = np.zeros(n)
-    E = lib().orc_forces(d, n, L, x, _f64(sig), pot, c, eps, np.ascontiguousarray(rp, np.int64),
+    E = (lib_omp() if omp else lib()).orc_forces(d, n, L, x, _f64(sig), pot, c, eps, np.ascontiguousarray(rp, np.int64),
                          np.ascontiguousarray(cols, np.int32), F, e)
     return F, e, E
 

@@ -405,6 +405,29 @@ void launch_slot_of(const SysDev* s, int n, int32_t* slot_of, hipStream_t st) {
   k_slot_of<<<(n + 255) / 256, 256, 0, st>>>(s, slot_of);
 }
 
+// SWAP set-up: zeroes the round counters (ctl[0..2]) and flags in ctl[3] any
+// pair id outside [0, n).
+__global__ __launch_bounds__(256) void k_swap_init(int64_t n_att, const int32_t* pairs, int n,
+                                                   long long* ctl) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = 0;
+  }
+  bool bad = false;
+  for (int64_t k = t; k < 2 * n_att; k += (int64_t)gridDim.x * 256) {
+    const int32_t v = pairs[k];
+    bad = bad || v < 0 || v >= n;
+  }
+  if (bad) atomicOr(reinterpret_cast<unsigned long long*>(ctl + 3), 1ull);
+}
+
+void launch_swap_init(int64_t n_att, const int32_t* pairs, int n, long long* ctl, hipStream_t st) {
+  const int64_t g = (2 * n_att + 255) / 256;
+  k_swap_init<<<(int)(g < 1 ? 1 : (g > 1024 ? 1024 : g)), 256, 0, st>>>(n_att, pairs, n, ctl);
+}
+
 void launch_reduce_pe(const SysDev* s, double* out, hipStream_t st) {
   k_reduce_pe<<<1, 256, 0, st>>>(s, out);
 }

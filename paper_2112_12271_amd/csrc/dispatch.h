@@ -10,6 +10,10 @@ struct DKernels {
                const double* diam, const double* vel);
   void (*unload)(bool mix, const SysDev* s, int grid, hipStream_t st, double* pos, double* vel,
                  double* force);
+  // resume check (caller arrays == workspace state) and displacement restart
+  void (*same_state)(bool mix, SysDev* s, int grid, hipStream_t st, const double* pos,
+                     const double* vel, const double* diam);
+  void (*disp_restart)(SysDev* s, int grid, hipStream_t st);
   void (*bin)(const KArgs& a, int grid, hipStream_t st);
   void (*cellsort)(bool mix, const KArgs& a, int grid, hipStream_t st);
   // blk: workgroup size of the home-atom-lane build (64/128/256), or 1 for the
@@ -22,13 +26,14 @@ struct DKernels {
   void (*fire_update)(bool mix, const KArgs& a, int grid, hipStream_t st);
   void (*vanhove)(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
                   unsigned long long* hist, double* disp);
-  // SWAP Monte Carlo: dE of a batch, then its settlement (kernels.h)
-  void (*swap_de)(const SysDev* s, hipStream_t st, const int32_t* todo, int nb, const int32_t* pairs,
-                  const int32_t* slot_of, double* de, unsigned long long* conf);
-  void (*swap_settle)(SysDev* s, hipStream_t st, const int32_t* todo_in, int n_todo, int nb,
-                      int32_t* todo_out, const int32_t* pairs, const double* u, double T,
-                      const int32_t* slot_of, const double* de, const unsigned long long* conf,
-                      int32_t* acc, double* diam, long long* ctl);
+  // SWAP Monte Carlo: dE of a round's batch, then its settlement (kernels.h)
+  void (*swap_de)(const SysDev* s, hipStream_t st, const long long* ctl, const int32_t* off_in,
+                  int64_t n_att, const int32_t* pairs, const int32_t* slot_of, double* de,
+                  unsigned long long* conf);
+  void (*swap_settle)(SysDev* s, hipStream_t st, long long* ctl, const int32_t* off_in,
+                      int32_t* off_out, int64_t n_att, const int32_t* pairs, const double* u,
+                      double T, const int32_t* slot_of, const double* de,
+                      const unsigned long long* conf, int32_t* acc, double* diam);
 };
 
 const DKernels* dkernels(int d);
@@ -54,6 +59,8 @@ void launch_finalize(const KArgs& a, int grid, hipStream_t st);
 void launch_fire_ctrl(const KArgs& a, int grid, hipStream_t st);
 void launch_reduce_pe(const SysDev* s, double* out, hipStream_t st);
 void launch_slot_of(const SysDev* s, int n, int32_t* slot_of, hipStream_t st);
+// SWAP set-up: every pair id in [0, n) (else ctl[3] = 1), counters zeroed
+void launch_swap_init(int64_t n_att, const int32_t* pairs, int n, long long* ctl, hipStream_t st);
 void launch_export(const SysDev* s, int n, int64_t* row_ptr, int32_t* cols, hipStream_t st,
                    int phase);
 void launch_set_status(SysDev* s, int32_t status, hipStream_t st);

@@ -127,7 +127,8 @@ struct SysDev {
   double ke, pe;
   double fdt, falpha, fmax, c_dt, c_keep, c_mix;
   double vscale;  // Berendsen factor of the next full-step kick (1: none)
-  int32_t npos, nneg, c_zero, pad2;
+  int32_t npos, nneg, c_zero;
+  int32_t differ;  // set by k_same_state when the caller's arrays differ from the state
 };
 
 // Tile tables of a batch: one list per dimension class (index d).

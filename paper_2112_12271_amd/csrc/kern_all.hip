@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_cellsort_all(KArgs a) {
 template <bool MORSE>
 __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
   __shared__ double sh[kPart];
+  __shared__ vd2 stage[kStage16];
   for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
@@ -138,8 +139,8 @@ __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
     switch (s->d) {
 #define HDMD_CASE(DD)                                           \
   case DD:                                                      \
-    if (mix) force_tile<DD, true, 1, MORSE>(s, tile, fire, sh); \
-    else force_tile<DD, false, 1, MORSE>(s, tile, fire, sh);    \
+    if (mix) force_tile<DD, true, 1, MORSE>(s, tile, fire, sh, stage); \
+    else force_tile<DD, false, 1, MORSE>(s, tile, fire, sh, stage);    \
     break;
       HDMD_BUILD_D(HDMD_CASE)
 #undef HDMD_CASE

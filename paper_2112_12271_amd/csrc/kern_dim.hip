@@ -21,6 +21,14 @@ void l_unload(bool mix, const SysDev* s, int grid, hipStream_t st, double* pos, 
   if (mix) k_unload<D, float><<<grid, kTile, 0, st>>>(s, pos, vel, force);
   else k_unload<D, double><<<grid, kTile, 0, st>>>(s, pos, vel, force);
 }
+void l_same_state(bool mix, SysDev* s, int grid, hipStream_t st, const double* pos, const double* vel,
+                  const double* diam) {
+  if (mix) k_same_state<D, float><<<grid, kTile, 0, st>>>(s, pos, vel, diam);
+  else k_same_state<D, double><<<grid, kTile, 0, st>>>(s, pos, vel, diam);
+}
+void l_disp_restart(SysDev* s, int grid, hipStream_t st) {
+  k_disp_restart<D><<<grid, kTile, 0, st>>>(s);
+}
 void l_bin(const KArgs& a, int grid, hipStream_t st) { k_bin<D><<<grid, kTile, 0, st>>>(a); }
 void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
   if (mix) k_cellsort<D, float><<<grid, 256, 0, st>>>(a);
@@ -88,18 +96,19 @@ void l_vanhove(const SysDev* s, int grid, hipStream_t st, int nbins, double w,
                unsigned long long* hist, double* disp) {
   k_vanhove<D><<<grid, kTile, 0, st>>>(s, nbins, w, hist, disp);
 }
-void l_swap_de(const SysDev* s, hipStream_t st, const int32_t* todo, int nb, const int32_t* pairs,
-               const int32_t* slot_of, double* de, unsigned long long* conf) {
-  k_swap_de<D><<<nb, 1024, 0, st>>>(s, todo, nb, pairs, slot_of, de, conf);
+void l_swap_de(const SysDev* s, hipStream_t st, const long long* ctl, const int32_t* off_in,
+               int64_t n_att, const int32_t* pairs, const int32_t* slot_of, double* de,
+               unsigned long long* conf) {
+  k_swap_de<D><<<kSwapBatch, 1024, 0, st>>>(s, ctl, off_in, n_att, pairs, slot_of, de, conf);
 }
-void l_swap_settle(SysDev* s, hipStream_t st, const int32_t* todo_in, int n_todo, int nb,
-                   int32_t* todo_out, const int32_t* pairs, const double* u, double T,
+void l_swap_settle(SysDev* s, hipStream_t st, long long* ctl, const int32_t* off_in,
+                   int32_t* off_out, int64_t n_att, const int32_t* pairs, const double* u, double T,
                    const int32_t* slot_of, const double* de, const unsigned long long* conf,
-                   int32_t* acc, double* diam, long long* ctl) {
-  k_swap_settle<D><<<1, 1024, 0, st>>>(s, todo_in, n_todo, nb, todo_out, pairs, u, T, slot_of, de,
-                                       conf, acc, diam, ctl);
+                   int32_t* acc, double* diam) {
+  k_swap_settle<D><<<1, 1024, 0, st>>>(s, ctl, off_in, off_out, n_att, pairs, u, T, slot_of, de,
+                                       conf, acc, diam);
 }
-const DKernels table = {l_load, l_unload, l_bin, l_cellsort, l_build, l_force, l_step,
+const DKernels table = {l_load, l_unload, l_same_state, l_disp_restart, l_bin, l_cellsort, l_build, l_force, l_step,
                         l_fire_update, l_vanhove, l_swap_de, l_swap_settle};
 }  // namespace
 

@@ -100,6 +100,45 @@ __global__ __launch_bounds__(kTile) void k_unload(const SysDev* s, double* __res
   }
 }
 
+// Whether the caller's arrays (positions, velocities, diameters in caller
+// order) are bit for bit the state the workspace holds, as the last unload
+// wrote them; any difference sets s->differ.
+template <int D, typename VT>
+__global__ __launch_bounds__(kTile) void k_same_state(SysDev* s, const double* __restrict__ pos,
+                                                      const double* __restrict__ vel,
+                                                      const double* __restrict__ diam) {
+  const int p = blockIdx.x * kTile + threadIdx.x;
+  if (p >= s->n) return;
+  const int pc = s->pcur, npad = s->npad;
+  const int a = s->oid[pc][p];
+  double x[D], sg;
+  load_rec<D>(s->x[s->xcur], p, x, sg);
+  const VT* v = reinterpret_cast<const VT*>(s->v[pc]);
+  bool same = diam[a] == sg;
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    same = same && pos[(size_t)a * D + k] == x[k];
+    same = same && vel[(size_t)a * D + k] == double(v[(size_t)k * npad + p]);
+  }
+  if (!same) atomicOr(&s->differ, 1);
+}
+
+// The displacement observables of a continued run start from zero: the
+// displacement up to the last build is set to minus the part since it.
+template <int D>
+__global__ __launch_bounds__(kTile) void k_disp_restart(SysDev* s) {
+  const int p = blockIdx.x * kTile + threadIdx.x;
+  if (p >= s->npad) return;
+  const int pc = s->pcur, npad = s->npad;
+  double x[D];
+  load_x<D>(s->x[s->xcur], p, x);
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    const size_t o = (size_t)k * npad + p;
+    s->disp[pc][o] = p < s->n ? -min_image(x[k] - s->xref[o], s->L, s->hL) : 0.0;
+  }
+}
+
 // Unwrapped displacement of every atom since the MD call's step 0 (the
 // displacement up to the last build plus the minimum image of x - x_ref),
 // written in caller order to disp ([n][d], optional), and the histogram of
@@ -1306,20 +1345,35 @@ __device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[
   return pi == pj ? 0.0 : ea - eb;
 }
 
-// dE of the batch's attempts todo[0 .. nb), one workgroup each, with the
-// two diameters it was taken with: de[3b] = dE, de[3b+1], de[3b+2] = the
-// diameters of the first and the second atom.  conf[b][w] bit c: attempt
-// b' = 64 w + c < b has an atom within c sigma_max of an atom of attempt b.
+// The batch of a round: the nput attempts put off by the previous round
+// (off_in, in order) followed by the attempts cursor, cursor + 1, ... not yet
+// begun; kSwapBatch of them at most.  ctl[0] = nput, ctl[2] = cursor.
+__device__ inline int swap_batch_size(const long long* ctl, int64_t n_att) {
+  const long long rest = (long long)n_att - ctl[2];
+  const long long nb = ctl[0] + rest;
+  return (int)(nb < kSwapBatch ? nb : kSwapBatch);
+}
+__device__ inline int swap_attempt(const long long* ctl, const int32_t* off_in, int b) {
+  const int nput = (int)ctl[0];
+  return b < nput ? off_in[b] : (int)(ctl[2] + (b - nput));
+}
+
+// dE of the round's attempts, one workgroup each, with the two diameters it
+// was taken with: de[3b] = dE, de[3b+1], de[3b+2] = the diameters of the
+// first and the second atom.  conf[b][w] bit c: attempt b' = 64 w + c < b
+// has an atom within c sigma_max of an atom of attempt b.
 template <int D>
-__global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const int32_t* __restrict__ todo,
-                                                  int nb, const int32_t* __restrict__ pairs,
+__global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const long long* __restrict__ ctl,
+                                                  const int32_t* __restrict__ off_in, int64_t n_att,
+                                                  const int32_t* __restrict__ pairs,
                                                   const int32_t* __restrict__ slot_of,
                                                   double* __restrict__ de,
                                                   unsigned long long* __restrict__ conf) {
   __shared__ double red[2][16];
   const int b = blockIdx.x;
+  const int nb = swap_batch_size(ctl, n_att);
   if (b >= nb) return;
-  const int k = todo[b];
+  const int k = swap_attempt(ctl, off_in, b);
   const int pi = slot_of[pairs[2 * k]], pj = slot_of[pairs[2 * k + 1]];
   {
     const double* xb = s->x[s->xcur];
@@ -1328,7 +1382,7 @@ __global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const int32_t
     const int t = threadIdx.x;
     bool near = false;
     if (t < b) {
-      const int k2 = todo[t];
+      const int k2 = swap_attempt(ctl, off_in, t);
       const int q2[2] = {slot_of[pairs[2 * k2]], slot_of[pairs[2 * k2 + 1]]};
       for (int e = 0; e < 4; e++) {
         double xa[D], xc[D];
@@ -1354,32 +1408,33 @@ __global__ __launch_bounds__(1024) void k_swap_de(const SysDev* s, const int32_t
   }
 }
 
-// Settles the batch todo_in[0 .. nb) in order (see above), applies the kept
-// exchanges, and writes the attempts still to run (put off ones first) to
-// todo_out; ctl[0] = their number, ctl[1] += exchanges kept.
+// Settles the round's batch in order (see above), applies the kept exchanges,
+// and writes the attempts put off to off_out; ctl[0] = their number, ctl[2]
+// advances past the attempts begun, ctl[1] += exchanges kept.
 template <int D>
-__global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, const int32_t* __restrict__ todo_in,
-                                                      int n_todo, int nb,
-                                                      int32_t* __restrict__ todo_out,
+__global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, long long* __restrict__ ctl,
+                                                      const int32_t* __restrict__ off_in,
+                                                      int32_t* __restrict__ off_out, int64_t n_att,
                                                       const int32_t* __restrict__ pairs,
                                                       const double* __restrict__ u, double T,
                                                       const int32_t* __restrict__ slot_of,
                                                       const double* __restrict__ de,
                                                       const unsigned long long* __restrict__ cfg,
                                                       int32_t* __restrict__ acc,
-                                                      double* __restrict__ diam,
-                                                      long long* __restrict__ ctl) {
+                                                      double* __restrict__ diam) {
   constexpr int DR = Dims<D>::DR, NW = kSwapBatch / 64;
   __shared__ unsigned long long conf[kSwapBatch][NW];
   __shared__ int put_off[kSwapBatch];
   __shared__ int att[kSwapBatch], cid[kSwapBatch][2], slot[kSwapBatch][2];
-  __shared__ double thr[kSwapBatch];  // u_k, then the Metropolis decision as 0 / 1
-  __shared__ int n_off;
+  __shared__ double thr[kSwapBatch];  // the Metropolis decision as 0 / 1
   const int tid = threadIdx.x;
+  const int nb = swap_batch_size(ctl, n_att);
+  if (nb <= 0) return;
+  const int nput = (int)ctl[0];
   double* xb = s->x[s->xcur];
   for (int t = tid; t < nb * NW; t += blockDim.x) conf[t / NW][t % NW] = cfg[t];
   for (int t = tid; t < 2 * nb; t += blockDim.x) {
-    const int b = t >> 1, e = t & 1, k = todo_in[b];
+    const int b = t >> 1, e = t & 1, k = swap_attempt(ctl, off_in, b);
     const int c = pairs[2 * k + e], q = slot_of[c];
     cid[b][e] = c;
     slot[b][e] = q;
@@ -1419,14 +1474,11 @@ __global__ __launch_bounds__(1024) void k_swap_settle(SysDev* s, const int32_t* 
         blk[b >> 6] |= 1ull << (b & 63);
       }
     }
-    n_off = noff;
-    ctl[0] = noff + (n_todo - nb);
+    for (int b = 0; b < noff; b++) off_out[b] = put_off[b];
+    ctl[2] += nb - nput;
+    ctl[0] = noff;
     ctl[1] += kept;
   }
-  __syncthreads();
-  const int noff = n_off;
-  for (int t = tid; t < noff; t += blockDim.x) todo_out[t] = put_off[t];
-  for (int t = nb + tid; t < n_todo; t += blockDim.x) todo_out[noff + t - nb] = todo_in[t];
 }
 
 // Own atom's data as the force loop needs it.
@@ -1551,6 +1603,142 @@ __device__ inline void force_part(const SysDev* s, int i, int sub, const Own<D, 
   for (int k = 0; k < D; k++) F[k] = FT(Fs[k]);
 }
 
+// Partial force of one lane per atom (the whole row), with the neighbour
+// records staged through LDS.  A gather in which every lane loads its own
+// neighbour's record touches as many cache lines per load instruction as
+// there are lanes; here the wave loads the records of R row entries of all 64
+// lanes cooperatively (RB/16 lanes share one record, one 16-byte piece each,
+// so an instruction covers 16 / 32 / 64 whole records) straight into LDS
+// (global_load_lds_dwordx4), then every lane reads its own records back.  The
+// pairs are summed in row order, exactly as force_part does, so the results
+// are the same bits.  The loop runs to the longest row of the wave; the
+// pieces of record r sit rotated by r in its LDS slot so that the lanes'
+// reads spread over the banks.  stage: kStage16 16-byte slots of LDS.
+constexpr int kStage16 = 512;  // 8 KiB per wave
+
+template <int D, bool MIX>
+struct StageGeom {
+  static constexpr int RB = MIX ? Dims<D>::DQ * 4 : Dims<D>::DR * 8;  // record bytes
+  static constexpr int PR = RB / 16;                                  // pieces per record
+  static constexpr int R = kStage16 / (64 * PR);                      // rows entries per pass
+};
+
+template <int D, bool MIX, typename FT, bool MORSE>
+__device__ inline void force_part_lds(const SysDev* s, int i, bool vi, const Own<D, MIX>& me,
+                                      FT (&F)[D], double& e, double& w, double& z, vd2* stage) {
+  typedef StageGeom<D, MIX> G;
+  constexpr int PR = G::PR, R = G::R, RPI = 64 / PR;  // records per load instruction
+  static_assert(R >= 1 && R * 64 * PR <= kStage16, "stage size");
+  const int lane = threadIdx.x & 63;
+  const int npad = s->npad, W = s->width;
+  const int len = vi ? min(gbl(s->nlen)[i], W) : 0;
+  const int mx = uniform_int(wave_max_i(len));
+  const HDMD_GLOBAL int* __restrict__ nl = gbl(s->nl);
+  const double L = s->L, c = s->cutoff, eps = s->eps, invL = 1.0 / L, ma = s->morse_a;
+  const int pot = s->potential;
+  const char* __restrict__ base =
+      MIX ? reinterpret_cast<const char*>(s->q[s->xcur]) : reinterpret_cast<const char*>(s->x[s->xcur]);
+  const double fxinv = s->fxinv;
+  double Fs[D];
+#pragma unroll
+  for (int k = 0; k < D; k++) Fs[k] = 0.0;
+  e = 0.0;
+  w = 0.0;
+  z = 0.0;
+  for (int k0 = 0; k0 < mx; k0 += R) {
+    int j[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int kk = k0 + r;
+      const int raw = nl[(size_t)min(kk, W - 1) * npad + i];
+      j[r] = kk < len ? raw : -1;
+    }
+    wave_lds_sync();  // the previous pass's reads of the stage are done
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+#pragma unroll
+      for (int q = 0; q < PR; q++) {
+        // lane t loads piece ((t % PR) - rec) mod PR of record rec = q RPI + t / PR
+        // of this round into slot t % PR: LDS byte 16 t of the instruction's 1 KiB
+        const int rec = q * RPI + lane / PR;
+        const int jr = PR == 1 ? j[r] : __shfl(j[r], rec, 64);
+        const int piece = ((lane % PR) - rec) & (PR - 1);
+        const char* src = base + (size_t)(jr >= 0 ? jr : 0) * G::RB + 16 * piece;
+        __builtin_amdgcn_global_load_lds((const void*)src, (void*)(stage + (r * PR + q) * 64), 16, 0,
+                                         0);
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      // own record of this round: pieces p at slots (p + lane) mod PR
+      const vd2* rec = stage + r * PR * 64 + lane * PR;
+      if (!MIX) {
+        double xj[D], sj = 0.0;
+        vd2 pc[PR];
+#pragma unroll
+        for (int p = 0; p < PR; p++) pc[p] = rec[(p + lane) & (PR - 1)];
+#pragma unroll
+        for (int k = 0; k < D; k++) xj[k] = (k & 1) ? pc[k >> 1].y : pc[k >> 1].x;
+        sj = (D & 1) ? pc[D >> 1].y : pc[D >> 1].x;
+        if (j[r] < 0) continue;
+        const double sij = 0.5 * (me.sg + sj);
+        const double rc = c * sij;
+        double dx[D];
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          dx[k] = near_image(xj[k] - me.x[k], L, invL);
+          r2 = __builtin_fma(dx[k], dx[k], r2);
+        }
+        if (r2 < rc * rc) {
+          double fc, uu;
+          pair_f64<MORSE>(pot, eps, ma, r2, sij, fc, uu);
+#pragma unroll
+          for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
+          e += 0.5 * uu;
+          w += 0.5 * fc * r2;
+          z += 1.0;
+        }
+      } else {
+        constexpr int SQ = Dims<D>::SQ;
+        int v[4 * PR];
+#pragma unroll
+        for (int p = 0; p < PR; p++) {
+          const vi4 t = reinterpret_cast<const vi4*>(rec)[(p + lane) & (PR - 1)];
+          v[4 * p] = t.x;
+          v[4 * p + 1] = t.y;
+          v[4 * p + 2] = t.z;
+          v[4 * p + 3] = t.w;
+        }
+        const double sj = __longlong_as_double(
+            (long long)(((unsigned long long)(unsigned)v[SQ + 1] << 32) | (unsigned)v[SQ]));
+        if (j[r] < 0) continue;
+        const double sij = 0.5 * (me.sg + sj);
+        const double rc = c * sij;
+        double dx[D];
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          dx[k] = (double)(int)(v[k] - me.u[k]) * fxinv;  // two's complement = minimum image
+          r2 = __builtin_fma(dx[k], dx[k], r2);
+        }
+        if (r2 < rc * rc) {
+          double fc, uu;
+          pair_f64<MORSE>(pot, eps, ma, r2, sij, fc, uu);
+#pragma unroll
+          for (int k = 0; k < D; k++) Fs[k] -= fc * dx[k];
+          e += 0.5 * uu;
+          w += 0.5 * fc * r2;
+          z += 1.0;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < D; k++) F[k] = FT(Fs[k]);
+}
+
 template <int D, bool MIX>
 __device__ inline void load_own(const SysDev* s, int i, Own<D, MIX>& me) {
   load_rec<D>(s->x[s->xcur], i, me.x, me.sg);
@@ -1624,7 +1812,7 @@ __device__ inline bool kernel_serves(const SysDev* s, bool mix, bool morse) {
 }
 
 template <int D, bool MIX, int LPA, bool MORSE>
-__device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
+__device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh, vd2* stage) {
   typedef typename VType<MIX>::T FT;
   const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
   const int i = tile * kTile + slot;
@@ -1635,7 +1823,8 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
   load_own<D, MIX>(s, ii, me);
   FT F[D];
   double e, w, z;
-  force_part<D, MIX, LPA, FT, MORSE>(s, ii, sub, me, F, e, w, z);
+  if constexpr (LPA == 1) force_part_lds<D, MIX, FT, MORSE>(s, ii, vi, me, F, e, w, z, stage);
+  else force_part<D, MIX, LPA, FT, MORSE>(s, ii, sub, me, F, e, w, z);
   double vals[kPart], mx = 0.0;
 #pragma unroll
   for (int p = 0; p < kPart; p++) vals[p] = 0.0;
@@ -1665,13 +1854,14 @@ __device__ inline void force_tile(SysDev* s, int tile, int fire, double* sh) {
 template <int D, bool MIX, int LPA, bool MORSE>
 __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
   __shared__ double sh[LPA * kPart];
+  __shared__ vd2 stage[LPA == 1 ? kStage16 : 1];
   for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
     if (!running(s) || !kernel_serves(s, MIX, MORSE)) continue;
     if (fire && s->mode != MODE_FIRE) continue;
-    force_tile<D, MIX, LPA, MORSE>(s, tile, fire, sh);
+    force_tile<D, MIX, LPA, MORSE>(s, tile, fire, sh, stage);
   }
 }
 
@@ -1691,6 +1881,7 @@ template <int D, bool MIX, int LPA, bool MORSE>
 __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
   typedef typename VType<MIX>::T VT;
   __shared__ double sh[LPA * kPart];
+  __shared__ vd2 stage[LPA == 1 ? kStage16 : 1];
   const int sub = threadIdx.x % LPA, slot = threadIdx.x / LPA;
   for (int t = xcd_tile(blockIdx.x, gridDim.x);; t += gridDim.x) {
     SysDev* s;
@@ -1708,7 +1899,8 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     load_own<D, MIX>(s, ii, me);
     VT F[D];
     double e, w, z;
-    force_part<D, MIX, LPA, VT, MORSE>(s, ii, sub, me, F, e, w, z);
+    if constexpr (LPA == 1) force_part_lds<D, MIX, VT, MORSE>(s, ii, vi, me, F, e, w, z, stage);
+    else force_part<D, MIX, LPA, VT, MORSE>(s, ii, sub, me, F, e, w, z);
     double vals[kPart], mx = 0.0;
 #pragma unroll
     for (int p = 0; p < kPart; p++) vals[p] = 0.0;

@@ -37,6 +37,29 @@ static int fail(int code, const std::string& msg) {
 
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// SWAP Monte Carlo scratch (fixed size, whatever the number of attempts):
+// round counters, the two put-off queues, a batch's dE and conflict masks.
+struct SwapScratch {
+  long long* ctl;      // [0] attempts put off, [1] kept, [2] next attempt not begun, [3] bad id
+  int32_t* off[2];     // put-off queues, kSwapBatch each
+  double* de;          // 3 kSwapBatch
+  unsigned long long* conf;  // kSwapBatch x kSwapBatch/64
+};
+constexpr size_t kSwapCtlBytes = 256, kSwapOffBytes = kSwapBatch * 4;
+constexpr size_t kSwapDeBytes = 3 * kSwapBatch * 8, kSwapConfBytes = kSwapBatch * (kSwapBatch / 64) * 8;
+constexpr size_t kSwapScratchBytes = kSwapCtlBytes + 2 * kSwapOffBytes + kSwapDeBytes + kSwapConfBytes;
+
+static SwapScratch swap_scratch(void* base) {
+  char* b = static_cast<char*>(base);
+  SwapScratch w;
+  w.ctl = reinterpret_cast<long long*>(b);
+  w.off[0] = reinterpret_cast<int32_t*>(b + kSwapCtlBytes);
+  w.off[1] = reinterpret_cast<int32_t*>(b + kSwapCtlBytes + kSwapOffBytes);
+  w.de = reinterpret_cast<double*>(b + kSwapCtlBytes + 2 * kSwapOffBytes);
+  w.conf = reinterpret_cast<unsigned long long*>(b + kSwapCtlBytes + 2 * kSwapOffBytes + kSwapDeBytes);
+  return w;
+}
+
 // ---------------------------------------------------------------------------
 // geometry and workspace plan
 // ---------------------------------------------------------------------------
@@ -50,7 +73,8 @@ struct Plan {
          off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_disp[2] = {0, 0}, off_ycell = 0, off_qc = 0, off_qc16 = 0,
          off_cell_of = 0,
          off_rank = 0, off_cell_count = 0, off_cell_flat = 0, off_cell_local = 0, off_chunk_sum = 0,
-         off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0;
+         off_chunk_off = 0, off_key = 0, off_src = 0, off_nl = 0, off_nlen = 0, off_part = 0,
+         off_swap = 0;
   size_t bytes = 0;
 };
 
@@ -145,6 +169,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.off_nl = take((size_t)p.width * np * 4);
   p.off_nlen = take(np * 4);
   p.off_part = take((size_t)p.nwaves * kPart * 8);
+  p.off_swap = take(kSwapScratchBytes);
   p.bytes = o;
   return HDMD_OK;
 }
@@ -326,21 +351,42 @@ static KArgs single_args(SysDev* dev, int d) {
   return a;
 }
 
-// bin -> scan -> scatter -> per-subcell sort/permute -> list build; every
-// kernel exits at once for systems that need no rebuild.
-static void chain_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+// bin -> scan -> scatter -> per-subcell sort/permute (chain_sort), then the
+// list build; every kernel exits at once for systems that need no rebuild.
+// The binning, placement and subcell-sort grids stride over their tiles:
+// at most 1024 workgroups, so that the launches of steps without a rebuild
+// (which exit at once) dispatch few of them.
+static void chain_sort(const Plan& p, SysDev* dev, hipStream_t st) {
   const DKernels* K = dkernels(p.d);
   KArgs a = single_args(dev, p.d);
-  // the binning, placement and subcell-sort grids stride over their tiles:
-  // at most 1024 workgroups, so that the launches of steps without a rebuild
-  // (which exit at once) dispatch few of them
   const int gt = std::min(p.ntiles, 1024), gc = std::min(p.ncells, 1024);
   K->bin(a, gt, st);
   launch_scan1(a, p.nchunks, st);
   launch_scan2(a, 1, st);
   launch_scatter(a, gt, st);
   K->cellsort(p.mix, a, gc, st);
-  K->build(p.wrap, blk, a, p.ncells, st);
+}
+
+static void chain_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+  chain_sort(p, dev, st);
+  dkernels(p.d)->build(p.wrap, blk, single_args(dev, p.d), p.ncells, st);
+}
+
+// HIP events of the profiling mode, created once (with the system fence
+// disabled, so that recording them neither writes back nor invalidates the
+// caches) and reused by later calls.
+static std::mutex g_ev_mu;
+static std::vector<hipEvent_t> g_events;
+
+static int event_pool(size_t n, std::vector<hipEvent_t>& out) {
+  std::lock_guard<std::mutex> g(g_ev_mu);
+  while (g_events.size() < n) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    g_events.push_back(e);
+  }
+  out.assign(g_events.begin(), g_events.begin() + n);
+  return HDMD_OK;
 }
 
 static int read_desc(const SysDev* dev, SysDev* host, hipStream_t st) {
@@ -361,7 +407,7 @@ static int err_to_status(int32_t err, const char* where) {
 // MODE_STATIC, running, with current buffers holding the sorted state).
 static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
                        const double* diam, const double* vel, void* ws, size_t ws_bytes,
-                       hipStream_t st, int* blk_out) {
+                       hipStream_t st, int* blk_out, bool allow_tune = true) {
   if (!pos || !diam || !ws) return fail(HDMD_ERR_ARG, "null device pointer");
   if (ws_bytes < p.bytes)
     return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
@@ -377,7 +423,7 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
   bool known = false;
   int blk = lookup_blk(p, &known);
   if (std::getenv("HDMD_BUILD_BLK")) known = true;
-  if (!known && tuning_enabled()) {
+  if (!known && tuning_enabled() && allow_tune) {
     // run the chain up to the build, then time each build variant
     KArgs a = single_args(dev, p.d);
     K->bin(a, p.ntiles, st);
@@ -577,14 +623,16 @@ int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_
   return HDMD_OK;
 }
 
-int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
-                size_t ws_bytes, double* force, double* energy, void* stream) {
-  Plan p;
-  int rc = make_plan(sys, p);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace hdmd {
+
+static int forces_run(const hdmd_system* sys, const Plan& p, const double* pos, const double* diam,
+                      void* ws, size_t ws_bytes, double* force, double* energy, void* stream,
+                      bool allow_tune) {
   if (!force || !energy) return fail(HDMD_ERR_ARG, "null output pointer");
   hipStream_t st = S(stream);
-  rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr);
+  int rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr, allow_tune);
   if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   const DKernels* K = dkernels(p.d);
@@ -598,34 +646,92 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
   return err_to_status(h.err, "hdmd_forces");
 }
 
+}  // namespace hdmd
+
+extern "C" {
+
+int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
+                size_t ws_bytes, double* force, double* energy, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  return forces_run(sys, p, pos, diam, ws, ws_bytes, force, energy, stream, true);
+}
+
 static int step_chunk_len() {
   const char* e = std::getenv("HDMD_CHUNK");
   int c = e ? std::atoi(e) : 50;
   return c < 1 ? 1 : c;
 }
 
-int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
-              size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
-              hdmd_step_stats* stats, void* stream) {
+}  // extern "C"
+
+namespace hdmd {
+
+// Whether the descriptor h (read from ws) is a completed MD run of exactly
+// this system (same plan and parameters, laid out in this workspace), as the
+// last hdmd_step / hdmd_step_resume on ws left it.
+static bool holds_run_of(const SysDev& h, const hdmd_system* sys, const Plan& p, void* ws) {
+  return h.d == p.d && h.n == p.n && h.npad == p.npad && h.ncell == p.ncell &&
+         h.width == p.width && h.precision == sys->precision && h.potential == sys->potential &&
+         h.L == sys->box_l && h.cutoff == sys->cutoff && h.skin == sys->skin &&
+         h.eps == sys->epsilon && h.sigma_max == sys->sigma_max &&
+         (sys->potential != HDMD_MORSE || h.morse_a == sys->morse_a) && h.mode == MODE_MD &&
+         h.status == SLOT_DONE && h.err == 0 && h.step > 0 &&
+         h.x[0] == at<double>(ws, p.off_x[0]) && h.nl == at<int32_t>(ws, p.off_nl);
+}
+
+// The MD run behind hdmd_step and hdmd_step_resume: a fresh call loads the
+// caller's state and builds the list; a resumed one checks on the device that
+// the caller's arrays are the state ws holds and continues from it.
+static int md_run(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
+                  size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
+                  hdmd_step_stats* stats, void* stream, bool resume) {
   Plan p;
   int rc = make_plan(sys, p);
   if (rc) return rc;
-  if (!vel) return fail(HDMD_ERR_ARG, "null velocity pointer");
+  if (!vel || !pos || !diam || !ws) return fail(HDMD_ERR_ARG, "null pointer");
   if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HDMD_ERR_ARG, "need nsteps >= 0 and dt > 0");
   if (sys->thermostat_tau > 0 && sys->thermostat_tau < dt)
     return fail(HDMD_ERR_ARG, "thermostat_tau must be >= dt");
   hipStream_t st = S(stream);
-  int blk = 0;
-  rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
-  if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   SysDev h;
-  rc = read_desc(dev, &h, st);
-  if (rc) return rc;
-  rc = err_to_status(h.err, "hdmd_step");
-  if (rc) {
-    if (stats) stats->max_row = h.max_row;
-    return rc;
+  int blk = 0;
+  const DKernels* K = dkernels(p.d);
+  if (resume) {
+    if (ws_bytes < p.bytes)
+      return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+    if (!holds_run_of(h, sys, p, ws))
+      return fail(HDMD_ERR_STATE, "hdmd_step_resume: the workspace holds no completed run of this system");
+    set_i32(dev, offsetof(SysDev, differ), 0, st);
+    K->same_state(p.mix, dev, p.ntiles, st, pos, vel, diam);
+    HIPCHK(hipGetLastError());
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+    if (h.differ)
+      return fail(HDMD_ERR_STATE,
+                  "hdmd_step_resume: pos, vel or diam differ from the state the last call returned");
+    K->disp_restart(dev, p.ntiles, st);
+    bool known = false;
+    blk = lookup_blk(p, &known);
+    h.tau_t = sys->thermostat_tau;
+    h.temp_t = sys->target_temp;
+    h.vscale = 1.0;
+    h.force_rebuild = 0;
+    h.status = SLOT_RUNNING;
+  } else {
+    rc = init_system(sys, p, pos, diam, vel, ws, ws_bytes, st, &blk);
+    if (rc) return rc;
+    rc = read_desc(dev, &h, st);
+    if (rc) return rc;
+    rc = err_to_status(h.err, "hdmd_step");
+    if (rc) {
+      if (stats) stats->max_row = h.max_row;
+      return rc;
+    }
   }
   const int64_t builds0 = h.builds;
   // switch the descriptor to MD mode
@@ -641,20 +747,16 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
   const bool profile = prof_env && prof_env[0] == '1';
   std::vector<hipEvent_t> ev;
   if (profile) {
-    // one launch at a time, fused-step and list-build kernels bracketed by events
-    const DKernels* K = dkernels(p.d);
+    // one launch at a time (the launches of the captured chunks), fused-step
+    // and list-build kernels bracketed by events
     KArgs a = single_args(dev, p.d);
-    ev.resize(4 * (size_t)(nsteps + 1));
-    for (auto& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    rc = event_pool(4 * (size_t)(nsteps + 1), ev);
+    if (rc) return rc;
     for (int64_t k = 0; k <= nsteps; k++) {
       HIPCHK(hipEventRecord(ev[4 * k], st));
       K->step(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, st);
       HIPCHK(hipEventRecord(ev[4 * k + 1], st));
-      K->bin(a, p.ntiles, st);
-      launch_scan1(a, p.nchunks, st);
-      launch_scan2(a, 1, st);
-      launch_scatter(a, p.ntiles, st);
-      K->cellsort(p.mix, a, p.ncells, st);
+      chain_sort(p, dev, st);
       HIPCHK(hipEventRecord(ev[4 * k + 2], st));
       K->build(p.wrap, blk, a, p.ncells, st);
       HIPCHK(hipEventRecord(ev[4 * k + 3], st));
@@ -701,13 +803,30 @@ int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* di
       stats->build_kernels = nb;
     }
   }
-  for (auto& e : ev) hipEventDestroy(e);
   rc = err_to_status(h.err, "hdmd_step");
   if (rc) return rc;  // caller arrays untouched
-  dkernels(p.d)->unload(p.mix, dev, p.ntiles, st, pos, vel, nullptr);
+  K->unload(p.mix, dev, p.ntiles, st, pos, vel, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return HDMD_OK;
+}
+
+}  // namespace hdmd
+
+extern "C" {
+
+int hdmd_step(const hdmd_system* sys, double* pos, double* vel, const double* diam, void* ws,
+              size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every, double* thermo,
+              hdmd_step_stats* stats, void* stream) {
+  return md_run(sys, pos, vel, diam, ws, ws_bytes, nsteps, dt, thermo_every, thermo, stats, stream,
+                false);
+}
+
+int hdmd_step_resume(const hdmd_system* sys, double* pos, double* vel, const double* diam,
+                     void* ws, size_t ws_bytes, int64_t nsteps, double dt, int64_t thermo_every,
+                     double* thermo, hdmd_step_stats* stats, void* stream) {
+  return md_run(sys, pos, vel, diam, ws, ws_bytes, nsteps, dt, thermo_every, thermo, stats, stream,
+                true);
 }
 
 int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbins,
@@ -736,9 +855,18 @@ int hdmd_van_hove(const hdmd_system* sys, void* ws, size_t ws_bytes, int32_t nbi
   return HDMD_OK;
 }
 
-int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
-              int64_t n_att, const int32_t* pairs, const double* u, double temperature,
-              int32_t* accepted, int64_t* n_accepted, void* stream) {
+}  // extern "C"
+
+namespace hdmd {
+
+// SWAP Monte Carlo with its scratch at `scr` (kSwapScratchBytes of device
+// memory): one rounds of a batch each (dE of every attempt, then the
+// settlement in order), enqueued in runs of as many rounds as the attempts
+// left need at least, the counters read back after each run.
+static int swap_run(const hdmd_system* sys, const double* pos, double* diam, void* ws,
+                    size_t ws_bytes, int64_t n_att, const int32_t* pairs, const double* u,
+                    double temperature, int32_t* accepted, int64_t* n_accepted, void* stream,
+                    void* scr) {
   Plan p;
   int rc = make_plan(sys, p);
   if (rc) return rc;
@@ -748,14 +876,15 @@ int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws,
   if (!(temperature > 0) || !std::isfinite(temperature))
     return fail(HDMD_ERR_ARG, "temperature must be > 0");
   hipStream_t st = S(stream);
-  // every attempt names two atoms of the system (checked before any launch)
-  std::vector<int32_t> hp((size_t)n_att * 2);
-  if (n_att > 0) {
-    HIPCHK(hipMemcpyAsync(hp.data(), pairs, hp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int32_t v : hp)
-      if (v < 0 || v >= p.n) return fail(HDMD_ERR_ARG, "swap pair names an atom outside [0, n)");
-  }
+  SwapScratch w = swap_scratch(scr);
+  long long hc[4] = {0, 0, 0, 0};
+  // every attempt names two atoms of the system (checked before any change)
+  launch_fill_i32(reinterpret_cast<int32_t*>(w.ctl), 8, 0, st);
+  launch_swap_init(n_att, pairs, p.n, w.ctl, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hc, w.ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hc[3]) return fail(HDMD_ERR_ARG, "swap pair names an atom outside [0, n)");
   rc = init_system(sys, p, pos, diam, nullptr, ws, ws_bytes, st, nullptr);
   if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
@@ -768,60 +897,44 @@ int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws,
   if (n_att == 0) return HDMD_OK;
   int32_t* slot_of = at<int32_t>(ws, p.off_src);  // free outside a rebuild
   launch_slot_of(dev, p.n, slot_of, st);
-  // the attempts still to run (two buffers, in turn), a batch's dE and the
-  // settlement counters
-  int32_t* todo[2] = {nullptr, nullptr};
-  double* de = nullptr;
-  unsigned long long* conf = nullptr;
-  long long* ctl = nullptr;
-  auto release = [&]() {
-    hipFree(todo[0]);
-    hipFree(todo[1]);
-    hipFree(de);
-    hipFree(conf);
-    hipFree(ctl);
-  };
-  if (hipMalloc(&todo[0], (size_t)n_att * 4) != hipSuccess ||
-      hipMalloc(&todo[1], (size_t)n_att * 4) != hipSuccess ||
-      hipMalloc(&de, 3 * kSwapBatch * sizeof(double)) != hipSuccess ||
-      hipMalloc(&conf, (size_t)kSwapBatch * (kSwapBatch / 64) * 8) != hipSuccess ||
-      hipMalloc(&ctl, 2 * sizeof(long long)) != hipSuccess) {
-    release();
-    return fail(HDMD_ERR_HIP, "hdmd_swap: device allocation failed");
-  }
-  std::vector<int32_t> order((size_t)n_att);
-  for (int64_t k = 0; k < n_att; k++) order[(size_t)k] = (int32_t)k;
-  long long hc[2] = {n_att, 0};
-  int rc2 = HDMD_OK;
-  if (hipMemcpyAsync(todo[0], order.data(), order.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(ctl, hc, sizeof(hc), hipMemcpyHostToDevice, st) != hipSuccess)
-    rc2 = fail(HDMD_ERR_HIP, "hdmd_swap: copy failed");
   const DKernels* K = dkernels(p.d);
-  int64_t n_todo = n_att, rounds = 0;
+  int64_t left = n_att, rounds = 0;
   int cur = 0;
-  while (rc2 == HDMD_OK && n_todo > 0) {
-    // the first attempt of a batch is always settled, so every round makes progress
-    if (++rounds > n_att) {
-      rc2 = fail(HDMD_ERR_STATE, "hdmd_swap: no progress");
-      break;
+  while (left > 0) {
+    // the first attempt of a batch always settles, so every round makes progress
+    const int64_t run = std::max<int64_t>(1, (left + kSwapBatch - 1) / kSwapBatch);
+    if (rounds + run > n_att + 1) return fail(HDMD_ERR_STATE, "hdmd_swap: no progress");
+    for (int64_t r = 0; r < run; r++) {
+      K->swap_de(dev, st, w.ctl, w.off[cur], n_att, pairs, slot_of, w.de, w.conf);
+      K->swap_settle(dev, st, w.ctl, w.off[cur], w.off[cur ^ 1], n_att, pairs, u, temperature,
+                     slot_of, w.de, w.conf, accepted, diam);
+      cur ^= 1;
     }
-    const int nb = (int)std::min<int64_t>(kSwapBatch, n_todo);
-    K->swap_de(dev, st, todo[cur], nb, pairs, slot_of, de, conf);
-    K->swap_settle(dev, st, todo[cur], (int)n_todo, nb, todo[cur ^ 1], pairs, u, temperature,
-                   slot_of, de, conf, accepted, diam, ctl);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-      rc2 = fail(HDMD_ERR_HIP, "hdmd_swap: launch failed");
-      break;
-    }
-    n_todo = hc[0];
-    cur ^= 1;
+    rounds += run;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hc, w.ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    left = hc[0] + (n_att - hc[2]);
   }
-  release();
-  if (rc2 != HDMD_OK) return rc2;
   *n_accepted = hc[1];
   return HDMD_OK;
+}
+
+}  // namespace hdmd
+
+extern "C" {
+
+int hdmd_swap(const hdmd_system* sys, const double* pos, double* diam, void* ws, size_t ws_bytes,
+              int64_t n_att, const int32_t* pairs, const double* u, double temperature,
+              int32_t* accepted, int64_t* n_accepted, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (!ws) return fail(HDMD_ERR_ARG, "null workspace");
+  if (ws_bytes < p.bytes)
+    return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+  return swap_run(sys, pos, diam, ws, ws_bytes, n_att, pairs, u, temperature, accepted, n_accepted,
+                  stream, at<char>(ws, p.off_swap));
 }
 
 static void set_fire(SysDev& h, const hdmd_fire_params* fp) {

@@ -88,6 +88,9 @@ _SIGS = {
     "hdmd_forces": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp]),
     "hdmd_step": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, C.c_size_t, C.c_int64,
                             C.c_double, C.c_int64, _vp, C.POINTER(hdmd_step_stats), _vp]),
+    "hdmd_step_resume": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, C.c_size_t,
+                                   C.c_int64, C.c_double, C.c_int64, _vp,
+                                   C.POINTER(hdmd_step_stats), _vp]),
     "hdmd_van_hove": (C.c_int, [C.POINTER(hdmd_system), _vp, C.c_size_t, C.c_int32, C.c_double,
                                 _vp, _vp, _vp]),
     "hdmd_swap": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t, C.c_int64, _vp, _vp,
@@ -249,21 +252,24 @@ def hdmd_forces(sys: System, pos, diam, ws, stream=None) -> tuple[torch.Tensor, 
 
 
 def hdmd_step(sys: System, pos, vel, diam, ws, nsteps: int, dt: float, thermo_every: int = 0,
-              stream=None):
-    """Runs nsteps of NVE velocity Verlet in place on pos/vel.
+              stream=None, resume: bool = False):
+    """Runs nsteps of velocity Verlet in place on pos/vel.
     Returns (stats, thermo rows (k, THERMO_COLS) or None); the columns are
     step, KE, PE, KE+PE, W (virial sum over pairs of r_ij . F_ij), Z (mean
     neighbours inside the cutoff), <|dr|^2>, <|dr|^4>, alpha_2 and f_ov of the
-    unwrapped displacement dr since step 0 of this call."""
+    unwrapped displacement dr since step 0 of this call.  resume: continue
+    the run the last call left in ws (hdmd_step_resume; pos/vel/diam must be
+    the arrays that call returned)."""
     th = None
     if thermo_every > 0:
         th = torch.zeros((nsteps // thermo_every + 1, THERMO_COLS), dtype=torch.float64,
                          device=pos.device)
     st = hdmd_step_stats()
-    rc = lib().hdmd_step(C.byref(sys.c()), _ptr(_dev_f64(pos, "pos")), _ptr(_dev_f64(vel, "vel")),
-                         _ptr(_dev_f64(diam, "diam")), _ptr(ws), ws.numel(), nsteps, dt,
-                         thermo_every, _ptr(th), C.byref(st), _stream(stream))
-    _check(rc, "hdmd_step")
+    fn = lib().hdmd_step_resume if resume else lib().hdmd_step
+    rc = fn(C.byref(sys.c()), _ptr(_dev_f64(pos, "pos")), _ptr(_dev_f64(vel, "vel")),
+            _ptr(_dev_f64(diam, "diam")), _ptr(ws), ws.numel(), nsteps, dt,
+            thermo_every, _ptr(th), C.byref(st), _stream(stream))
+    _check(rc, "hdmd_step_resume" if resume else "hdmd_step")
     return st, th
 
 

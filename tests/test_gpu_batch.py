@@ -1,5 +1,7 @@
 """Batched uneven replicas: each result in the mix equals the same system run
-alone, bit for bit (FIRE and MD), including slots admitted mid-run."""
+alone, bit for bit (FIRE and MD), including slots admitted mid-run, and every
+slot's result is checked against the oracle: FIRE positions after 5 and 40
+iterations, converged states under the oracle's forces, MD trajectories."""
 import numpy as np
 import pytest
 import torch
@@ -30,6 +32,18 @@ def _fire_case(d, n, phi, seed, pot=H.HDMD_HARMONIC):
     return sysd, x, sig
 
 
+def _oracle_fmax(orc, sysd, x, sig):
+    """max_i |F_i| of the oracle's forces at x (the oracle's own list)."""
+    if sysd.potential == H.HDMD_MORSE:
+        orc.set_morse_a(sysd.morse_a)
+    try:
+        rp, cols = orc.nlist_cells(x, sig, sysd.box_l, sysd.cutoff, sysd.skin)
+        F, _, _ = orc.forces(x, sig, sysd.box_l, sysd.potential, sysd.cutoff, 1.0, rp, cols)
+    finally:
+        orc.set_morse_a(30.0)
+    return float(np.sqrt((F * F).sum(axis=1)).max())
+
+
 def _alone_fire(sysd, x, sig, params):
     """Runs alone (regrowing the row width if a row overflows) and returns the
     final positions, result and the width used, which the batch then reuses:
@@ -46,8 +60,56 @@ CASES = [(3, 700, 0.62, 1), (4, 450, 0.44, 2), (5, 900, 0.3, 3), (6, 1300, 0.2, 
          (9, 3100, 0.02, 8)]
 
 
+def _run_batch(systems, params, max_slots=8):
+    """All systems in one batch; returns {slot: (positions, result)}."""
+    B = H.Batch(max_slots=max_slots, max_atoms=30000, max_cells=200000)
+    keep = []
+    for k, (s, x, sig) in enumerate(systems):
+        ws = H.workspace(s)
+        X, SG = dev(x), dev(sig)
+        keep.append((X, SG, ws))
+        B.hdmd_batch_add_fire(k, s, X, SG, ws, params)
+    done = {}
+    for _ in range(10000):
+        B.hdmd_batch_run(25)
+        state, _ = B.hdmd_batch_poll()
+        for k in range(len(systems)):
+            if k not in done and state[k] == H.HDMD_SLOT_DONE:
+                pos, _, res = B.hdmd_batch_take(k)
+                done[k] = (pos.cpu().numpy(), res)
+        if len(done) == len(systems):
+            return done
+    raise AssertionError("batch did not finish")
+
+
+@pytest.mark.parametrize("iters", [5, 40])
+def test_fire_batch_matches_oracle_short_horizon(orc, iters):
+    """Every class of the batch (d = 3..6, the Morse system, d = 9) after 5 and
+    40 FIRE iterations in one batch: positions within 1e-9 of the oracle's
+    FIRE 2.0 (FP64)."""
+    params = H.hdmd_fire_defaults(0.05, 1e-12, iters)
+    systems = [_fire_case(*case) for case in CASES]
+    # the row capacity each system needs over these iterations, from a lone run
+    systems = [(_alone_fire(s, x, sig, params)[2], x, sig) for s, x, sig in systems]
+    done = _run_batch(systems, params)
+    for k, (s, x, sig) in enumerate(systems):
+        xb, rb = done[k]
+        assert rb.iterations == iters, k
+        if s.potential == H.HDMD_MORSE:
+            orc.set_morse_a(s.morse_a)
+        try:
+            xo, ro = orc.fire(x, sig, s.box_l, s.potential, s.cutoff, s.skin, 1.0,
+                              orc.fire_params(dt0=0.05, ftol=1e-12, maxiter=iters))
+        finally:
+            orc.set_morse_a(30.0)
+        assert ro.iters == iters
+        dx = xb - xo
+        dx -= s.box_l * np.round(dx / s.box_l)
+        assert np.abs(dx).max() < 1e-9, (k, np.abs(dx).max())
+
+
 @pytest.mark.parametrize("prec", [H.HDMD_FP64, H.HDMD_MIXED])
-def test_fire_mix_equals_alone(prec):
+def test_fire_mix_equals_alone(orc, prec):
     params = H.hdmd_fire_defaults(0.05, 1e-10 if prec == H.HDMD_FP64 else 1e-5, 3000)
     systems = []
     for case in CASES:
@@ -91,12 +153,20 @@ def test_fire_mix_equals_alone(prec):
         assert rb.status == ra.status
         assert np.array_equal(xb, xa), k
         assert rb.energy == ra.energy
+        # a converged slot is a minimum under the oracle's own forces (the
+        # precision form stores forces in FP32, so its bound has room for that)
+        if rb.status == 0:
+            s, x, sig = systems[k]
+            tol = params.f_tol if prec == H.HDMD_FP64 else 1.5 * params.f_tol
+            assert _oracle_fmax(orc, s, xb, sig) < tol, k
 
 
-def test_md_mix_equals_alone():
+def test_md_mix_equals_alone(orc):
     """Classes holding systems of both precision forms (d = 4) and of both
     potential classes (d = 3) take one step launch per kind; a slot with the
-    Berendsen thermostat (d = 5) runs as it does alone."""
+    Berendsen thermostat (d = 5) runs as it does alone.  Every slot's final
+    positions and velocities against the oracle's velocity Verlet: within
+    1e-9 / 1e-8 (FP64), 1e-4 (the precision form)."""
     W, M = H.HDMD_WCA, H.HDMD_MORSE
     cases = [(3, 8, 1.12, 1, H.HDMD_FP64, W, 0.0), (4, 5, 1.1, 2, H.HDMD_FP64, W, 0.0),
              (6, 4, 1.05, 3, H.HDMD_FP64, W, 0.0), (4, 5, 1.12, 4, H.HDMD_MIXED, W, 0.0),
@@ -117,6 +187,14 @@ def test_md_mix_equals_alone():
         H.hdmd_step(sysd, X, V, dev(sig), ws, nsteps, dt)
         alone.append((X.cpu().numpy(), V.cpu().numpy()))
         states.append((sysd, x, v, sig))
+        # the oracle's trajectory of the same slot
+        xo, vo, _, _ = orc.vv(x, v, sig, L, pot, sysd.cutoff, sysd.skin, 1.0, nsteps, dt,
+                              tau=tau, T0=0.4 if tau else 0.0)
+        dx = X.cpu().numpy() - xo
+        dx -= L * np.round(dx / L)
+        tx, tv = (1e-9, 1e-8) if prec == H.HDMD_FP64 else (1e-4, 1e-4)
+        assert np.abs(dx).max() < tx, (d, prec, pot, np.abs(dx).max())
+        assert np.abs(V.cpu().numpy() - vo).max() < tv, (d, prec, pot)
     B = H.Batch(max_slots=8, max_atoms=10000, max_cells=100000)
     for k, (s, x, v, sig) in enumerate(states):
         B.hdmd_batch_add_md(k, s, dev(x), dev(v), dev(sig), H.workspace(s), nsteps, dt)

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2112_12271_amd import hdmd as H
 from paper_2112_12271_amd import inputs
-from tests.gpu_util import csr_equal, gpu_list, partnered
+from tests.gpu_util import csr_equal, dev, gpu_list, partnered
 
 pytestmark = pytest.mark.gpu
 C6 = inputs.WCA_CUT
@@ -222,3 +222,30 @@ def test_sparse_system_with_one_crowded_subcell(orc, d, n, L, prec):
                     sigma_max=1.4, precision=prec, max_neighbors=128)
     got, _, _ = gpu_list(sysd, x, sig)
     assert csr_equal(got, ref)
+
+
+def test_c2_full_size_list_and_forces(orc):
+    """The d = 4 workload at its full size (N = 65536, phi = 0.4, n_cell = 10),
+    from its seeded uniform start: the whole list equals the oracle's subcell
+    path in both precision forms (lists are FP64-exact in both), and the FP64
+    forces over it (the workload's precision) agree with the oracle's within
+    1e-12 F_rms.  (The precision form's force errors are stated on relaxed and
+    lattice states: at the uniform start's near-coincident pairs an FP32
+    force store alone exceeds 1e-5 of F_rms.)"""
+    from tests.gpu_util import force_err
+    cfg = inputs.C2
+    sig = cfg.diameters()
+    L = cfg.box(sig)
+    x = cfg.positions(L)
+    ref = orc.nlist_cells(x, sig, L, C6, cfg.skin)
+    Fo, _, Eo = orc.forces(x, sig, L, 0, C6, 1.0, *ref)
+    for prec in (H.HDMD_FP64, H.HDMD_MIXED):
+        sysd = H.System(d=4, n=cfg.n, box_l=L, cutoff=C6, skin=cfg.skin,
+                        sigma_max=float(sig.max()), precision=prec, max_neighbors=64)
+        assert H.hdmd_cells_per_axis(sysd) == 10
+        got, sysf, ws = gpu_list(sysd, x, sig)
+        assert csr_equal(got, ref), prec
+        if prec == H.HDMD_FP64:
+            F, E = H.hdmd_forces(sysf, dev(x), dev(sig), ws)
+            assert force_err(F.cpu().numpy(), Fo) < 1e-12
+            assert abs(float(E) - Eo) <= 1e-12 * abs(Eo)

@@ -1,6 +1,8 @@
 """Serving on the GPU: a seeded stream of FIRE minimisations and short MD runs
 of mixed d and N, admitted by HBM budget while others run; every result equals
-the same request run alone (bit for bit)."""
+the same request run alone (bit for bit), every converged minimisation is a
+minimum under the oracle's forces, and every MD request ends where the
+oracle's velocity Verlet does."""
 import numpy as np
 import pytest
 import torch
@@ -44,9 +46,10 @@ def _alone(req, width, params, prec):
     return X.cpu().numpy(), st.steps_done, 0
 
 
-@pytest.mark.parametrize("prec", [H.HDMD_MIXED])
-def test_mix_equals_alone(prec):
-    params = H.hdmd_fire_defaults(0.05, 1e-5, 20000)
+@pytest.mark.parametrize("prec", [H.HDMD_MIXED, H.HDMD_FP64])
+def test_mix_equals_alone(orc, prec):
+    tol = 1e-5 if prec == H.HDMD_MIXED else 1e-10
+    params = H.hdmd_fire_defaults(0.05, tol, 20000)
     reqs = _stream(24)
     ex = S.GpuExecutor(max_slots=8, max_atoms=40000, max_cells=400000, precision=prec,
                        fire_params=params)
@@ -70,3 +73,16 @@ def test_mix_equals_alone(prec):
         assert r.status in (0, 1) and r.status == st, r.rid
         assert r.iterations == it, r.rid
         assert np.array_equal(r.x, xa), r.rid
+        x0 = np.asarray(req.x)
+        if req.kind == "fire" and r.status == 0:
+            rp, cols = orc.nlist_cells(r.x, req.sig, req.box_l, req.cutoff, req.skin)
+            F, _, _ = orc.forces(r.x, req.sig, req.box_l, req.potential, req.cutoff, 1.0, rp, cols)
+            # the precision form stores forces in FP32: room for that rounding
+            bound = tol if prec == H.HDMD_FP64 else 1.5 * tol
+            assert np.sqrt((F * F).sum(axis=1)).max() < bound, r.rid
+        elif req.kind == "md":
+            xo, vo, _, _ = orc.vv(x0, req.v, req.sig, req.box_l, req.potential, req.cutoff,
+                                  req.skin, 1.0, req.nsteps, req.dt)
+            dx = r.x - xo
+            dx -= req.box_l * np.round(dx / req.box_l)
+            assert np.abs(dx).max() < (1e-9 if prec == H.HDMD_FP64 else 1e-4), r.rid
