@@ -159,6 +159,23 @@ int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_
 int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
                 size_t ws_bytes, double* force, double* energy, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * hdmd_forces with no workspace argument.  The workspace lives in a scratch
+ * array the library holds on each device it runs on until the process ends,
+ * hdmd_forces_noalloc_bytes() bytes (16 MiB); a system whose
+ * hdmd_workspace_bytes() exceeds it is refused with HDMD_ERR_WORKSPACE
+ * before any device work.  The call allocates nothing and does not time
+ * list-build variants (it takes the one an earlier call tuned for this kind
+ * of system, else the default); results are those of hdmd_forces with the
+ * same arguments.  Every call on one device shares that device's array and
+ * leaves its contents behind (the next call rewrites what it reads): calls
+ * that overlap on one device (other streams, other threads) race.  Other
+ * arguments, outputs and errors as hdmd_forces.  Synchronises. */
+size_t hdmd_forces_noalloc_bytes(void);
+int hdmd_forces_noalloc(const hdmd_system* sys, const double* pos, const double* diam,
+                        double* force, double* energy, void* stream);
+
 #define HDMD_THERMO_COLS 10
 
 /* Velocity Verlet, the kick-drift-kick leapfrog of Sec. II.B: per step

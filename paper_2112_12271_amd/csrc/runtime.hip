@@ -646,6 +646,34 @@ static int forces_run(const hdmd_system* sys, const Plan& p, const double* pos, 
   return err_to_status(h.err, "hdmd_forces");
 }
 
+
+// Device memory of hdmd_forces_noalloc: a scratch array the library holds on
+// every device it runs on (until the process ends) in place of a caller's
+// workspace.  Host code never passes the array's name to a kernel or a copy
+// (on the host it is only a stand-in for the symbol): it uses the device
+// address hipGetSymbolAddress returns, taken once per device with that
+// device current.
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+static int scratch_ptr(void** out) {
+  int devid = -1;
+  HIPCHK(hipGetDevice(&devid));
+  if (devid < 0 || devid >= kMaxDevices) return fail(HDMD_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[devid]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(HDMD_ERR_HIP, "no device address for the scratch array");
+    g_scratch_ptr[devid] = ptr;
+  }
+  *out = g_scratch_ptr[devid];
+  return HDMD_OK;
+}
+
 }  // namespace hdmd
 
 extern "C" {
@@ -656,6 +684,26 @@ int hdmd_forces(const hdmd_system* sys, const double* pos, const double* diam, v
   int rc = make_plan(sys, p);
   if (rc) return rc;
   return forces_run(sys, p, pos, diam, ws, ws_bytes, force, energy, stream, true);
+}
+
+size_t hdmd_forces_noalloc_bytes(void) { return kNoAllocBytes; }
+
+int hdmd_forces_noalloc(const hdmd_system* sys, const double* pos, const double* diam,
+                        double* force, double* energy, void* stream) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  if (p.bytes > kNoAllocBytes)
+    return fail(HDMD_ERR_WORKSPACE, "hdmd_forces_noalloc: the system needs " +
+                                        std::to_string(p.bytes) + " bytes of workspace, more "
+                                        "than the library's scratch array of " +
+                                        std::to_string(kNoAllocBytes));
+  void* ws = nullptr;
+  rc = scratch_ptr(&ws);
+  if (rc) return rc;
+  // the build variant the autotuner chose for this key, or the default: no
+  // timing runs (they would create events)
+  return forces_run(sys, p, pos, diam, ws, kNoAllocBytes, force, energy, stream, false);
 }
 
 static int step_chunk_len() {

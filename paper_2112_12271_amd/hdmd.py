@@ -86,6 +86,8 @@ _SIGS = {
     "hdmd_nlist_export": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_int64,
                                     C.POINTER(C.c_int64), _vp]),
     "hdmd_forces": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp]),
+    "hdmd_forces_noalloc_bytes": (C.c_size_t, []),
+    "hdmd_forces_noalloc": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, _vp]),
     "hdmd_step": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, C.c_size_t, C.c_int64,
                             C.c_double, C.c_int64, _vp, C.POINTER(hdmd_step_stats), _vp]),
     "hdmd_step_resume": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, _vp, C.c_size_t,

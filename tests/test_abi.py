@@ -11,7 +11,7 @@ from paper_2112_12271_amd import hdmd as H
 
 def test_library_exports_every_header_symbol():
     names = H.header_symbols()
-    assert len(names) == 19
+    assert len(names) == 21
     raw = ctypes.CDLL(H.LIB_PATH)
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
