@@ -47,6 +47,7 @@ typedef enum {
 
 typedef enum { HDMD_WCA = 0, HDMD_HARMONIC = 1, HDMD_MORSE = 2 } hdmd_potential;
 typedef enum { HDMD_FP64 = 0, HDMD_MIXED = 1 } hdmd_precision;
+typedef enum { HDMD_SUBCELLS_AUTO = 0, HDMD_SUBCELLS_FULL = 1, HDMD_SUBCELLS_HALF = 2 } hdmd_subcells;
 
 /* One system (Sec. II.A-C).  Pair (i,j) interacts for r < r_c = cutoff*sigma_ij
  * with sigma_ij = (sigma_i + sigma_j)/2 (Lorentz-Berthelot, Sec. II.A) and is
@@ -86,6 +87,19 @@ typedef struct {
    * tau must be >= dt.  thermostat_tau = 0: NVE.  Unused by FIRE. */
   double thermostat_tau;
   double target_temp;
+  /* Subcell grid of the list build (Sec. II.C).  HDMD_SUBCELLS_FULL:
+   * n_cell = floor(L / r_l,max) per axis (eq. setnc) and the 3^d stencil.
+   * HDMD_SUBCELLS_HALF: the half-size subcells the paper describes as the
+   * common alternative, side >= r_l,max/2 (floor(2L / r_l,max) per axis,
+   * at least 5) and the 5^d stencil; HDMD_ERR_ARG when L < 5 r_l,max/2.
+   * HDMD_SUBCELLS_AUTO (0): the autotuner times both grids (where the half
+   * grid applies and has at most max(64, 4n) subcells) on the first list
+   * build of each key (d, n_cell <= 2, log2 of the atoms per subcell) in the
+   * process and keeps the faster for every later call with that key.  The
+   * lists are the same on either grid; the atom order, and so the rounding
+   * of the force sums, follows the grid. */
+  int32_t subcells;
+  int32_t pad;
 } hdmd_system;
 
 /* FIRE 2.0 controls (Sec. II.B cites FIRE 2.0 with the semi-implicit Euler
@@ -132,9 +146,21 @@ void hdmd_fire_defaults(hdmd_fire_params* p, double dt0, double f_tol, int64_t m
 /* Bytes of the per-system workspace (256-byte aligned device memory). */
 size_t hdmd_workspace_bytes(const hdmd_system* sys);
 
-/* Subcell count per axis chosen for sys (eq. setnc with a rounding guard),
- * or <= 0 with the status of the failed validation. */
+/* Subcells per axis of sys's grid of side >= r_l,max (eq. setnc with a
+ * rounding guard; the half-size grid's for HDMD_SUBCELLS_HALF), or <= 0 with
+ * the status of the failed validation.  hdmd_build_config reports the grid
+ * an autotuned system builds on. */
 int hdmd_cells_per_axis(const hdmd_system* sys);
+
+/* The list-build configuration calls on sys use now (Sec. II.C): *reach 1
+ * (subcells of side >= r_l,max, 3^d stencil) or 2 (half-size subcells, 5^d
+ * stencil), *cells_per_axis of that grid, and *variant 1, 2 or 4 (waves per
+ * subcell of the candidate-lane build) or 64, 128, 256 (lanes per workgroup
+ * of the home-lane build).  Returns 1 when the autotuner has decided for
+ * sys's key, 0 when not yet (the defaults are reported: what the next build
+ * would time), or a negative status.  Any pointer may be null. */
+int hdmd_build_config(const hdmd_system* sys, int32_t* reach, int32_t* cells_per_axis,
+                      int32_t* variant);
 
 /* Verlet-list build, Sec. II.C (Fig. 1): loads pos/diam into ws, bins atoms
  * into n_cell^d subcells (flat index sum_k C_k n^(d-1-k)), sorts them by

@@ -16,9 +16,11 @@ struct DKernels {
   void (*disp_restart)(SysDev* s, int grid, hipStream_t st);
   void (*bin)(const KArgs& a, int grid, hipStream_t st);
   void (*cellsort)(bool mix, const KArgs& a, int grid, hipStream_t st);
-  // blk: workgroup size of the home-atom-lane build (64/128/256), or 1 for the
-  // candidate-lane build (n_cell >= 3 only)
-  void (*build)(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st);
+  // reach: stencil radius in subcells (1: subcells of side >= r_l,max, 3^d
+  // stencil; 2: half-size subcells, 5^d stencil); blk: workgroup size of the
+  // home-atom-lane build (64/128/256), or 1, 2, 4 waves per subcell of the
+  // candidate-lane build.  Each launch serves the systems of its own reach.
+  void (*build)(int reach, bool wrap, int blk, const KArgs& a, int grid, hipStream_t st);
   // the force kernels serve the systems of one precision form (mix) and one
   // potential class (morse: the Morse form; otherwise WCA and harmonic)
   void (*force)(bool mix, int lpa, bool morse, const KArgs& a, int grid, int fire, hipStream_t st);
@@ -47,7 +49,7 @@ void launch_force_all(const KArgs& a, int grid, int fire, bool morse, hipStream_
 // list build and FIRE forces of the classes d <= kBuildAllMaxD; larger d keep
 // per-class launches
 constexpr int kBuildAllMaxD = 8;
-void launch_build_all(const KArgs& a, int grid, hipStream_t st);
+void launch_build_all(const KArgs& a, int grid, int reach, hipStream_t st);
 
 // dimension-independent kernels (common.hip)
 void launch_setdesc(SysDev* dst, const SysDev& val, hipStream_t st);

@@ -77,7 +77,8 @@ struct SysDev {
   int32_t d, potential, precision, n;
   int32_t npad, ncell, radix, ncells;
   int32_t nstencil, width, nchunks, ntiles;
-  int32_t mode, wrap, nwaves, pad0;
+  int32_t mode, wrap, nwaves;
+  int32_t reach;  // stencil radius in subcells: 1 (side >= r_l,max), 2 (half-size subcells)
   double L, hL, cutoff, skin, eps, sigma_max;
   double rlmax, lsc, inv_lsc, halfskin2;
   double fxscale, qinv;  // 2^32 / L; 250 / L_sc

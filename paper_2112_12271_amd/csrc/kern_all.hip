@@ -153,7 +153,10 @@ __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
 // those classes keep launches of their own): a subcell of an n_cell >= 3
 // system is one wave's work (four such per workgroup), a subcell of an
 // n_cell <= 2 system (crowded: it holds the atoms of 1/2^d of the box) is
-// split over the four waves of a workgroup.
+// split over the four waves of a workgroup.  One launch per stencil radius
+// present (RAD 1: subcells of side >= r_l,max; RAD 2: half-size subcells),
+// each passing over the subcells of the other radius.
+template <int RAD>
 __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
   __shared__ unsigned long long msk_all[4][8 * 128];
   __shared__ int cand_all[4][8 * 64];
@@ -188,12 +191,13 @@ __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
         const int2 e = tiles[idx];
         SysDev* s = uniform_ptr(a.tab->sys[uniform_int(e.x)]);
         const int hc = uniform_int(e.y);
-        if (!running(s) || !need_rebuild(s)) continue;
+        if (!running(s) || !need_rebuild(s) || uniform_int(s->reach) != RAD) continue;
         switch (s->d) {
-#define HDMD_CASE(DD)                                                          \
-  case DD:                                                                     \
-    if (wr) build_t_tile<DD, 4, true>(s, hc, wv, msk_all[wv], cand_all[wv]);   \
-    else build_t_tile<DD, 1, false>(s, hc, 0, msk_all[wv], cand_all[wv]);      \
+#define HDMD_CASE(DD)                                                             \
+  case DD:                                                                        \
+    if (RAD == 2) build_t_tile<DD, 1, false, 2>(s, hc, 0, msk_all[wv], cand_all[wv]); \
+    else if (wr) build_t_tile<DD, 4, true>(s, hc, wv, msk_all[wv], cand_all[wv]); \
+    else build_t_tile<DD, 1, false>(s, hc, 0, msk_all[wv], cand_all[wv]);         \
     break;
           HDMD_BUILD_D(HDMD_CASE)
 #undef HDMD_CASE
@@ -204,7 +208,10 @@ __global__ __launch_bounds__(256) void k_build_all(KArgs a) {
   }
 }
 
-void launch_build_all(const KArgs& a, int grid, hipStream_t st) { k_build_all<<<grid, 256, 0, st>>>(a); }
+void launch_build_all(const KArgs& a, int grid, int reach, hipStream_t st) {
+  if (reach == 2) k_build_all<2><<<grid, 256, 0, st>>>(a);
+  else k_build_all<1><<<grid, 256, 0, st>>>(a);
+}
 void launch_bin_all(const KArgs& a, int grid, hipStream_t st) { k_bin_all<<<grid, kTile, 0, st>>>(a); }
 void launch_force_all(const KArgs& a, int grid, int fire, bool morse, hipStream_t st) {
   if (morse) k_force_all<true><<<grid, kTile, 0, st>>>(a, fire);

@@ -34,8 +34,16 @@ void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
   if (mix) k_cellsort<D, float><<<grid, 256, 0, st>>>(a);
   else k_cellsort<D, double><<<grid, 256, 0, st>>>(a);
 }
-void l_build(bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
-  if (wrap) {
+void l_build(int reach, bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
+  if (reach == 2) {
+    // half-size subcells, 5^d stencil (never wrapped)
+    if (blk == 1) k_build_t<D, 1, false, 2><<<grid, 64, 0, st>>>(a);
+    else if (blk == 2) k_build_t<D, 2, false, 2><<<grid, 128, 0, st>>>(a);
+    else if (blk == 4) k_build_t<D, 4, false, 2><<<grid, 256, 0, st>>>(a);
+    else if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
+    else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
+    else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);
+  } else if (wrap) {
     if (blk == 1) k_build_t<D, 1, true><<<grid, 64, 0, st>>>(a);
     else if (blk == 2) k_build_t<D, 2, true><<<grid, 128, 0, st>>>(a);
     else if (blk == 4) k_build_t<D, 4, true><<<grid, 256, 0, st>>>(a);

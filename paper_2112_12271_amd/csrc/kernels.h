@@ -417,17 +417,20 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
 // min(|u|, L - |u|), against the largest list radius enlarged by 1e-4.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ inline void decode_linked(int q, int radix, int nc, const int (&ci)[D], int (&o)[D],
-                                     int (&cj)[D]) {
+__device__ inline void decode_linked(int q, int radix, int reach, int nc, const int (&ci)[D],
+                                     int (&o)[D], int (&cj)[D]) {
+  // radix 2 reach + 1: offsets -reach..+reach; fewer subcells per axis than
+  // that: each of the n_cell subcells once (the deduplicated stencil)
+  const bool dedup = radix < 2 * reach + 1;
 #pragma unroll
   for (int k = D - 1; k >= 0; k--) {
     int dig = q % radix;
     q /= radix;
-    int oo = (radix == 3) ? dig - 1 : dig;
+    int oo = dedup ? dig : dig - reach;
     int c2 = ci[k] + oo;
     c2 = c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
     cj[k] = c2;
-    o[k] = (radix == 3) ? oo : c2 - ci[k];
+    o[k] = dedup ? c2 - ci[k] : oo;
   }
 }
 
@@ -447,6 +450,7 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
     const int h0 = cell_start(s, hc), h1 = cell_start(s, hc + 1);
     if (h0 == h1) continue;
     const int nc = s->ncell, radix = s->radix, nst = s->nstencil, npad = s->npad;
+    const int reach = s->reach;
     const int W = s->width;
     const double* __restrict__ xb = s->x[s->xcur];
     int* __restrict__ nl = s->nl;
@@ -501,7 +505,7 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 
       for (int q = 0; q < nst; q++) {
         int o[D], cj[D];
-        decode_linked<D>(q, radix, nc, ci, o, cj);
+        decode_linked<D>(q, radix, reach, nc, ci, o, cj);
         int J = 0;
 #pragma unroll
         for (int k = 0; k < D; k++) J = J * nc + cj[k];
@@ -693,9 +697,13 @@ __device__ inline void wave_lds_sync() {
 // One home subcell of a system that rebuilds, split over G waves: gw (< G)
 // selects this wave's share of the home atoms; msk/cand are the wave's LDS
 // arrays.
-template <int D, int G, bool WR>
+template <int D, int G, bool WR, int RAD = 1>
 __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long long* msk, int* cand) {
+  static_assert(RAD == 1 || (RAD == 2 && !WR), "wrapped systems take the 3^d stencil");
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
+  // subcell slots of a row along the last axis: offsets -RAD..+RAD (wrapped:
+  // the subcell itself and, for n_cell = 2, the other one; the third slot empty)
+  constexpr int NRS = WR ? 3 : 2 * RAD + 1;
   constexpr int RW = HW < 4 ? 4 : 8;     // record words read per home atom
   constexpr int BW = RW - 1;             // word of B = |q|^2
   constexpr int CB = 4;                  // chunks of a row tested per home-record load
@@ -716,8 +724,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   if (h0 >= h1) return;
   const int nc = uniform_int(s->ncell), npad = uniform_int(s->npad);
   const int W = uniform_int(s->width), tq = uniform_int(s->tq), tcull = uniform_int(s->tcull);
-  // sparse subcells (n_cell >= 3): three of them hold 48 atoms or fewer on average
-  const bool sparse = !WR && 3 * uniform_int(s->n) <= 48 * uniform_int(s->ncells);
+  // sparse subcells (not wrapped): a row's NRS subcells hold 48 atoms or fewer on average
+  const bool sparse = !WR && NRS * uniform_int(s->n) <= 48 * uniform_int(s->ncells);
   const double* __restrict__ xb = uniform_ptr(s->x[s->xcur]);
   const int* __restrict__ qc16 = uniform_ptr(s->qc16);
   HDMD_GLOBAL int* __restrict__ nl = gbl(uniform_ptr(s->nl));
@@ -738,27 +746,34 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       st *= nc;
     }
   }
-  // rows of linked subcells: radix 3 (offsets -1, 0, +1) or, for n_cell <= 2,
-  // radix n_cell (offsets 0, +1: the deduplicated stencil)
-  const int R = WR ? nc : 3;
+  // rows of linked subcells: radix 2 RAD + 1 (offsets -RAD..+RAD; 3 for
+  // subcells of side >= r_l,max, 5 for half-size subcells) or, for n_cell <=
+  // 2, radix n_cell (offsets 0, +1: the deduplicated stencil)
+  const int R = WR ? nc : NRS;
   int nrow = 1;
 #pragma unroll
   for (int k = 0; k < D - 1; k++) nrow *= R;
-  const int lm = WR ? cl : (cl == 0 ? nc - 1 : cl - 1);
-  const int lp = cl == nc - 1 ? 0 : cl + 1;
-  // offsets of the last axis (-1, 0, +1 subcells) in their int16 half
+  // the subcells of a row along the last axis and their offsets in the int16
+  // half of the last axis (n_cell >= 2 RAD + 1 when not wrapped: all distinct)
   constexpr int lsh = 16 * ((D - 1) % 2);
-  const int lastm = (int)((unsigned)(-kQScale & 0xffff) << lsh);
-  const int lastpp = (int)((unsigned)(kQScale & 0xffff) << lsh);
+  auto lcell = [&](int r) -> int {
+    if (WR) return r == 0 ? cl : (cl == nc - 1 ? 0 : cl + 1);
+    const int c2 = cl + r - RAD;
+    return c2 < 0 ? c2 + nc : (c2 >= nc ? c2 - nc : c2);
+  };
+  auto lvalid = [&](int r) -> bool { return !WR || r == 0 || (r == 1 && R >= 2); };
+  auto lshift = [&](int r) -> int {
+    return WR ? 0 : (int)((unsigned)((kQScale * (r - RAD)) & 0xffff) << lsh);
+  };
   // base subcell index of a row of linked subcells (offset digits of `row`
-  // in base 3 over the first d-1 axes, last digit fastest)
+  // in base R over the first d-1 axes, last digit fastest)
   auto row_base = [&](int row, int (&Dp)[HW], int (&og)[D - 1]) -> int {
     int P = 0, r = row;
 #pragma unroll
     for (int k = 0; k < HW; k++) Dp[k] = 0;
 #pragma unroll
     for (int k = D - 2; k >= 0; k--) {
-      const int o = WR ? r % R : r % 3 - 1;
+      const int o = WR ? r % R : r % R - RAD;
       r /= R;
       og[k] = o;
       int c2 = ci[k] + o;
@@ -950,9 +965,17 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         if (WR) {
           g0 = o ? qh0[k] : 0;
           g1 = o ? qh1[k] : 0;
-        } else {
+        } else if (RAD == 1) {
           g0 = (kQScale / 2) - o * qh0[k] - 1;
           g1 = (kQScale / 2) - o * qh1[k] - 1;
+          g0 = (o == 0 || g0 < 0) ? 0 : g0;
+          g1 = (o == 0 || g1 < 0) ? 0 : g1;
+        } else {
+          // the near face of a subcell |o| away: (|o| - 1/2) sides from the centre
+          const int ao = o < 0 ? -o : o;
+          const int face = (kQScale / 2) * (2 * ao - 1);
+          g0 = face - (o > 0 ? qh0[k] : -qh0[k]) - 1;
+          g1 = face - (o > 0 ? qh1[k] : -qh1[k]) - 1;
           g0 = (o == 0 || g0 < 0) ? 0 : g0;
           g1 = (o == 0 || g1 < 0) ? 0 : g1;
         }
@@ -962,16 +985,23 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       keep0 = __ballot(v0 && S0 < tc0);
       keep1 = __ballot(v1 && S1 < tc1);
     };
-    // candidate tt of a row whose subcells (stencil order) hold n0, n1 and
-    // the rest of its T atoms from st0, st1, st2: its record (an in-range
-    // atom for an empty lane) shifted by the subcell offset as packed int16
-    // adds; returns the atom, or -1 for an empty lane
-    auto cand_words = [&](int tt, int T, int st0, int n0, int st1, int n1, int st2,
-                          const int (&Dp)[HW], int (&cwc)[HW], int& tAc) -> int {
+    // candidate tt of a row of T atoms whose subcell slot r (stencil order)
+    // holds the candidates from cum[r-1] on, atom tt + db[0] + ... + db[r]:
+    // its record (an in-range atom for an empty lane) shifted by the subcell
+    // offset as packed int16 adds; returns the atom, or -1 for an empty lane.
+    // (The atom is a sum of increments rather than a pick among run bases:
+    // the compiler turns such a pick into an indexed load from scratch.)
+    auto cand_words = [&](int tt, int T, const int (&db)[NRS], const int (&cum)[NRS],
+                          const int (&Dp)[HW], int (&cwc)[HW], int& tAc)
+        __attribute__((always_inline)) -> int {
       const bool valid = tt < T;
-      const bool s1 = tt >= n0, s2 = tt >= n0 + n1;
-      const int j = (s2 ? st2 - n0 - n1 : (s1 ? st1 - n0 : st0)) + tt;
-      const int lastv = s2 ? lastpp : (s1 ? 0 : lastm);
+      int j = tt + db[0], lastv = lshift(0);
+#pragma unroll
+      for (int r = 1; r < NRS; r++) {
+        const bool past = tt >= cum[r - 1];
+        j += past ? db[r] : 0;
+        lastv = past ? lshift(r) : lastv;
+      }
       const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(valid ? j : hb) * 8);
       if (WR) {
 #pragma unroll
@@ -1011,7 +1041,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     };
 
     // one row of linked subcells, walked chunk by chunk
-    auto do_row = [&](int row) {
+    auto do_row = [&](int row) __attribute__((always_inline)) {
       // A SIMD issues for its oldest waves first, so without this the waves
       // of a launch finish one by one and the last ones run alone, their
       // latencies exposed.  A wave's priority falls as it gets through its
@@ -1023,20 +1053,22 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       unsigned long long keep0, keep1;
       row_keep(og, keep0, keep1);
       if ((keep0 | keep1) == 0) return;
-      // the row's subcells in stencil order: (-1, 0, +1) or, wrapped, (0, +1)
-      // (all six scalar loads issued before the first is used)
-      const int c1 = WR ? lp : cl;
-      int f[6];
-      f[0] = flat[P + lm];
-      f[1] = flat[P + lm + 1];
-      f[2] = (WR && R < 2) ? 0 : flat[P + c1];
-      f[3] = (WR && R < 2) ? 0 : flat[P + c1 + 1];
-      f[4] = WR ? 0 : flat[P + lp];
-      f[5] = WR ? 0 : flat[P + lp + 1];
-      const int st0 = f[0], n0 = f[1] - f[0];
-      const int st1 = f[2], n1 = f[3] - f[2];
-      const int st2 = f[4], n2 = f[5] - f[4];
-      const int T = n0 + n1 + n2;
+      // the row's subcells in stencil order: (-RAD..+RAD) or, wrapped, (0, +1)
+      // (all scalar loads issued before the first is used)
+      int f[2 * NRS];
+#pragma unroll
+      for (int r = 0; r < NRS; r++) {
+        f[2 * r] = lvalid(r) ? flat[P + lcell(r)] : 0;
+        f[2 * r + 1] = lvalid(r) ? flat[P + lcell(r) + 1] : 0;
+      }
+      int db[NRS], cum[NRS], T = 0;
+#pragma unroll
+      for (int r = 0; r < NRS; r++) {
+        // run r starts at atom f[2r] and takes candidates T.. (T before it)
+        db[r] = r == 0 ? f[0] : (f[2 * r] - f[2 * r - 2]) - (cum[r - 1] - (r >= 2 ? cum[r - 2] : 0));
+        T += f[2 * r + 1] - f[2 * r];
+        cum[r] = T;
+      }
       for (int k0 = 0; k0 < T; k0 += CB * 64) {
         const int nch = min(CB, (T - k0 + 63) / 64);
         if (nb + CB > NB) exact_pass();
@@ -1044,8 +1076,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c >= nch) continue;
-          cand[(nb + c) * 64 + lane] =
-              cand_words(k0 + c * 64 + lane, T, st0, n0, st1, n1, st2, Dp, cw[c], tA[c]);
+          cand[(nb + c) * 64 + lane] = cand_words(k0 + c * 64 + lane, T, db, cum, Dp, cw[c], tA[c]);
         }
         test_chunks(keep0, keep1, nch, cw, tA);
       }
@@ -1075,19 +1106,23 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           k1m |= rv ? kp1 : 0ull;
         }
         if ((k0m | k1m) == 0) continue;
-        int fl[CB][6];
+        int fl[CB][2 * NRS];
 #pragma unroll
         for (int c = 0; c < CB; c++) {
-          fl[c][0] = flat[P[c] + lm];
-          fl[c][1] = flat[P[c] + lm + 1];
-          fl[c][2] = flat[P[c] + cl];
-          fl[c][3] = flat[P[c] + cl + 1];
-          fl[c][4] = flat[P[c] + lp];
-          fl[c][5] = flat[P[c] + lp + 1];
-        }
-        int tmx = 0;
 #pragma unroll
-        for (int c = 0; c < CB; c++) tmx = max(tmx, fl[c][1] - fl[c][0] + fl[c][3] - fl[c][2] + fl[c][5] - fl[c][4]);
+          for (int r = 0; r < NRS; r++) {
+            fl[c][2 * r] = flat[P[c] + lcell(r)];
+            fl[c][2 * r + 1] = flat[P[c] + lcell(r) + 1];
+          }
+        }
+        int tmx = 0, Tr[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          Tr[c] = 0;
+#pragma unroll
+          for (int r = 0; r < NRS; r++) Tr[c] += fl[c][2 * r + 1] - fl[c][2 * r];
+          tmx = max(tmx, Tr[c]);
+        }
         if (tmx > 64) {
 #pragma unroll 1
           for (int c = 0; c < CB && row + c < nrow; c++) do_row(row + c);
@@ -1097,11 +1132,17 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         int jj[CB], lv[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) {
-          const int n0 = fl[c][1] - fl[c][0], n1 = fl[c][3] - fl[c][2];
-          const int T = row + c < nrow ? n0 + n1 + fl[c][5] - fl[c][4] : 0;
-          const bool s1 = lane >= n0, s2 = lane >= n0 + n1;
-          const int j = (s2 ? fl[c][4] - n0 - n1 : (s1 ? fl[c][2] - n0 : fl[c][0])) + lane;
-          lv[c] = s2 ? lastpp : (s1 ? 0 : lastm);
+          const int T = row + c < nrow ? Tr[c] : 0;
+          int j = fl[c][0] + lane, acc = fl[c][1] - fl[c][0];
+          lv[c] = lshift(0);
+#pragma unroll
+          for (int r = 1; r < NRS; r++) {
+            if (lane >= acc) {
+              j = fl[c][2 * r] - acc + lane;
+              lv[c] = lshift(r);
+            }
+            acc += fl[c][2 * r + 1] - fl[c][2 * r];
+          }
           jj[c] = lane < T ? j : -1;
           const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(lane < T ? j : hb) * 8);
 #pragma unroll
@@ -1146,7 +1187,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   }
 }
 
-template <int D, int G, bool WR>
+template <int D, int G, bool WR, int RAD = 1>
 __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
   // per wave: survivor masks of up to 128 home atoms and the candidates of 8 chunks
   __shared__ unsigned long long msk_all[G][8 * 128];
@@ -1158,8 +1199,8 @@ __global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
     if (!fetch_cell_tile(a, t, s, hc)) break;
     s = uniform_ptr(s);
     hc = uniform_int(hc);
-    if (!running(s) || !need_rebuild(s)) continue;
-    build_t_tile<D, G, WR>(s, hc, wv, msk_all[wv], cand_all[wv]);
+    if (!running(s) || !need_rebuild(s) || uniform_int(s->reach) != RAD) continue;
+    build_t_tile<D, G, WR, RAD>(s, hc, wv, msk_all[wv], cand_all[wv]);
   }
 }
 
@@ -1255,8 +1296,12 @@ __device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[
   const bool morse = pot == kPotMorse;
   double* xb = s->x[s->xcur];
   const int* flat = s->cell_flat;
+  // the linked subcells: offsets -reach..+reach per axis, or every subcell
+  // once where an axis has fewer than 2 reach + 1
+  const int reach = s->reach, rx = nc < 2 * reach + 1 ? nc : 2 * reach + 1;
+  const bool dedup = nc < 2 * reach + 1;
   int nst = 1;
-  for (int k = 0; k < D; k++) nst *= nc <= 2 ? nc : 3;
+  for (int k = 0; k < D; k++) nst *= rx;
   const double si = sig_get(xb + (size_t)pi * DR + D), sj = sig_get(xb + (size_t)pj * DR + D);
   si_out = si;
   sj_out = sj;
@@ -1282,12 +1327,12 @@ __device__ inline double swap_de(const SysDev* s, int pi, int pj, double (*red)[
           int cell = 0, r = t, mult = 1;
           for (int a = D - 1; a >= 0; a--) {
             int ca;
-            if (nc <= 2) {
+            if (dedup) {
               ca = r % nc;
               r /= nc;
             } else {
-              ca = cd[a] + r % 3 - 1;
-              r /= 3;
+              ca = cd[a] + r % rx - reach;
+              r /= rx;
               ca = ca < 0 ? ca + nc : (ca >= nc ? ca - nc : ca);
             }
             cell += ca * mult;

@@ -68,6 +68,11 @@ struct Plan {
   int n = 0, npad = 0, ncell = 0, radix = 0, ncells = 0, nstencil = 0, nchunks = 0;
   int ntiles = 0, nwaves = 0, width = 0;
   bool wrap = false, mix = false, morse = false;
+  // reach: stencil radius in subcells (1: side >= r_l,max, 3^d stencil; 2:
+  // half-size subcells, 5^d stencil); key_wrap/key_occ: the autotuner's key,
+  // taken from the grid of side >= r_l,max; nh_auto: half-size subcells per
+  // axis the autotuner may take (0: none)
+  int reach = 1, key_wrap = 0, key_occ = 0, nh_auto = 0;
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
          off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_disp[2] = {0, 0}, off_ycell = 0, off_qc = 0, off_qc16 = 0,
@@ -92,14 +97,44 @@ static int64_t ipow(int64_t b, int e) {
 // than the list radius by more than rounding, and while the subcell count
 // would exceed 2^26 or four per atom (fewer, wider subcells list the same
 // pairs).
+static int64_t cell_cap(const hdmd_system& s) {
+  return std::min<int64_t>(int64_t(1) << 26, std::max<int64_t>(64, 4 * s.n));
+}
+
 static int choose_ncell(const hdmd_system& s, double rlmax) {
   double q = std::floor(s.box_l / rlmax);
   int nc = q < 1.0 ? 1 : (q > 4096.0 ? 4096 : (int)q);
   while (nc > 1 && s.box_l / (double)nc < rlmax * (1.0 + 1.0e-9)) nc--;
-  const int64_t cap = std::min<int64_t>(int64_t(1) << 26, std::max<int64_t>(64, 4 * s.n));
+  const int64_t cap = cell_cap(s);
   while (nc > 1 && ipow(nc, s.d) > cap) nc--;
   return nc;
 }
+
+// Half-size subcells (Sec. II.C: side at least r_l,max/2, each linked to the
+// 5^d - 1 around it): floor(2 L / r_l,max) per axis with the same rounding
+// guard, lowered while the count exceeds cap.  0 where fewer than 5 per axis
+// would remain: there the 5^d stencil would meet a subcell twice.
+static int half_ncell(const hdmd_system& s, double rlmax, int64_t cap) {
+  const double hr = 0.5 * rlmax;
+  const double q = std::floor(s.box_l / hr);
+  int nc = q < 1.0 ? 1 : (q > 4096.0 ? 4096 : (int)q);
+  while (nc > 1 && s.box_l / (double)nc < hr * (1.0 + 1.0e-9)) nc--;
+  while (nc > 5 && ipow(nc, s.d) > cap) nc--;
+  return (nc >= 5 && ipow(nc, s.d) <= cap) ? nc : 0;
+}
+
+static int occ_bucket(int64_t n, int64_t ncells) {
+  double occ = (double)n / (double)ncells;
+  int b = 0;
+  while (occ >= 2.0 && b < 20) {
+    occ *= 0.5;
+    b++;
+  }
+  return b;
+}
+
+// the autotuner's grid for a key: 0 (not tuned yet), 1 or 2 (reach)
+static int tuned_reach(int d, int wrap, int occ);
 
 static int make_plan(const hdmd_system* s, Plan& p) {
   if (!s) return fail(HDMD_ERR_ARG, "null system");
@@ -128,15 +163,50 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.n = (int)s->n;
   p.npad = (int)((s->n + kTile - 1) / kTile * kTile);  // whole 64-atom tiles
   p.rlmax = s->cutoff * s->sigma_max + s->skin;
-  p.ncell = choose_ncell(*s, p.rlmax);
-  p.radix = p.ncell < 3 ? p.ncell : 3;
+  // the grid: subcells of side >= r_l,max (3^d stencil) or half-size ones
+  // (5^d stencil), by request or, for HDMD_SUBCELLS_AUTO, as the autotuner
+  // chose for the key; the workspace holds the cell arrays of either grid
+  // the system may take, so its layout does not depend on the choice
+  const int ncf = choose_ncell(*s, p.rlmax);
+  const int64_t cells_full = ipow(ncf, p.d);
+  p.key_wrap = ncf <= 2;
+  p.key_occ = occ_bucket(p.n, cells_full);
+  int64_t cells_alloc = cells_full;
+  bool need_ycell = ncf <= 2, need_qc = ncf > 2;
+  p.reach = 1;
+  p.ncell = ncf;
+  if (s->subcells == HDMD_SUBCELLS_HALF) {
+    const int nh = half_ncell(*s, p.rlmax, int64_t(1) << 26);
+    if (!nh)
+      return fail(HDMD_ERR_ARG, "half-size subcells need box_l >= 5 r_l,max / 2 (five per axis) "
+                                "and at most 2^26 of them");
+    p.reach = 2;
+    p.ncell = nh;
+    cells_alloc = ipow(nh, p.d);
+    need_ycell = false;
+    need_qc = true;
+  } else if (s->subcells == HDMD_SUBCELLS_AUTO) {
+    p.nh_auto = half_ncell(*s, p.rlmax, cell_cap(*s));
+    if (p.nh_auto) {
+      cells_alloc = std::max<int64_t>(cells_alloc, ipow(p.nh_auto, p.d));
+      need_qc = true;
+      if (tuned_reach(p.d, p.key_wrap, p.key_occ) == 2) {
+        p.reach = 2;
+        p.ncell = p.nh_auto;
+      }
+    }
+  } else if (s->subcells != HDMD_SUBCELLS_FULL) {
+    return fail(HDMD_ERR_ARG, "subcells must be HDMD_SUBCELLS_AUTO, _FULL or _HALF");
+  }
+  p.radix = p.reach == 2 ? 5 : (p.ncell < 3 ? p.ncell : 3);
   p.ncells = (int)ipow(p.ncell, p.d);
   p.nstencil = (int)ipow(p.radix, p.d);
   p.nchunks = (p.ncells + kChunk - 1) / kChunk;
+  const int64_t chunks_alloc = (cells_alloc + kChunk - 1) / kChunk;
   p.ntiles = p.npad / kTile;
   p.nwaves = p.npad / kWave;
   p.width = s->max_neighbors;
-  p.wrap = p.ncell <= 2;
+  p.wrap = p.reach == 1 && p.ncell <= 2;
   p.mix = s->precision == HDMD_MIXED;
   p.morse = s->potential == HDMD_MORSE;
   const size_t np = (size_t)p.npad, vsz = p.mix ? 4 : 8;
@@ -154,16 +224,16 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.off_f = take(np * p.d * vsz);
   p.off_xref = take(np * p.d * 8);
   for (int b = 0; b < 2; b++) p.off_disp[b] = take(np * p.d * 8);
-  p.off_ycell = take(p.wrap ? np * p.dy * 4 : 0);
-  p.off_qc = take(p.wrap ? 0 : np * 16);
+  p.off_ycell = take(need_ycell ? np * p.dy * 4 : 0);
+  p.off_qc = take(need_qc ? np * 16 : 0);
   p.off_qc16 = take(np * 32);
   p.off_cell_of = take(np * 4);
   p.off_rank = take(np * 4);
-  p.off_cell_count = take((size_t)p.ncells * 4);
-  p.off_cell_flat = take((size_t)(p.ncells + 1) * 4);
-  p.off_cell_local = take((size_t)p.ncells * 4);
-  p.off_chunk_sum = take((size_t)p.nchunks * 4);
-  p.off_chunk_off = take((size_t)p.nchunks * 4);
+  p.off_cell_count = take((size_t)cells_alloc * 4);
+  p.off_cell_flat = take((size_t)(cells_alloc + 1) * 4);
+  p.off_cell_local = take((size_t)cells_alloc * 4);
+  p.off_chunk_sum = take((size_t)chunks_alloc * 4);
+  p.off_chunk_off = take((size_t)chunks_alloc * 4);
   p.off_key = take(np * 4);
   p.off_src = take(np * 4);
   p.off_nl = take((size_t)p.width * np * 4);
@@ -192,6 +262,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.n = p.n;
   h.npad = p.npad;
   h.ncell = p.ncell;
+  h.reach = p.reach;
   h.radix = p.radix;
   h.ncells = p.ncells;
   h.nstencil = p.nstencil;
@@ -278,22 +349,23 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
 // occupancy bucket), chosen by timing every variant on the first build that
 // meets the key.  All variants produce identical lists.
 // ---------------------------------------------------------------------------
+// Per key: the grid an autotuned system takes (reach 1 or 2; 0: not decided)
+// and the best build variant on each grid (0: not timed).
+struct Tuned {
+  int reach = 0, blk[3] = {0, 0, 0};
+};
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, int> g_tune;
+static std::map<std::tuple<int, int, int>, Tuned> g_tune;
 
 static bool tuning_enabled() {
   const char* e = std::getenv("HDMD_AUTOTUNE");
   return !(e && e[0] == '0');
 }
 
-static int occ_bucket(const Plan& p) {
-  double occ = (double)p.n / (double)p.ncells;
-  int b = 0;
-  while (occ >= 2.0 && b < 20) {
-    occ *= 0.5;
-    b++;
-  }
-  return b;
+static int tuned_reach(int d, int wrap, int occ) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find({d, wrap, occ});
+  return it == g_tune.end() ? 0 : it->second.reach;
 }
 
 static int default_blk(const Plan& p) {
@@ -309,20 +381,18 @@ static int lookup_blk(const Plan& p, bool* known) {
     return default_blk(p);
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tune.find({p.d, (int)p.wrap, occ_bucket(p)});
-  if (it == g_tune.end()) {
+  auto it = g_tune.find({p.d, p.key_wrap, p.key_occ});
+  // an autotuned system's key is known once its grid is decided
+  const bool need_grid = p.nh_auto > 0;
+  if (it == g_tune.end() || !it->second.blk[p.reach] || (need_grid && !it->second.reach)) {
     *known = false;
     return default_blk(p);
   }
   *known = true;
-  return it->second;
+  return it->second.blk[p.reach];
 }
 
-extern "C" int hdmd_tuned_blk(int d, int wrap, int bucket) {
-  std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tune.find({d, wrap, bucket});
-  return it == g_tune.end() ? 0 : it->second;
-}
+
 
 // Lanes per atom of the force kernels: fixed per (d, precision) so that a
 // system gives the same bits alone and in a batch (the LPA partial sums are
@@ -367,9 +437,13 @@ static void chain_sort(const Plan& p, SysDev* dev, hipStream_t st) {
   K->cellsort(p.mix, a, gc, st);
 }
 
+static void build_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
+  dkernels(p.d)->build(p.reach, p.wrap, blk, single_args(dev, p.d), p.ncells, st);
+}
+
 static void chain_single(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
   chain_sort(p, dev, st);
-  dkernels(p.d)->build(p.wrap, blk, single_args(dev, p.d), p.ncells, st);
+  build_single(p, dev, st, blk);
 }
 
 // HIP events of the profiling mode, created once (with the system fence
@@ -403,14 +477,9 @@ static int err_to_status(int32_t err, const char* where) {
   return HDMD_OK;
 }
 
-// Loads a system into ws and builds its list (the descriptor ends in
-// MODE_STATIC, running, with current buffers holding the sorted state).
-static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
-                       const double* diam, const double* vel, void* ws, size_t ws_bytes,
-                       hipStream_t st, int* blk_out, bool allow_tune = true) {
-  if (!pos || !diam || !ws) return fail(HDMD_ERR_ARG, "null device pointer");
-  if (ws_bytes < p.bytes)
-    return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+// Writes the descriptor of plan p and loads the caller's arrays into ws.
+static void load_system(const hdmd_system* sys, const Plan& p, const double* pos,
+                        const double* diam, const double* vel, void* ws, hipStream_t st) {
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   SysDev h = make_desc(sys, p, ws);
   launch_setdesc(dev, h, st);
@@ -418,49 +487,114 @@ static int init_system(const hdmd_system* sys, const Plan& p, const double* pos,
   // displacements start at zero (both buffers; the first build permutes them)
   launch_fill_i32(reinterpret_cast<int32_t*>(h.disp[0]), (int64_t)p.npad * p.d * 2, 0, st);
   launch_fill_i32(reinterpret_cast<int32_t*>(h.disp[1]), (int64_t)p.npad * p.d * 2, 0, st);
-  const DKernels* K = dkernels(p.d);
-  K->load(p.mix, dev, p.ntiles, st, pos, diam, vel);
-  bool known = false;
-  int blk = lookup_blk(p, &known);
-  if (std::getenv("HDMD_BUILD_BLK")) known = true;
-  if (!known && tuning_enabled() && allow_tune) {
-    // run the chain up to the build, then time each build variant
-    KArgs a = single_args(dev, p.d);
-    K->bin(a, p.ntiles, st);
-    launch_scan1(a, p.nchunks, st);
-    launch_scan2(a, 1, st);
-    launch_scatter(a, p.ntiles, st);
-    K->cellsort(p.mix, a, p.ncells, st);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_blk = blk;
-    for (int cand : {1, 2, 4, 64, 128, 256}) {
-      K->build(p.wrap, cand, a, p.ncells, st);  // warm-up
+  dkernels(p.d)->load(p.mix, dev, p.ntiles, st, pos, diam, vel);
+}
+
+// The autotuner, on the first build of a key: for each grid the system may
+// take (an autotuned system whose half-size grid applies: both; otherwise its
+// own), loads the system, times the binning and subcell sort, then each
+// list-build variant (every variant gives the same list), and records the
+// best variant of each grid timed and, for an autotuned system, the grid of
+// the lower sum.  Half-size subcells are timed with the candidate-lane
+// variants only: the home-lane build stages each of the 5^d linked subcells,
+// most of them nearly empty.
+static int tune_build(const hdmd_system* sys, const Plan& pf, const double* pos,
+                      const double* diam, const double* vel, void* ws, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto elapsed = [&](float* ms) -> int {
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return HDMD_OK;
+  };
+  Tuned t;
+  float total[3] = {0.f, 1e30f, 1e30f};
+  const int r0 = pf.nh_auto ? 1 : pf.reach, r1 = pf.nh_auto ? 2 : pf.reach;
+  for (int reach = r0; reach <= r1; reach++) {
+    Plan p = pf;
+    if (reach == 2) {
+      // the same layout with the half-size grid
+      p.reach = 2;
+      p.ncell = pf.nh_auto ? pf.nh_auto : pf.ncell;
+      p.radix = 5;
+      p.ncells = (int)ipow(p.ncell, p.d);
+      p.nstencil = (int)ipow(5, p.d);
+      p.nchunks = (p.ncells + kChunk - 1) / kChunk;
+      p.wrap = false;
+    } else {
+      p.reach = 1;
+      p.ncell = choose_ncell(*sys, pf.rlmax);
+      p.radix = p.ncell < 3 ? p.ncell : 3;
+      p.ncells = (int)ipow(p.ncell, p.d);
+      p.nstencil = (int)ipow(p.radix, p.d);
+      p.nchunks = (p.ncells + kChunk - 1) / kChunk;
+      p.wrap = p.ncell <= 2;
+    }
+    SysDev* dev = at<SysDev>(ws, p.off_desc);
+    float sort_ms = 0.f;
+    for (int rep = 0; rep < 2; rep++) {  // the second load and sort are timed
+      load_system(sys, p, pos, diam, vel, ws, st);
       HIPCHK(hipEventRecord(e0, st));
-      K->build(p.wrap, cand, a, p.ncells, st);
+      chain_sort(p, dev, st);
       HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
+      int rc = elapsed(&sort_ms);
+      if (rc) return rc;
+    }
+    float best = 1e30f;
+    for (int cand : {1, 2, 4, 64, 128, 256}) {
+      if (reach == 2 && cand > 4) break;
+      build_single(p, dev, st, cand);  // warm-up
+      HIPCHK(hipEventRecord(e0, st));
+      build_single(p, dev, st, cand);
+      HIPCHK(hipEventRecord(e1, st));
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      int rc = elapsed(&ms);
+      if (rc) return rc;
       if (ms < best) {
         best = ms;
-        best_blk = cand;
+        t.blk[reach] = cand;
       }
     }
-    HIPCHK(hipEventDestroy(e0));
-    HIPCHK(hipEventDestroy(e1));
-    blk = best_blk;
-    {
-      std::lock_guard<std::mutex> g(g_tune_mu);
-      g_tune[{p.d, (int)p.wrap, occ_bucket(p)}] = blk;
-    }
-    K->build(p.wrap, blk, a, p.ncells, st);
-  } else {
-    chain_single(p, dev, st, blk);
+    total[reach] = sort_ms + best;
   }
-  launch_finalize(single_args(dev, p.d), 1, st);
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  Tuned& e = g_tune[std::make_tuple(pf.d, pf.key_wrap, pf.key_occ)];
+  for (int r = r0; r <= r1; r++)
+    if (!e.blk[r]) e.blk[r] = t.blk[r];
+  // the grid of an autotuned system: decided once per key (one whose half
+  // grid does not apply takes the full grid)
+  if (!e.reach && (pf.nh_auto || pf.reach == 1) && sys->subcells == HDMD_SUBCELLS_AUTO)
+    e.reach = total[2] < total[1] ? 2 : 1;
+  return HDMD_OK;
+}
+
+// Loads a system into ws and builds its list (the descriptor ends in
+// MODE_STATIC, running, with current buffers holding the sorted state).  A
+// system whose key the autotuner has not met yet is tuned first, and p
+// becomes the plan of the grid it chose (the layout stays the same).
+static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
+                       const double* diam, const double* vel, void* ws, size_t ws_bytes,
+                       hipStream_t st, int* blk_out, bool allow_tune = true) {
+  if (!pos || !diam || !ws) return fail(HDMD_ERR_ARG, "null device pointer");
+  if (ws_bytes < p.bytes)
+    return fail(HDMD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+  bool known = false;
+  int blk = lookup_blk(p, &known);
+  if (!known && tuning_enabled() && allow_tune) {
+    int rc = tune_build(sys, p, pos, diam, vel, ws, st);
+    if (rc) return rc;
+    Plan q;
+    rc = make_plan(sys, q);
+    if (rc) return rc;
+    p = q;
+    blk = lookup_blk(p, &known);
+  }
+  load_system(sys, p, pos, diam, vel, ws, st);
+  chain_single(p, at<SysDev>(ws, p.off_desc), st, blk);
+  launch_finalize(single_args(at<SysDev>(ws, p.off_desc), p.d), 1, st);
   HIPCHK(hipGetLastError());
   if (blk_out) *blk_out = blk;
   return HDMD_OK;
@@ -517,7 +651,7 @@ static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p,
     HIPCHK(hipGetLastError());
     return HDMD_OK;
   }
-  GraphKey key{ws,      kind,  chunk, p.d,     (int)p.mix, (int)p.morse, (int)p.wrap,
+  GraphKey key{ws,      kind,  chunk, p.d,     (int)p.mix, (int)p.morse, (int)p.wrap + 2 * p.reach,
                blk,     p.ntiles, p.ncells, p.nchunks};
   hipGraphExec_t exec = nullptr;
   {
@@ -579,7 +713,21 @@ size_t hdmd_workspace_bytes(const hdmd_system* sys) {
 int hdmd_cells_per_axis(const hdmd_system* sys) {
   Plan p;
   int rc = make_plan(sys, p);
-  return rc == HDMD_OK ? p.ncell : rc;
+  if (rc) return rc;
+  return sys->subcells == HDMD_SUBCELLS_HALF ? p.ncell : choose_ncell(*sys, p.rlmax);
+}
+
+int hdmd_build_config(const hdmd_system* sys, int32_t* reach, int32_t* cells_per_axis,
+                      int32_t* variant) {
+  Plan p;
+  int rc = make_plan(sys, p);
+  if (rc) return rc;
+  bool known = false;
+  const int blk = lookup_blk(p, &known);
+  if (reach) *reach = p.reach;
+  if (cells_per_axis) *cells_per_axis = p.ncell;
+  if (variant) *variant = blk;
+  return known ? 1 : 0;
 }
 
 int hdmd_build_nlist(const hdmd_system* sys, const double* pos, const double* diam, void* ws,
@@ -627,7 +775,7 @@ int hdmd_nlist_export(const hdmd_system* sys, void* ws, int64_t* row_ptr, int32_
 
 namespace hdmd {
 
-static int forces_run(const hdmd_system* sys, const Plan& p, const double* pos, const double* diam,
+static int forces_run(const hdmd_system* sys, Plan& p, const double* pos, const double* diam,
                       void* ws, size_t ws_bytes, double* force, double* energy, void* stream,
                       bool allow_tune) {
   if (!force || !energy) return fail(HDMD_ERR_ARG, "null output pointer");
@@ -720,7 +868,7 @@ namespace hdmd {
 // this system (same plan and parameters, laid out in this workspace), as the
 // last hdmd_step / hdmd_step_resume on ws left it.
 static bool holds_run_of(const SysDev& h, const hdmd_system* sys, const Plan& p, void* ws) {
-  return h.d == p.d && h.n == p.n && h.npad == p.npad && h.ncell == p.ncell &&
+  return h.d == p.d && h.n == p.n && h.npad == p.npad && h.ncell == p.ncell && h.reach == p.reach &&
          h.width == p.width && h.precision == sys->precision && h.potential == sys->potential &&
          h.L == sys->box_l && h.cutoff == sys->cutoff && h.skin == sys->skin &&
          h.eps == sys->epsilon && h.sigma_max == sys->sigma_max &&
@@ -806,7 +954,7 @@ static int md_run(const hdmd_system* sys, double* pos, double* vel, const double
       HIPCHK(hipEventRecord(ev[4 * k + 1], st));
       chain_sort(p, dev, st);
       HIPCHK(hipEventRecord(ev[4 * k + 2], st));
-      K->build(p.wrap, blk, a, p.ncells, st);
+      build_single(p, dev, st, blk);
       HIPCHK(hipEventRecord(ev[4 * k + 3], st));
       launch_finalize(a, 1, st);
     }
@@ -1017,7 +1165,7 @@ static int check_fire_params(const hdmd_fire_params* fp) {
 }
 
 // load + build, switch to FIRE mode, first forces (velocities start at zero)
-static int fire_start(const hdmd_system* sys, const Plan& p, const double* pos, const double* diam,
+static int fire_start(const hdmd_system* sys, Plan& p, const double* pos, const double* diam,
                       void* ws, size_t ws_bytes, const hdmd_fire_params* fp, hipStream_t st,
                       int* blk) {
   int rc = check_fire_params(fp);
@@ -1109,7 +1257,8 @@ struct HostBatch {
   int n_chunk = 0, n_sys = 0, blk[kMaxD + 1] = {0};  // wrap-variant build tile per d
   int n_atom_all = 0, n_cell_all = 0, n_nowrap_all = 0;
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
-       has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false};
+       has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false},
+       has_half[kMaxD + 1] = {false};  // systems on half-size subcells
   // kernel kinds present per class, bit (mix | 2 morse): MD systems, FIRE systems
   int kinds_md[kMaxD + 1] = {0}, kinds_fire[kMaxD + 1] = {0};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
@@ -1168,7 +1317,7 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
   std::memset(B->n_nowrap, 0, sizeof(B->n_nowrap));
   B->has_fire = B->has_md = false;
   for (int d = 0; d <= kMaxD; d++) {
-    B->has_wrap[d] = B->has_nowrap[d] = B->mix[d] = false;
+    B->has_wrap[d] = B->has_nowrap[d] = B->mix[d] = B->has_half[d] = false;
     B->kinds_md[d] = B->kinds_fire[d] = 0;
   }
   int64_t atom_base = 0, cell_base = 0;
@@ -1183,6 +1332,7 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
       for (int k = 0; k < S.p.ntiles; k++) atom.push_back(make_int2(s, k));
       B->n_atom[d] += S.p.ntiles;
       if (S.p.mix) B->mix[d] = true;
+      if (S.p.reach == 2) B->has_half[d] = true;
       const int kind = 1 << ((S.p.mix ? 1 : 0) | (S.p.morse ? 2 : 0));
       if (S.mode == MODE_MD) B->kinds_md[d] |= kind;
       else B->kinds_fire[d] |= kind;
@@ -1307,17 +1457,21 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   launch_scan2(a0, gsys, st);
   launch_scatter(a0, ga_all, st);
   launch_cellsort_all(a0, gc_all, st);
+  // list builds: one launch per stencil radius present (a launch serves the
+  // systems of its own radius and passes over the others' subcells)
+  auto class_builds = [&](int d) {
+    if (B->has_nowrap[d]) dkernels(d)->build(1, false, 1, batch_args(B, d, 1), gc(d), st);
+    if (B->has_half[d]) dkernels(d)->build(2, false, 1, batch_args(B, d, 1), gc(d), st);
+    if (B->has_wrap[d]) dkernels(d)->build(1, true, B->blk[d], batch_args(B, d, 2), gc(d), st);
+  };
   if (gb_all > 0) {
-    launch_build_all(a0, gb_all, st);
-    for (int d = kBuildAllMaxD + 1; d <= kMaxD; d++) {
-      if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
-      if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
-    }
+    bool half = false;
+    for (int d = kMinD; d <= kBuildAllMaxD; d++) half |= B->has_half[d];
+    launch_build_all(a0, gb_all, 1, st);
+    if (half) launch_build_all(a0, gb_all, 2, st);
+    for (int d = kBuildAllMaxD + 1; d <= kMaxD; d++) class_builds(d);
   } else {
-    for (int d = kMinD; d <= kMaxD; d++) {
-      if (B->has_nowrap[d]) dkernels(d)->build(false, 1, batch_args(B, d, 1), gc(d), st);
-      if (B->has_wrap[d]) dkernels(d)->build(true, B->blk[d], batch_args(B, d, 2), gc(d), st);
-    }
+    for (int d = kMinD; d <= kMaxD; d++) class_builds(d);
   }
   launch_finalize(a0, gsys, st);
   if (B->has_fire) {
@@ -1467,7 +1621,8 @@ int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
     grids.push_back(B->n_atom[d] ? pow2_grid(B->n_atom[d], 4096) : 0);
     grids.push_back(B->n_cell[d] ? pow2_grid(B->n_cell[d], 8192) : 0);
     grids.push_back(B->blk[d] * 4 + (B->has_wrap[d] ? 2 : 0) + (B->has_nowrap[d] ? 1 : 0) +
-                    (B->mix[d] ? 1024 : 0) + (B->kinds_md[d] << 16) + (B->kinds_fire[d] << 20));
+                    (B->mix[d] ? 1024 : 0) + (B->has_half[d] ? 2048 : 0) +
+                    (B->kinds_md[d] << 16) + (B->kinds_fire[d] << 20));
   }
   grids.push_back(B->has_fire ? 1 : 0);
   grids.push_back(B->has_md ? 1 : 0);

@@ -33,6 +33,9 @@ HDMD_MORSE = 2
 MORSE_A = 30.0  # the paper's Morse stiffness (Sec. II.A)
 HDMD_FP64 = 0
 HDMD_MIXED = 1
+HDMD_SUBCELLS_AUTO = 0
+HDMD_SUBCELLS_FULL = 1
+HDMD_SUBCELLS_HALF = 2
 HDMD_SLOT_EMPTY = 0
 HDMD_SLOT_RUNNING = 1
 HDMD_SLOT_DONE = 2
@@ -51,7 +54,8 @@ class hdmd_system(C.Structure):
                 ("max_neighbors", C.c_int32), ("n", C.c_int64), ("box_l", C.c_double),
                 ("cutoff", C.c_double), ("skin", C.c_double), ("epsilon", C.c_double),
                 ("sigma_max", C.c_double), ("morse_a", C.c_double),
-                ("thermostat_tau", C.c_double), ("target_temp", C.c_double)]
+                ("thermostat_tau", C.c_double), ("target_temp", C.c_double),
+                ("subcells", C.c_int32), ("pad", C.c_int32)]
 
 
 class hdmd_fire_params(C.Structure):
@@ -81,6 +85,8 @@ _SIGS = {
     "hdmd_fire_defaults": (None, [C.POINTER(hdmd_fire_params), C.c_double, C.c_double, C.c_int64]),
     "hdmd_workspace_bytes": (C.c_size_t, [C.POINTER(hdmd_system)]),
     "hdmd_cells_per_axis": (C.c_int, [C.POINTER(hdmd_system)]),
+    "hdmd_build_config": (C.c_int, [C.POINTER(hdmd_system), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "hdmd_build_nlist": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t,
                                    C.POINTER(C.c_int32), _vp]),
     "hdmd_nlist_export": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_int64,
@@ -175,11 +181,12 @@ class System:
     morse_a: float = MORSE_A
     thermostat_tau: float = 0.0   # Berendsen time constant of MD runs (0: NVE)
     target_temp: float = 0.0
+    subcells: int = HDMD_SUBCELLS_AUTO  # grid of the list build (autotuned, full or half-size)
 
     def c(self) -> hdmd_system:
         return hdmd_system(self.d, self.potential, self.precision, self.max_neighbors, self.n,
                            self.box_l, self.cutoff, self.skin, self.epsilon, self.sigma_max,
-                           self.morse_a, self.thermostat_tau, self.target_temp)
+                           self.morse_a, self.thermostat_tau, self.target_temp, self.subcells, 0)
 
 
 def hdmd_fire_defaults(dt0: float = 0.05, f_tol: float = 1e-10,
@@ -198,6 +205,15 @@ def hdmd_workspace_bytes(sys: System) -> int:
 
 def hdmd_cells_per_axis(sys: System) -> int:
     return int(lib().hdmd_cells_per_axis(C.byref(sys.c())))
+
+
+def hdmd_build_config(sys: System) -> tuple:
+    """(tuned, reach, cells per axis, build variant) that calls on sys use now."""
+    r, nc, v = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    rc = lib().hdmd_build_config(C.byref(sys.c()), C.byref(r), C.byref(nc), C.byref(v))
+    if rc < 0:
+        raise HdmdError(rc, "hdmd_build_config", last_error())
+    return bool(rc), int(r.value), int(nc.value), int(v.value)
 
 
 def workspace(sys: System, device="cuda") -> torch.Tensor:

@@ -2,6 +2,7 @@
 declares, and its host-only planning calls (no device work) behave as the
 header documents.  No compute call is made here."""
 import ctypes
+import dataclasses
 import math
 
 import pytest
@@ -11,7 +12,7 @@ from paper_2112_12271_amd import hdmd as H
 
 def test_library_exports_every_header_symbol():
     names = H.header_symbols()
-    assert len(names) == 21
+    assert len(names) == 22
     raw = ctypes.CDLL(H.LIB_PATH)
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
@@ -54,6 +55,42 @@ def test_cells_per_axis_follows_subcell_rule():
     assert H.hdmd_cells_per_axis(s) in (4, 5)
     s = _sys(d=3, box_l=5 * rl * (1 - 1e-6), n=4000)
     assert H.hdmd_cells_per_axis(s) == 4
+
+
+def test_half_size_subcells_follow_their_rule():
+    # half-size subcells (Sec. II.C): floor(2 L / r_l,max) per axis, at least 5
+    rl = H.WCA_CUT * 1.2 + 0.25
+    for d, L in [(2, 10.0), (3, 10.0), (4, 9.0), (6, 11.0)]:
+        s = _sys(d=d, box_l=L, n=4 * 4 ** d, subcells=H.HDMD_SUBCELLS_HALF)
+        assert H.hdmd_cells_per_axis(s) == math.floor(2 * L / rl)
+        tuned, reach, nc, var = H.hdmd_build_config(s)
+        assert (reach, nc) == (2, math.floor(2 * L / rl))
+    # fewer than five per axis: the 5^d stencil would alias -> refused
+    s = _sys(d=3, box_l=2.4 * rl, n=100, subcells=H.HDMD_SUBCELLS_HALF)
+    assert H.hdmd_cells_per_axis(s) == H.HDMD_ERR_ARG
+    assert "5 r_l,max / 2" in H.last_error()
+    s = _sys(d=3, box_l=2.5 * rl * (1 + 1e-9), n=100, subcells=H.HDMD_SUBCELLS_HALF)
+    assert H.hdmd_cells_per_axis(s) == 5
+    # an unknown grid value is an argument error
+    assert H.hdmd_cells_per_axis(_sys(subcells=3)) == H.HDMD_ERR_ARG
+
+
+def test_autotuned_grid_before_any_build():
+    # before its first build an autotuned system reports the defaults: subcells
+    # of side >= r_l,max and the one-wave candidate-lane build; its workspace
+    # holds the cell arrays of the half-size grid too, where that grid applies
+    rl = H.WCA_CUT * 1.2 + 0.25
+    s = _sys(d=3, box_l=30.0, n=20000)
+    tuned, reach, nc, var = H.hdmd_build_config(s)
+    assert (tuned, reach, nc) == (False, 1, math.floor(30.0 / rl))
+    assert var in (1, 2, 4, 64, 128, 256)
+    full = H.hdmd_workspace_bytes(dataclasses.replace(s, subcells=H.HDMD_SUBCELLS_FULL))
+    half = H.hdmd_workspace_bytes(dataclasses.replace(s, subcells=H.HDMD_SUBCELLS_HALF))
+    auto = H.hdmd_workspace_bytes(s)
+    nh = math.floor(2 * 30.0 / rl)
+    assert auto >= full and auto - full >= 12 * (nh ** 3 - math.floor(30.0 / rl) ** 3) - 6 * 256
+    assert half >= full - 16 * 20032  # no 16-bit wrapped copies on the half grid
+    assert H.hdmd_cells_per_axis(s) == math.floor(30.0 / rl)
 
 
 def test_cells_per_axis_rejects_tiny_box():
