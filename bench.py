@@ -244,30 +244,42 @@ def host_cpu():
     return info
 
 
-def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5, runs: int = 3):
+def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5, runs: int = 3,
+                 full_pairs: float = 3e9):
     """The oracle built with OpenMP (the paper's per-atom force loop and
-    per-subcell list loop on all host threads) on a bounded sample of the same
-    workload: `n` atoms at the same density and diameters, in a box of 3
+    per-subcell list loop on all host threads), timed on the workload itself
+    when its subcell path tests at most `full_pairs` candidate pairs per
+    build (N times the atoms of the 3^d linked subcells), else on a bounded
+    sample: `n` atoms at the same density and diameters, in a box of 3
     subcells per axis, so that the subcell path links every subcell and each
     atom meets n - 1 candidates.  Timed, median of `runs`: one list build by
     the oracle's subcell path, and `reps` force evaluations over that list.
-    The build time per atom is scaled to the candidates per atom of the full
-    box (3^d of its n_cell^d subcells: 46656 atoms for N = 262144 with
-    n_cell = 4) -- the build is one plain loop per candidate -- and per step
-    the oracle costs N * (force time per atom) + N * (build time per atom) /
-    steps_per_build, with the rebuild interval the GPU run measured."""
+    For the sample the build time per atom is scaled to the candidates per
+    atom of the full box (3^d of its n_cell^d subcells: 46656 atoms for
+    N = 262144 with n_cell = 4) -- the build is one plain loop per candidate.
+    Per step the oracle costs N * (force time per atom) + N * (build time per
+    atom) / steps_per_build, with the rebuild interval the GPU run measured."""
     from oracle import oracle as O
     from paper_2112_12271_amd import inputs
-    sig = (inputs.polydisperse(n, cfg.d, cfg.poly_R, 77) if cfg.poly_R > 0
-           else inputs.bidisperse(n, cfg.sig_a, cfg.sig_b, 77))
-    L = inputs.box_for_packing(cfg.d, sig, cfg.phi)
-    x = inputs.uniform_positions(n, cfg.d, L, 78)
-    rlmax = cfg.cutoff * float(sig.max()) + cfg.skin
+    sig_full = cfg.diameters()
+    L_full = cfg.box(sig_full)
+    rlmax = cfg.cutoff * float(sig_full.max()) + cfg.skin
+    nc_full = O.ncell(L_full, rlmax)
+    cand_full = cfg.n * (min(3, nc_full) / nc_full) ** cfg.d
+    whole = cfg.n * cand_full <= full_pairs
+    if whole:
+        n, sig, L = cfg.n, sig_full, L_full
+        x = cfg.positions(L)
+    else:
+        sig = (inputs.polydisperse(n, cfg.d, cfg.poly_R, 77) if cfg.poly_R > 0
+               else inputs.bidisperse(n, cfg.sig_a, cfg.sig_b, 77))
+        L = L_full * (n / cfg.n) ** (1.0 / cfg.d)  # the same number density
+        x = inputs.uniform_positions(n, cfg.d, L, 78)
+        if O.ncell(L, rlmax) != 3:
+            log("cpu baseline skipped: the %d-atom sample of %s has %d subcells per axis, not 3"
+                % (n, cfg.name, O.ncell(L, rlmax)))
+            return None
     O.lib_omp()
-    if O.ncell(L, rlmax) != 3:
-        log("cpu baseline skipped: the %d-atom sample of %s has %d subcells per axis, not 3"
-            % (n, cfg.name, O.ncell(L, rlmax)))
-        return None
     tb, tf = [], []
     for _ in range(runs):
         t0 = time.perf_counter()
@@ -280,19 +292,22 @@ def cpu_baseline(cfg, steps_per_build: float, n: int = 32768, reps: int = 5, run
     t_build, t_f = float(np.median(tb)), float(np.median(tf))
     log("cpu baseline: OpenMP oracle list build of %d atoms in %.2f s, force pass %.3f s"
         % (n, t_build, t_f))
-    nc_full = O.ncell(cfg.box(cfg.diameters()), rlmax)
-    cand_full = cfg.n * (3.0 / nc_full) ** cfg.d
-    build_per_atom = t_build / n * (cand_full / (n - 1))
+    build_per_atom = t_build / n * (1.0 if whole else cand_full / (n - 1))
     step_s = cfg.n * (t_f / n) + cfg.n * build_per_atom / steps_per_build
     host = host_cpu()
+    if whole:
+        what = ("the workload itself (%d atoms, d=%d, %d subcells per axis, uniform positions)"
+                % (n, cfg.d, nc_full))
+    else:
+        what = ("%d atoms (d=%d, same density, 3 subcells per axis; list build scaled from %d "
+                "candidates per atom to the %.0f of N=%d)" % (n, cfg.d, n - 1, cand_full, cfg.n))
     return dict(value=cfg.n / step_s, unit="atom-steps/s", cores=host["omp_threads"],
                 kind="oracle",
-                sample="oracle FP64 built with -fopenmp, %d threads, %d atoms (d=%d, phi=%.2f, "
-                       "3 subcells per axis): subcell-path list build %.2f s (%d candidates per "
-                       "atom, scaled to the %.0f of N=%d) and force pass %.3f s (mean row %.1f), "
-                       "medians of %d runs, combined at %.2f steps per build"
-                       % (host["omp_threads"], n, cfg.d, cfg.phi, t_build, n - 1, cand_full,
-                          cfg.n, t_f, len(cols) / n, runs, steps_per_build),
+                sample="oracle FP64 built with -fopenmp, %d threads, on %s: subcell-path list "
+                       "build %.3f s and force pass %.4f s (mean row %.1f), medians of %d runs, "
+                       "combined at %.2f steps per build"
+                       % (host["omp_threads"], what, t_build, t_f, len(cols) / n, runs,
+                          steps_per_build),
                 build_s_full=cfg.n * build_per_atom, force_s_full=cfg.n * t_f / n, host=host)
 
 

@@ -152,15 +152,20 @@ size_t hdmd_workspace_bytes(const hdmd_system* sys);
  * an autotuned system builds on. */
 int hdmd_cells_per_axis(const hdmd_system* sys);
 
-/* The list-build configuration calls on sys use now (Sec. II.C): *reach 1
- * (subcells of side >= r_l,max, 3^d stencil) or 2 (half-size subcells, 5^d
- * stencil), *cells_per_axis of that grid, and *variant 1, 2 or 4 (waves per
- * subcell of the candidate-lane build) or 64, 128, 256 (lanes per workgroup
- * of the home-lane build).  Returns 1 when the autotuner has decided for
- * sys's key, 0 when not yet (the defaults are reported: what the next build
- * would time), or a negative status.  Any pointer may be null. */
+/* The kernel configuration calls on sys use now.  List build (Sec. II.C):
+ * *reach 1 (subcells of side >= r_l,max, 3^d stencil) or 2 (half-size
+ * subcells, 5^d stencil), *cells_per_axis of that grid, and *variant 1, 2 or
+ * 4 (waves per subcell of the candidate-lane build) or 64, 128, 256 (lanes
+ * per workgroup of the home-lane build).  Forces (Sec. II.B getforce):
+ * *lanes_per_atom 1, 2 or 4 lanes sharing an atom's row; the autotuner times
+ * them on the first list built for a key and precision form, and every later
+ * system of that key and form, alone or in a batch, takes its choice (the
+ * lane count fixes the rounding of the force sums); Morse systems take one.
+ * Returns 1 when the autotuner has decided the list build for sys's key, 0
+ * when not yet (the defaults are reported: what the next build would time),
+ * or a negative status.  Any pointer may be null. */
 int hdmd_build_config(const hdmd_system* sys, int32_t* reach, int32_t* cells_per_axis,
-                      int32_t* variant);
+                      int32_t* variant, int32_t* lanes_per_atom);
 
 /* Verlet-list build, Sec. II.C (Fig. 1): loads pos/diam into ws, bins atoms
  * into n_cell^d subcells (flat index sum_k C_k n^(d-1-k)), sorts them by

@@ -79,6 +79,8 @@ struct SysDev {
   int32_t nstencil, width, nchunks, ntiles;
   int32_t mode, wrap, nwaves;
   int32_t reach;  // stencil radius in subcells: 1 (side >= r_l,max), 2 (half-size subcells)
+  int32_t lpa;    // lanes per atom of the force kernels (1, 2 or 4)
+  int32_t pad0;
   double L, hL, cutoff, skin, eps, sigma_max;
   double rlmax, lsc, inv_lsc, halfskin2;
   double fxscale, qinv;  // 2^32 / L; 250 / L_sc

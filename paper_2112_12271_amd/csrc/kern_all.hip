@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kTile) void k_force_all(KArgs a, int fire) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || (s->potential == kPotMorse) != MORSE) continue;
+    if (!running(s) || (s->potential == kPotMorse) != MORSE || s->lpa != 1) continue;
     if (fire && s->mode != MODE_FIRE) continue;
     const bool mix = s->precision != 0;
     switch (s->d) {

@@ -1851,9 +1851,10 @@ __device__ inline void tile_partials(double* dst, double (&vals)[kPart], double&
 // One atom tile's forces (stored in s->f) with the tile's energy and, for
 // FIRE, the power P = F.v, |F|^2, |v|^2 and max_i |F_i|^2 partial sums.
 // The force kernels serve the systems of one potential class: MORSE, or WCA
-// and harmonic (run-time switch); and of one precision form.
-__device__ inline bool kernel_serves(const SysDev* s, bool mix, bool morse) {
-  return (s->precision != 0) == mix && (s->potential == kPotMorse) == morse;
+// and harmonic (run-time switch); of one precision form; and of one number
+// of lanes per atom.
+__device__ inline bool kernel_serves(const SysDev* s, bool mix, bool morse, int lpa) {
+  return (s->precision != 0) == mix && (s->potential == kPotMorse) == morse && s->lpa == lpa;
 }
 
 template <int D, bool MIX, int LPA, bool MORSE>
@@ -1904,7 +1905,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_force(KArgs a, int fire) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || !kernel_serves(s, MIX, MORSE)) continue;
+    if (!running(s) || !kernel_serves(s, MIX, MORSE, LPA)) continue;
     if (fire && s->mode != MODE_FIRE) continue;
     force_tile<D, MIX, LPA, MORSE>(s, tile, fire, sh, stage);
   }
@@ -1932,7 +1933,7 @@ __global__ __launch_bounds__(kTile * LPA) void k_step(KArgs a) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || s->mode != MODE_MD || !kernel_serves(s, MIX, MORSE)) continue;
+    if (!running(s) || s->mode != MODE_MD || !kernel_serves(s, MIX, MORSE, LPA)) continue;
     const int i = tile * kTile + slot;
     const int n = s->n, npad = s->npad, pc = s->pcur, cur = s->xcur;
     const bool vi = i < n;

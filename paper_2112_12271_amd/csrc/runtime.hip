@@ -73,6 +73,7 @@ struct Plan {
   // taken from the grid of side >= r_l,max; nh_auto: half-size subcells per
   // axis the autotuner may take (0: none)
   int reach = 1, key_wrap = 0, key_occ = 0, nh_auto = 0;
+  int lpa = 1;  // lanes per atom of the force kernels
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
          off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_disp[2] = {0, 0}, off_ycell = 0, off_qc = 0, off_qc16 = 0,
@@ -135,6 +136,8 @@ static int occ_bucket(int64_t n, int64_t ncells) {
 
 // the autotuner's grid for a key: 0 (not tuned yet), 1 or 2 (reach)
 static int tuned_reach(int d, int wrap, int occ);
+// lanes per atom of the force kernels for a system (the autotuner's, or 1)
+static int lanes_for(const hdmd_system* s, int d, int wrap, int occ);
 
 static int make_plan(const hdmd_system* s, Plan& p) {
   if (!s) return fail(HDMD_ERR_ARG, "null system");
@@ -208,6 +211,7 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.width = s->max_neighbors;
   p.wrap = p.reach == 1 && p.ncell <= 2;
   p.mix = s->precision == HDMD_MIXED;
+  p.lpa = lanes_for(s, p.d, p.key_wrap, p.key_occ);
   p.morse = s->potential == HDMD_MORSE;
   const size_t np = (size_t)p.npad, vsz = p.mix ? 4 : 8;
   size_t o = 0;
@@ -263,6 +267,7 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
   h.npad = p.npad;
   h.ncell = p.ncell;
   h.reach = p.reach;
+  h.lpa = p.lpa;
   h.radix = p.radix;
   h.ncells = p.ncells;
   h.nstencil = p.nstencil;
@@ -349,10 +354,11 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
 // occupancy bucket), chosen by timing every variant on the first build that
 // meets the key.  All variants produce identical lists.
 // ---------------------------------------------------------------------------
-// Per key: the grid an autotuned system takes (reach 1 or 2; 0: not decided)
-// and the best build variant on each grid (0: not timed).
+// Per key: the grid an autotuned system takes (reach 1 or 2; 0: not decided),
+// the best build variant on each grid (0: not timed), and the lanes per atom
+// of the force kernels per precision form (0: not timed).
 struct Tuned {
-  int reach = 0, blk[3] = {0, 0, 0};
+  int reach = 0, blk[3] = {0, 0, 0}, lpa[2] = {0, 0};
 };
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Tuned> g_tune;
@@ -394,18 +400,29 @@ static int lookup_blk(const Plan& p, bool* known) {
 
 
 
-// Lanes per atom of the force kernels: fixed per (d, precision) so that a
-// system gives the same bits alone and in a batch (the LPA partial sums are
-// combined in a tree that depends on LPA).  HDMD_LPA overrides it.
-static int lpa_for(int d, bool mix) {
+// Lanes per atom of the force kernels (1, 2 or 4 lanes share an atom's row;
+// their partial sums meet in a tree that depends on the count, so the choice
+// fixes the rounding of the forces): chosen by the autotuner per key and
+// precision form, and kept for every later system of that key, alone or in a
+// batch.  Morse systems take one lane.  HDMD_LPA overrides the choice.
+static int lpa_env() {
   const char* e = std::getenv("HDMD_LPA");
-  if (e) {
-    int v = std::atoi(e);
-    return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
-  }
-  (void)mix;
-  return 1;
+  if (!e) return 0;
+  const int v = std::atoi(e);
+  return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
 }
+
+static int lanes_for(const hdmd_system* s, int d, int wrap, int occ) {
+  if (s->potential == HDMD_MORSE) return 1;
+  if (const int e = lpa_env()) return e;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find({d, wrap, occ});
+  const int mix = s->precision == HDMD_MIXED ? 1 : 0;
+  return (it == g_tune.end() || !it->second.lpa[mix]) ? 1 : it->second.lpa[mix];
+}
+
+static int lpa_index(int lpa) { return lpa >= 4 ? 2 : (lpa == 2 ? 1 : 0); }
+static int lpa_of_index(int k) { return 1 << k; }
 
 // ---------------------------------------------------------------------------
 // launch sequences
@@ -475,6 +492,11 @@ static int err_to_status(int32_t err, const char* where) {
   if (err & ERR_OVERFLOW) return fail(HDMD_ERR_NLIST_OVERFLOW, std::string(where) + ": Verlet row longer than max_neighbors");
   if (err & ERR_RUN_NAN) return fail(HDMD_ERR_NONFINITE, std::string(where) + ": non-finite energy during the run");
   return HDMD_OK;
+}
+
+// one int32 field of a device descriptor
+static void set_i32(SysDev* dev, size_t off, int32_t v, hipStream_t st) {
+  launch_fill_i32(reinterpret_cast<int32_t*>(reinterpret_cast<char*>(dev) + off), 1, v, st);
 }
 
 // Writes the descriptor of plan p and loads the caller's arrays into ws.
@@ -593,9 +615,52 @@ static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
     blk = lookup_blk(p, &known);
   }
   load_system(sys, p, pos, diam, vel, ws, st);
-  chain_single(p, at<SysDev>(ws, p.off_desc), st, blk);
-  launch_finalize(single_args(at<SysDev>(ws, p.off_desc), p.d), 1, st);
+  SysDev* dev = at<SysDev>(ws, p.off_desc);
+  chain_single(p, dev, st, blk);
+  launch_finalize(single_args(dev, p.d), 1, st);
   HIPCHK(hipGetLastError());
+  if (!p.morse && !lpa_env() && tuning_enabled() && allow_tune) {
+    const int mix = p.mix ? 1 : 0;
+    bool timed = false;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find({p.d, p.key_wrap, p.key_occ});
+      timed = it != g_tune.end() && it->second.lpa[mix];
+    }
+    if (!timed) {
+      // the force kernel with 1, 2 and 4 lanes per atom on the list just built
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      const DKernels* K = dkernels(p.d);
+      KArgs a = single_args(dev, p.d);
+      float best = 1e30f;
+      int best_lpa = 1;
+      for (int cand : {1, 2, 4}) {
+        set_i32(dev, offsetof(SysDev, lpa), cand, st);
+        K->force(p.mix, cand, p.morse, a, p.ntiles, 0, st);  // warm-up
+        HIPCHK(hipEventRecord(e0, st));
+        K->force(p.mix, cand, p.morse, a, p.ntiles, 0, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          best_lpa = cand;
+        }
+      }
+      HIPCHK(hipEventDestroy(e0));
+      HIPCHK(hipEventDestroy(e1));
+      {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        Tuned& e = g_tune[std::make_tuple(p.d, p.key_wrap, p.key_occ)];
+        if (!e.lpa[mix]) e.lpa[mix] = best_lpa;
+        p.lpa = e.lpa[mix];
+      }
+      set_i32(dev, offsetof(SysDev, lpa), p.lpa, st);
+    }
+  }
   if (blk_out) *blk_out = blk;
   return HDMD_OK;
 }
@@ -629,7 +694,7 @@ typedef void (*EnqueueFn)(const Plan& p, SysDev* dev, hipStream_t st, int blk);
 static void enqueue_md_step(const Plan& p, SysDev* dev, hipStream_t st, int blk) {
   const DKernels* K = dkernels(p.d);
   KArgs a = single_args(dev, p.d);
-  K->step(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, st);
+  K->step(p.mix, p.lpa, p.morse, a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
 }
@@ -641,7 +706,7 @@ static void enqueue_fire_iter(const Plan& p, SysDev* dev, hipStream_t st, int bl
   K->fire_update(p.mix, a, p.ntiles, st);
   chain_single(p, dev, st, blk);
   launch_finalize(a, 1, st);
-  K->force(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, 1, st);
+  K->force(p.mix, p.lpa, p.morse, a, p.ntiles, 1, st);
 }
 
 static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p, SysDev* dev,
@@ -651,7 +716,7 @@ static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p,
     HIPCHK(hipGetLastError());
     return HDMD_OK;
   }
-  GraphKey key{ws,      kind,  chunk, p.d,     (int)p.mix, (int)p.morse, (int)p.wrap + 2 * p.reach,
+  GraphKey key{ws,      kind,  chunk, p.d,     (int)p.mix + 2 * p.lpa, (int)p.morse, (int)p.wrap + 2 * p.reach,
                blk,     p.ntiles, p.ncells, p.nchunks};
   hipGraphExec_t exec = nullptr;
   {
@@ -673,9 +738,6 @@ static int run_chunk(void* ws, int kind, EnqueueFn fn, int chunk, const Plan& p,
   return HDMD_OK;
 }
 
-static void set_i32(SysDev* dev, size_t off, int32_t v, hipStream_t st) {
-  launch_fill_i32(reinterpret_cast<int32_t*>(reinterpret_cast<char*>(dev) + off), 1, v, st);
-}
 
 }  // namespace hdmd
 
@@ -718,7 +780,7 @@ int hdmd_cells_per_axis(const hdmd_system* sys) {
 }
 
 int hdmd_build_config(const hdmd_system* sys, int32_t* reach, int32_t* cells_per_axis,
-                      int32_t* variant) {
+                      int32_t* variant, int32_t* lanes_per_atom) {
   Plan p;
   int rc = make_plan(sys, p);
   if (rc) return rc;
@@ -727,6 +789,7 @@ int hdmd_build_config(const hdmd_system* sys, int32_t* reach, int32_t* cells_per
   if (reach) *reach = p.reach;
   if (cells_per_axis) *cells_per_axis = p.ncell;
   if (variant) *variant = blk;
+  if (lanes_per_atom) *lanes_per_atom = p.lpa;
   return known ? 1 : 0;
 }
 
@@ -784,7 +847,7 @@ static int forces_run(const hdmd_system* sys, Plan& p, const double* pos, const 
   if (rc) return rc;
   SysDev* dev = at<SysDev>(ws, p.off_desc);
   const DKernels* K = dkernels(p.d);
-  K->force(p.mix, lpa_for(p.d, p.mix), p.morse, single_args(dev, p.d), p.ntiles, 0, st);
+  K->force(p.mix, p.lpa, p.morse, single_args(dev, p.d), p.ntiles, 0, st);
   launch_reduce_pe(dev, energy, st);
   K->unload(p.mix, dev, p.ntiles, st, nullptr, nullptr, force);
   HIPCHK(hipGetLastError());
@@ -869,6 +932,7 @@ namespace hdmd {
 // last hdmd_step / hdmd_step_resume on ws left it.
 static bool holds_run_of(const SysDev& h, const hdmd_system* sys, const Plan& p, void* ws) {
   return h.d == p.d && h.n == p.n && h.npad == p.npad && h.ncell == p.ncell && h.reach == p.reach &&
+         h.lpa == p.lpa &&
          h.width == p.width && h.precision == sys->precision && h.potential == sys->potential &&
          h.L == sys->box_l && h.cutoff == sys->cutoff && h.skin == sys->skin &&
          h.eps == sys->epsilon && h.sigma_max == sys->sigma_max &&
@@ -950,7 +1014,7 @@ static int md_run(const hdmd_system* sys, double* pos, double* vel, const double
     if (rc) return rc;
     for (int64_t k = 0; k <= nsteps; k++) {
       HIPCHK(hipEventRecord(ev[4 * k], st));
-      K->step(p.mix, lpa_for(p.d, p.mix), p.morse, a, p.ntiles, st);
+      K->step(p.mix, p.lpa, p.morse, a, p.ntiles, st);
       HIPCHK(hipEventRecord(ev[4 * k + 1], st));
       chain_sort(p, dev, st);
       HIPCHK(hipEventRecord(ev[4 * k + 2], st));
@@ -1180,7 +1244,7 @@ static int fire_start(const hdmd_system* sys, Plan& p, const double* pos, const 
   if (rc) return rc;
   set_fire(h, fp);
   launch_setdesc(dev, h, st);
-  dkernels(p.d)->force(p.mix, lpa_for(p.d, p.mix), p.morse, single_args(dev, p.d), p.ntiles, 1, st);
+  dkernels(p.d)->force(p.mix, p.lpa, p.morse, single_args(dev, p.d), p.ntiles, 1, st);
   HIPCHK(hipGetLastError());
   return HDMD_OK;
 }
@@ -1259,7 +1323,8 @@ struct HostBatch {
   bool has_fire = false, has_md = false, has_wrap[kMaxD + 1] = {false},
        has_nowrap[kMaxD + 1] = {false}, mix[kMaxD + 1] = {false},
        has_half[kMaxD + 1] = {false};  // systems on half-size subcells
-  // kernel kinds present per class, bit (mix | 2 morse): MD systems, FIRE systems
+  // kernel kinds present per class, bit (mix | 2 morse | 4 lanes index): MD
+  // systems, FIRE systems (lanes index 0, 1, 2: 1, 2, 4 lanes per atom)
   int kinds_md[kMaxD + 1] = {0}, kinds_fire[kMaxD + 1] = {0};
   std::map<std::vector<int>, hipGraphExec_t> graphs;
 };
@@ -1333,7 +1398,7 @@ static int upload_tables(HostBatch* B, hipStream_t st) {
       B->n_atom[d] += S.p.ntiles;
       if (S.p.mix) B->mix[d] = true;
       if (S.p.reach == 2) B->has_half[d] = true;
-      const int kind = 1 << ((S.p.mix ? 1 : 0) | (S.p.morse ? 2 : 0));
+      const int kind = 1 << ((S.p.mix ? 1 : 0) | (S.p.morse ? 2 : 0) | (lpa_index(S.p.lpa) << 2));
       if (S.mode == MODE_MD) B->kinds_md[d] |= kind;
       else B->kinds_fire[d] |= kind;
       occ_tot += S.p.n;
@@ -1449,9 +1514,9 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   }
   if (B->has_md)
     for (int d = kMinD; d <= kMaxD; d++)
-      for (int k = 0; k < 4; k++)
+      for (int k = 0; k < 12; k++)
         if (B->kinds_md[d] >> k & 1)
-          dkernels(d)->step(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), st);
+          dkernels(d)->step(k & 1, lpa_of_index(k >> 2), k & 2, batch_args(B, d), ga(d), st);
   launch_bin_all(a0, ga_all, st);
   launch_scan1(a0, gchunk, st);
   launch_scan2(a0, gsys, st);
@@ -1475,22 +1540,17 @@ static void enqueue_batch_iter(HostBatch* B, const std::vector<int>& grids, hipS
   }
   launch_finalize(a0, gsys, st);
   if (B->has_fire) {
-    if (!std::getenv("HDMD_LPA")) {
-      // one lane per atom in every class; Morse systems in a launch of their own
-      int kinds = 0;
-      for (int d = kMinD; d <= kMaxD; d++) kinds |= B->kinds_fire[d];
-      if (kinds & 0x3) launch_force_all(a0, ga_all, 1, false, st);
-      if (kinds & 0xc) launch_force_all(a0, ga_all, 1, true, st);
-      for (int d = kBuildAllMaxD + 1; d <= kMaxD; d++)
-        for (int k = 0; k < 4; k++)
-          if (B->kinds_fire[d] >> k & 1)
-            dkernels(d)->force(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), 1, st);
-    } else {
-      for (int d = kMinD; d <= kMaxD; d++)
-        for (int k = 0; k < 4; k++)
-          if (B->kinds_fire[d] >> k & 1)
-            dkernels(d)->force(k & 1, lpa_for(d, k & 1), k & 2, batch_args(B, d), ga(d), 1, st);
-    }
+    // systems with one lane per atom in classes d <= kBuildAllMaxD: one launch
+    // over every class (Morse systems in a launch of their own); the others:
+    // a launch per class and kind
+    int kinds = 0;
+    for (int d = kMinD; d <= kBuildAllMaxD; d++) kinds |= B->kinds_fire[d];
+    if (kinds & 0x3) launch_force_all(a0, ga_all, 1, false, st);
+    if (kinds & 0xc) launch_force_all(a0, ga_all, 1, true, st);
+    for (int d = kMinD; d <= kMaxD; d++)
+      for (int k = d <= kBuildAllMaxD ? 4 : 0; k < 12; k++)
+        if (B->kinds_fire[d] >> k & 1)
+          dkernels(d)->force(k & 1, lpa_of_index(k >> 2), k & 2, batch_args(B, d), ga(d), 1, st);
   }
 }
 
@@ -1621,9 +1681,9 @@ int hdmd_batch_run(void* table_ws, int32_t iterations, void* stream) {
     grids.push_back(B->n_atom[d] ? pow2_grid(B->n_atom[d], 4096) : 0);
     grids.push_back(B->n_cell[d] ? pow2_grid(B->n_cell[d], 8192) : 0);
     grids.push_back(B->blk[d] * 4 + (B->has_wrap[d] ? 2 : 0) + (B->has_nowrap[d] ? 1 : 0) +
-                    (B->mix[d] ? 1024 : 0) + (B->has_half[d] ? 2048 : 0) +
-                    (B->kinds_md[d] << 16) + (B->kinds_fire[d] << 20));
+                    (B->mix[d] ? 1024 : 0) + (B->has_half[d] ? 2048 : 0));
   }
+  for (int d = kMinD; d <= kMaxD; d++) grids.push_back(B->kinds_md[d] | (B->kinds_fire[d] << 12));
   grids.push_back(B->has_fire ? 1 : 0);
   grids.push_back(B->has_md ? 1 : 0);
   grids.push_back(pow2_grid(B->n_atom_all, 4096));  // all-class launches

@@ -86,7 +86,8 @@ _SIGS = {
     "hdmd_workspace_bytes": (C.c_size_t, [C.POINTER(hdmd_system)]),
     "hdmd_cells_per_axis": (C.c_int, [C.POINTER(hdmd_system)]),
     "hdmd_build_config": (C.c_int, [C.POINTER(hdmd_system), C.POINTER(C.c_int32),
-                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
     "hdmd_build_nlist": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_size_t,
                                    C.POINTER(C.c_int32), _vp]),
     "hdmd_nlist_export": (C.c_int, [C.POINTER(hdmd_system), _vp, _vp, _vp, C.c_int64,
@@ -208,12 +209,14 @@ def hdmd_cells_per_axis(sys: System) -> int:
 
 
 def hdmd_build_config(sys: System) -> tuple:
-    """(tuned, reach, cells per axis, build variant) that calls on sys use now."""
-    r, nc, v = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-    rc = lib().hdmd_build_config(C.byref(sys.c()), C.byref(r), C.byref(nc), C.byref(v))
+    """(tuned, reach, cells per axis, build variant, lanes per atom) that calls
+    on sys use now."""
+    r, nc, v, la = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    rc = lib().hdmd_build_config(C.byref(sys.c()), C.byref(r), C.byref(nc), C.byref(v),
+                                 C.byref(la))
     if rc < 0:
         raise HdmdError(rc, "hdmd_build_config", last_error())
-    return bool(rc), int(r.value), int(nc.value), int(v.value)
+    return bool(rc), int(r.value), int(nc.value), int(v.value), int(la.value)
 
 
 def workspace(sys: System, device="cuda") -> torch.Tensor:

@@ -63,7 +63,7 @@ def test_half_size_subcells_follow_their_rule():
     for d, L in [(2, 10.0), (3, 10.0), (4, 9.0), (6, 11.0)]:
         s = _sys(d=d, box_l=L, n=4 * 4 ** d, subcells=H.HDMD_SUBCELLS_HALF)
         assert H.hdmd_cells_per_axis(s) == math.floor(2 * L / rl)
-        tuned, reach, nc, var = H.hdmd_build_config(s)
+        tuned, reach, nc, var, lanes = H.hdmd_build_config(s)
         assert (reach, nc) == (2, math.floor(2 * L / rl))
     # fewer than five per axis: the 5^d stencil would alias -> refused
     s = _sys(d=3, box_l=2.4 * rl, n=100, subcells=H.HDMD_SUBCELLS_HALF)
@@ -81,7 +81,7 @@ def test_autotuned_grid_before_any_build():
     # holds the cell arrays of the half-size grid too, where that grid applies
     rl = H.WCA_CUT * 1.2 + 0.25
     s = _sys(d=3, box_l=30.0, n=20000)
-    tuned, reach, nc, var = H.hdmd_build_config(s)
+    tuned, reach, nc, var, lanes = H.hdmd_build_config(s)
     assert (tuned, reach, nc) == (False, 1, math.floor(30.0 / rl))
     assert var in (1, 2, 4, 64, 128, 256)
     full = H.hdmd_workspace_bytes(dataclasses.replace(s, subcells=H.HDMD_SUBCELLS_FULL))

@@ -261,14 +261,14 @@ def test_autotuner_records_one_grid_per_key(orc):
                         max_neighbors=400, subcells=grid), x, sig
 
     s1, x1, sg1 = make(20000, 61)
-    tuned, reach0, nc0, _ = H.hdmd_build_config(s1)
+    tuned, reach0, nc0, _, _ = H.hdmd_build_config(s1)
     assert not tuned and reach0 == 1 and nc0 == 2
     H.hdmd_build_nlist(s1, dev(x1), dev(sg1), H.workspace(s1))
-    tuned, reach, nc, var = H.hdmd_build_config(s1)
+    tuned, reach, nc, var, lanes = H.hdmd_build_config(s1)
     assert tuned and reach in (1, 2)
     assert nc == (2 if reach == 1 else 5)
     s2, x2, sg2 = make(19600, 71)            # the same key: d, wrapped, occupancy bucket
-    assert H.hdmd_build_config(s2) == (True, reach, nc, var)
+    assert H.hdmd_build_config(s2) == (True, reach, nc, var, lanes)
     F2, E2 = H.hdmd_forces(s2, dev(x2), dev(sg2), H.workspace(s2))
     s3 = make(19600, 71, HALF if reach == 2 else FULL)[0]
     F3, E3 = H.hdmd_forces(s3, dev(x2), dev(sg2), H.workspace(s3))
