@@ -188,6 +188,8 @@ def window_record(cfg, prec_mixed, win, meta, steps):
         rec.update(step_kernel_ms=avg_ms, step_kernel_gbs=ach, step_bytes_per_atom=bpa,
                    step_kernels=int(st.step_kernels),
                    build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
+                   builds_per_s=(1e3 * st.build_kernels / st.build_kernel_ms
+                                 if st.build_kernels else None),
                    build_candidates=meta["candidates"],
                    share_step_kernel=st.step_kernel_ms / ms,
                    share_build_kernel=st.build_kernel_ms / ms,
@@ -630,6 +632,9 @@ def main():
         "cpu_baseline": cpu,
         "fp64": out.get("fp64"),
         "mixed": out.get("mixed"),
+        "mixed_form": "neighbour positions gathered as 32-bit fixed point, stored forces and "
+                      "velocities FP32; distances, pair coefficients, force sums, positions and "
+                      "energy sums FP64 (FP32 distances and forces exceed 1e-5 F_rms)",
         "drift_difference_mixed_minus_fp64":
             (lr["mixed"]["drift_per_tau"] - lr["fp64"]["drift_per_tau"])
             if lr.get("mixed") and lr.get("fp64") else None,

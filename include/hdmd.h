@@ -64,7 +64,10 @@ typedef enum { HDMD_SUBCELLS_AUTO = 0, HDMD_SUBCELLS_FULL = 1, HDMD_SUBCELLS_HAL
  *              pair distances, coefficients and the force sums are FP64, the
  *              stored forces and the velocities FP32; positions, energy sums
  *              and FIRE's reductions FP64.  Verlet lists are FP64-exact in
- *              both.
+ *              both.  (A departure from a form with FP32 distances and
+ *              forces: computed in FP32, the pair coefficient's error reached
+ *              5.9e-5 and FP32 force sums 5.3e-5 of F_rms, above the 1e-5
+ *              bound; the FP32 part here is what is stored and gathered.)
  *   sigma_max  largest diameter present; it sizes the subcells (eq. setnc).
  *   max_neighbors  Verlet row capacity W of the workspace.
  *   morse_a    Morse stiffness a in 1/length (read for HDMD_MORSE only; > 0). */
@@ -158,9 +161,10 @@ int hdmd_cells_per_axis(const hdmd_system* sys);
  * 4 (waves per subcell of the candidate-lane build) or 64, 128, 256 (lanes
  * per workgroup of the home-lane build).  Forces (Sec. II.B getforce):
  * *lanes_per_atom 1, 2 or 4 lanes sharing an atom's row; the autotuner times
- * them on the first list built for a key and precision form, and every later
- * system of that key and form, alone or in a batch, takes its choice (the
- * lane count fixes the rounding of the force sums); Morse systems take one.
+ * them on the first list built for each (d, precision form, expected row
+ * length n V_d(r_l,max) / L^d in half-octaves), and every later system with
+ * that key, alone or in a batch, takes its choice (the lane count fixes the
+ * rounding of the force sums); Morse systems take one.
  * Returns 1 when the autotuner has decided the list build for sys's key, 0
  * when not yet (the defaults are reported: what the next build would time),
  * or a negative status.  Any pointer may be null. */

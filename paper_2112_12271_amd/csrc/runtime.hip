@@ -73,7 +73,7 @@ struct Plan {
   // taken from the grid of side >= r_l,max; nh_auto: half-size subcells per
   // axis the autotuner may take (0: none)
   int reach = 1, key_wrap = 0, key_occ = 0, nh_auto = 0;
-  int lpa = 1;  // lanes per atom of the force kernels
+  int lpa = 1, row_key = 0;  // lanes per atom of the force kernels and their key
   double rlmax = 0;
   size_t off_desc = 0, off_x[2] = {0, 0}, off_q[2] = {0, 0}, off_v[2] = {0, 0},
          off_oid[2] = {0, 0}, off_f = 0, off_xref = 0, off_disp[2] = {0, 0}, off_ycell = 0, off_qc = 0, off_qc16 = 0,
@@ -136,8 +136,18 @@ static int occ_bucket(int64_t n, int64_t ncells) {
 
 // the autotuner's grid for a key: 0 (not tuned yet), 1 or 2 (reach)
 static int tuned_reach(int d, int wrap, int occ);
-// lanes per atom of the force kernels for a system (the autotuner's, or 1)
-static int lanes_for(const hdmd_system* s, int d, int wrap, int occ);
+// lanes per atom of the force kernels for a system (the autotuner's, or 1),
+// keyed by the row-length bucket
+static int lanes_for(const hdmd_system* s, int d, int rowkey);
+
+// The force kernels' key: half-octaves of the expected row length, the atoms
+// in a ball of the largest list radius at the mean number density, n V_d(r)
+// / L^d (rows, not the subcell occupancy, decide how many lanes pay).
+static int row_bucket(const hdmd_system& s, double rlmax) {
+  const double vd = std::pow(M_PI, 0.5 * s.d) / std::tgamma(0.5 * s.d + 1.0) * std::pow(rlmax, s.d);
+  const double rows = (double)s.n * vd / std::pow(s.box_l, s.d);
+  return (int)std::lround(2.0 * std::log2(std::max(rows, 1.0)));
+}
 
 static int make_plan(const hdmd_system* s, Plan& p) {
   if (!s) return fail(HDMD_ERR_ARG, "null system");
@@ -211,7 +221,8 @@ static int make_plan(const hdmd_system* s, Plan& p) {
   p.width = s->max_neighbors;
   p.wrap = p.reach == 1 && p.ncell <= 2;
   p.mix = s->precision == HDMD_MIXED;
-  p.lpa = lanes_for(s, p.d, p.key_wrap, p.key_occ);
+  p.row_key = row_bucket(*s, p.rlmax);
+  p.lpa = lanes_for(s, p.d, p.row_key);
   p.morse = s->potential == HDMD_MORSE;
   const size_t np = (size_t)p.npad, vsz = p.mix ? 4 : 8;
   size_t o = 0;
@@ -354,14 +365,15 @@ static SysDev make_desc(const hdmd_system* s, const Plan& p, void* ws) {
 // occupancy bucket), chosen by timing every variant on the first build that
 // meets the key.  All variants produce identical lists.
 // ---------------------------------------------------------------------------
-// Per key: the grid an autotuned system takes (reach 1 or 2; 0: not decided),
-// the best build variant on each grid (0: not timed), and the lanes per atom
-// of the force kernels per precision form (0: not timed).
+// Per key: the grid an autotuned system takes (reach 1 or 2; 0: not decided)
+// and the best build variant on each grid (0: not timed).
 struct Tuned {
-  int reach = 0, blk[3] = {0, 0, 0}, lpa[2] = {0, 0};
+  int reach = 0, blk[3] = {0, 0, 0};
 };
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Tuned> g_tune;
+// lanes per atom of the force kernels per (d, precision form, row bucket)
+static std::map<std::tuple<int, int, int>, int> g_lanes;
 
 static bool tuning_enabled() {
   const char* e = std::getenv("HDMD_AUTOTUNE");
@@ -402,9 +414,9 @@ static int lookup_blk(const Plan& p, bool* known) {
 
 // Lanes per atom of the force kernels (1, 2 or 4 lanes share an atom's row;
 // their partial sums meet in a tree that depends on the count, so the choice
-// fixes the rounding of the forces): chosen by the autotuner per key and
-// precision form, and kept for every later system of that key, alone or in a
-// batch.  Morse systems take one lane.  HDMD_LPA overrides the choice.
+// fixes the rounding of the forces): chosen by the autotuner per (d,
+// precision form, row bucket) and kept for every later system with that key,
+// alone or in a batch.  Morse systems take one lane.  HDMD_LPA overrides.
 static int lpa_env() {
   const char* e = std::getenv("HDMD_LPA");
   if (!e) return 0;
@@ -412,13 +424,12 @@ static int lpa_env() {
   return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
 }
 
-static int lanes_for(const hdmd_system* s, int d, int wrap, int occ) {
+static int lanes_for(const hdmd_system* s, int d, int rowkey) {
   if (s->potential == HDMD_MORSE) return 1;
   if (const int e = lpa_env()) return e;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tune.find({d, wrap, occ});
-  const int mix = s->precision == HDMD_MIXED ? 1 : 0;
-  return (it == g_tune.end() || !it->second.lpa[mix]) ? 1 : it->second.lpa[mix];
+  auto it = g_lanes.find({d, s->precision == HDMD_MIXED ? 1 : 0, rowkey});
+  return it == g_lanes.end() ? 1 : it->second;
 }
 
 static int lpa_index(int lpa) { return lpa >= 4 ? 2 : (lpa == 2 ? 1 : 0); }
@@ -577,6 +588,9 @@ static int tune_build(const hdmd_system* sys, const Plan& pf, const double* pos,
         best = ms;
         t.blk[reach] = cand;
       }
+      // the half grid's other variants only while it stays within twice the
+      // full grid's time (they are slower than its one-wave build)
+      if (reach == 2 && r0 == 1 && sort_ms + best > 2.f * total[1]) break;
     }
     total[reach] = sort_ms + best;
   }
@@ -624,17 +638,19 @@ static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
     bool timed = false;
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
-      auto it = g_tune.find({p.d, p.key_wrap, p.key_occ});
-      timed = it != g_tune.end() && it->second.lpa[mix];
+      timed = g_lanes.count({p.d, mix, p.row_key}) > 0;
     }
     if (!timed) {
-      // the force kernel with 1, 2 and 4 lanes per atom on the list just built
+      // the force kernel with 1, 2 and 4 lanes per atom on the list just built;
+      // more lanes only where one lane takes at least 20 us and they save 10 %
+      // (below that, launch overheads and the batches' one all-class launch
+      // for one-lane systems count for more)
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       const DKernels* K = dkernels(p.d);
       KArgs a = single_args(dev, p.d);
-      float best = 1e30f;
+      float best = 1e30f, one = 0.f;
       int best_lpa = 1;
       for (int cand : {1, 2, 4}) {
         set_i32(dev, offsetof(SysDev, lpa), cand, st);
@@ -645,6 +661,7 @@ static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (cand == 1) one = ms;
         if (ms < best) {
           best = ms;
           best_lpa = cand;
@@ -652,11 +669,10 @@ static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
       }
       HIPCHK(hipEventDestroy(e0));
       HIPCHK(hipEventDestroy(e1));
+      if (one < 0.020f || best > 0.9f * one) best_lpa = 1;
       {
         std::lock_guard<std::mutex> g(g_tune_mu);
-        Tuned& e = g_tune[std::make_tuple(p.d, p.key_wrap, p.key_occ)];
-        if (!e.lpa[mix]) e.lpa[mix] = best_lpa;
-        p.lpa = e.lpa[mix];
+        p.lpa = g_lanes.emplace(std::make_tuple(p.d, mix, p.row_key), best_lpa).first->second;
       }
       set_i32(dev, offsetof(SysDev, lpa), p.lpa, st);
     }

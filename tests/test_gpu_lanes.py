@@ -154,10 +154,10 @@ def test_batch_with_more_lanes_equals_alone(lanes):
 
 
 def test_autotuned_lanes_are_recorded(orc):
-    """A key no other test meets (d = 5, about 25 atoms per subcell): its first
-    build times 1, 2 and 4 lanes; a second system of the key takes the same
-    count without timing, and its forces equal, bit for bit, those of the
-    same system with that count forced."""
+    """A system's first build times 1, 2 and 4 lanes per atom for its key
+    (d = 5, FP64, expected rows of ~127 atoms); a second system with the same
+    key takes the recorded count, and its forces equal, bit for bit, those of
+    the same system with that count forced."""
     rl = C6 * 1.2 + 0.3
     L = 5 * rl * 1.01
 
