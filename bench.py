@@ -75,11 +75,14 @@ def build_candidates(x: np.ndarray, L: float, nc: int) -> int:
 def workload_name(cfg) -> str:
     if cfg.poly_R > 0:
         mix = "polydisperse P(d,R=%g,sigma)" % cfg.poly_R
+    elif cfg.sig_a == cfg.sig_b:
+        mix = "monodisperse sigma %.1f" % cfg.sig_a
     else:
         mix = "50:50 sigma %.1f/%.1f" % (cfg.sig_a, cfg.sig_b)
     pot = {0: "WCA", 1: "harmonic", 2: "Morse a=30"}[cfg.potential]
-    return "%s: d=%d N=%d %s %s phi=%.4g dt=%g skin=%g T=%g" % (
-        cfg.name, cfg.d, cfg.n, mix, pot, cfg.phi, cfg.dt, cfg.skin, cfg.T)
+    dens = "phi=%.4g" % cfg.phi if cfg.phi is not None else "rho=%.4g" % cfg.rho
+    return "%s: d=%d N=%d %s %s %s dt=%g skin=%g T=%g" % (
+        cfg.name, cfg.d, cfg.n, mix, pot, dens, cfg.dt, cfg.skin, cfg.T)
 
 
 def kernel_hash() -> str:
