@@ -919,10 +919,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c >= nch) break;
+          unsigned long long m[4];
+          if (WR) {
 #pragma unroll
-          for (int u = 0; u < 4; u++) {
-            unsigned long long m;
-            if (WR) {
+            for (int u = 0; u < 4; u++) {
               // |u_j - u_i|^2 over 16-bit wrapped differences (saturating: far
               // pairs clamp at INT_MAX) against the lane's threshold
               int acc = 0;
@@ -932,22 +932,33 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
                                    __builtin_bit_cast(short2v, (int)r[u][k]);
                 acc = __builtin_amdgcn_sdot2(dq, dq, acc, true);
               }
-              m = __ballot(acc < tA[c]);
-            } else {
-              // the first product in the three-operand form, so the lane's
-              // threshold needs no copy into an accumulator register
-              int acc;
+              m[u] = __ballot(acc < tA[c]);
+            }
+          } else {
+            // the four home atoms' products word by word, so that each dot
+            // product's result is not needed by the next instruction; the
+            // first in the three-operand form, so the lane's threshold needs
+            // no copy into an accumulator register
+            int acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
               asm("v_dot2_i32_i16 %0, %1, %2, %3"
-                  : "=v"(acc)
+                  : "=v"(acc[u])
                   : "s"((int)r[u][0]), "v"(cw[c][0]), "v"(tA[c]));
 #pragma unroll
-              for (int k = 1; k < HW; k++)
-                acc = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
-                                             __builtin_bit_cast(short2v, cw[c][k]), acc, false);
-              m = __ballot(acc > r[u][HW]);
-            }
-            mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m, hh[u], (int)mlo[c]);
-            mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m >> 32), hh[u], (int)mhi[c]);
+            for (int k = 1; k < HW; k++)
+#pragma unroll
+              for (int u = 0; u < 4; u++)
+                acc[u] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, (int)r[u][k]),
+                                                __builtin_bit_cast(short2v, cw[c][k]), acc[u],
+                                                false);
+#pragma unroll
+            for (int u = 0; u < 4; u++) m[u] = __ballot(acc[u] > r[u][HW]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            mlo[c] = (unsigned)amdgcn_writelane((int)(unsigned)m[u], hh[u], (int)mlo[c]);
+            mhi[c] = (unsigned)amdgcn_writelane((int)(unsigned)(m[u] >> 32), hh[u], (int)mhi[c]);
           }
         }
       }
