@@ -499,7 +499,7 @@ def main():
                     help="|F|max target of the batched FP64 leg on the prefix (0: skip)")
     ap.add_argument("--fire-max-iter", type=int, default=100000)
     ap.add_argument("--fire-slots", type=int, default=512)
-    ap.add_argument("--fire-budget-gb", type=float, default=0.25,
+    ap.add_argument("--fire-budget-gb", type=float, default=0.5,
                     help="HBM budget of the server's admission (below the stream's footprint)")
     ap.add_argument("--fire-chunk", type=int, default=50)
     ap.add_argument("--no-md", action="store_true", help="skip the MD legs (FIRE serving only)")
