@@ -164,7 +164,8 @@ int hdmd_cells_per_axis(const hdmd_system* sys);
  * them on the first list built for each (d, precision form, expected row
  * length n V_d(r_l,max) / L^d in half-octaves), and every later system with
  * that key, alone or in a batch, takes its choice (the lane count fixes the
- * rounding of the force sums); Morse systems take one.
+ * rounding of the force sums); Morse systems and systems of fewer than 16384
+ * atoms take one.
  * Returns 1 when the autotuner has decided the list build for sys's key, 0
  * when not yet (the defaults are reported: what the next build would time),
  * or a negative status.  Any pointer may be null. */

@@ -424,9 +424,15 @@ static int lpa_env() {
   return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
 }
 
+// Systems below this size take one lane per atom without timing: their force
+// kernels are short, and in a batch every other lane count costs a launch of
+// its own per class, on every iteration.
+constexpr int64_t kLanesMinAtoms = 16384;
+
 static int lanes_for(const hdmd_system* s, int d, int rowkey) {
   if (s->potential == HDMD_MORSE) return 1;
   if (const int e = lpa_env()) return e;
+  if (s->n < kLanesMinAtoms) return 1;
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_lanes.find({d, s->precision == HDMD_MIXED ? 1 : 0, rowkey});
   return it == g_lanes.end() ? 1 : it->second;
@@ -633,7 +639,7 @@ static int init_system(const hdmd_system* sys, Plan& p, const double* pos,
   chain_single(p, dev, st, blk);
   launch_finalize(single_args(dev, p.d), 1, st);
   HIPCHK(hipGetLastError());
-  if (!p.morse && !lpa_env() && tuning_enabled() && allow_tune) {
+  if (!p.morse && !lpa_env() && p.n >= kLanesMinAtoms && tuning_enabled() && allow_tune) {
     const int mix = p.mix ? 1 : 0;
     bool timed = false;
     {
