@@ -397,15 +397,16 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
 //
 // One workgroup per home subcell; its atoms are the lanes (in chunks of BLK).
 // The linked subcells are decoded on the fly from a mixed-radix counter
-// (offsets -1/0/+1 per axis, or the deduplicated {0,+1} / {0} when n_cell is 2
-// / 1).  Each linked subcell's atoms are staged in LDS and every lane tests
+// (offsets -1/0/+1 per axis, -2..+2 on half-size subcells, or the
+// deduplicated {0,+1} / {0} when n_cell is 2 / 1).  Each linked subcell's atoms are staged in LDS and every lane tests
 // every staged atom with a conservative prefilter; survivors go to a per-lane
 // LDS queue and are re-tested exactly in FP64 with the per-pair radius -- the
 // operation sequence of the list definition -- before being appended to the
 // row.  Row order: linked-subcell order, then slot order (deterministic).
 //
-// Prefilter, n_cell >= 3: the image shift of a linked subcell is its offset
-// times the subcell side for every pair within the list radius, so with
+// Prefilter, not wrapped (n_cell >= 3, or half-size subcells, at least 5 per
+// axis): the image shift of a linked subcell is its offset times the subcell
+// side for every pair within the list radius, so with
 // offsets y from the subcell centres quantised to q = y/Delta (Delta =
 // L_sc/250, shift D = 250 o exactly), |r - Delta |q_j + D - q_i|| <= Delta
 // sqrt(d) and
@@ -622,14 +623,14 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Verlet-list build, candidate-lane form (n_cell >= 3)
+// Verlet-list build, candidate-lane form
 //
 // Same list, same row order and the same exact FP64 test as k_build; the
-// work is laid out the other way round.  The linked subcells come in rows of
-// three along the last axis (offsets -1, 0, +1), whose atoms are packed into
-// 64-lane chunks: every lane takes one candidate j, shifts its quantised
-// offsets by the subcell offset (q'_j = q_j + 250 o as int16, |q'| <= 375)
-// and forms A_j = |q'_j|^2.  The home atoms i kept for the row are then
+// work is laid out the other way round.  The linked subcells come in rows
+// along the last axis (offsets -1, 0, +1; -2..+2 on half-size subcells, RAD
+// = 2), whose atoms are packed into 64-lane chunks: every lane takes one
+// candidate j, shifts its quantised offsets by the subcell offset (q'_j = q_j
+// + 250 o as int16, |q'| <= 125 + 250 RAD) and forms A_j = |q'_j|^2.  The home atoms i kept for the row are then
 // walked uniformly, their records (q_i as int16 pairs and B_i = |q_i|^2 - T_i)
 // coming through the scalar cache, each test being
 //   |q'_j - q_i|^2 < T_i + T_j  <=>  (T_j - A_j) + q_i.(2 q'_j) > B_i
@@ -836,10 +837,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // before set 1, each in chunk and lane order (the row order), so the
     // wave's trip count is the largest per-lane survivor count of the pass.
     // The nearest image is taken with rint: with n_cell >= 3 the list radius
-    // is at most L/3, so every pair it can admit has all |dx_k| clear of
-    // L/2, where rint and the definition's shift give the same value bit
-    // for bit; pairs with some |dx_k| near L/2 are beyond the radius either
-    // way.
+    // is at most L/3 (on half-size subcells, at least 5 per axis: 2L/5), so
+    // every pair it can admit has all |dx_k| clear of L/2, where rint and
+    // the definition's shift give the same value bit for bit; pairs with
+    // some |dx_k| near L/2 are beyond the radius either way.
     static_assert(NB <= 16, "chunk bits of both sets fit 32 bits");
     auto exact_pass = [&]() {
       wave_lds_sync();
