@@ -39,21 +39,24 @@ void l_build(int reach, bool wrap, int blk, const KArgs& a, int grid, hipStream_
     // half-size subcells, 5^d stencil (never wrapped)
     if (blk == 1) k_build_t<D, 1, false, 2><<<grid, 64, 0, st>>>(a);
     else if (blk == 2) k_build_t<D, 2, false, 2><<<grid, 128, 0, st>>>(a);
-    else if (blk == 4) k_build_t<D, 4, false, 2><<<grid, 256, 0, st>>>(a);
+    else if (blk == 4 || blk == 8 || blk == 16) k_build_t<D, 4, false, 2><<<grid, 256, 0, st>>>(a);
     else if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);
   } else if (wrap) {
+    // crowded subcells (n_cell <= 2): up to 16 waves share one
     if (blk == 1) k_build_t<D, 1, true><<<grid, 64, 0, st>>>(a);
     else if (blk == 2) k_build_t<D, 2, true><<<grid, 128, 0, st>>>(a);
     else if (blk == 4) k_build_t<D, 4, true><<<grid, 256, 0, st>>>(a);
+    else if (blk == 8) k_build_t<D, 8, true><<<grid, 512, 0, st>>>(a);
+    else if (blk == 16) k_build_t<D, 16, true><<<grid, 1024, 0, st>>>(a);
     else if (blk <= 64) k_build<D, true, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, true, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, true, 256><<<grid, 256, 0, st>>>(a);
   } else {
     if (blk == 1) k_build_t<D, 1, false><<<grid, 64, 0, st>>>(a);
     else if (blk == 2) k_build_t<D, 2, false><<<grid, 128, 0, st>>>(a);
-    else if (blk == 4) k_build_t<D, 4, false><<<grid, 256, 0, st>>>(a);
+    else if (blk == 4 || blk == 8 || blk == 16) k_build_t<D, 4, false><<<grid, 256, 0, st>>>(a);
     else if (blk <= 64) k_build<D, false, 64><<<grid, 64, 0, st>>>(a);
     else if (blk <= 128) k_build<D, false, 128><<<grid, 128, 0, st>>>(a);
     else k_build<D, false, 256><<<grid, 256, 0, st>>>(a);

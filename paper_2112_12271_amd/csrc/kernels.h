@@ -1200,7 +1200,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 }
 
 template <int D, int G, bool WR, int RAD = 1>
-__global__ __launch_bounds__(64 * G, 8) void k_build_t(KArgs a) {
+__global__ __launch_bounds__(64 * G, G >= 8 ? 16 / G : 8) void k_build_t(KArgs a) {
   // per wave: survivor masks of up to 128 home atoms and the candidates of 8 chunks
   __shared__ unsigned long long msk_all[G][8 * 128];
   __shared__ int cand_all[G][8 * 64];

@@ -177,9 +177,10 @@ def test_full_size_sampled_rows(orc, name):
                                            (3, 2, 200), (6, 2, 40), (8, 2, 4), (4, 1, 300)])
 def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
     """Each list-build variant (candidate-lane with 1, 2 or 4 waves per subcell,
-    home-lane with 64/128/256 lanes), forced in turn, gives the definition's
-    list; crowded subcells (more than 64 and 128 atoms) take several home
-    passes; n_cell = 2 and 1 take the wrapped-coordinate prefilter."""
+    and 8 or 16 for the crowded subcells of n_cell <= 2, home-lane with
+    64/128/256 lanes), forced in turn, gives the definition's list; crowded
+    subcells (more than 64 and 128 atoms) take several home passes; n_cell =
+    2 and 1 take the wrapped-coordinate prefilter."""
     import os
     c, s = C6, 0.3
     rlmax = c * 1.4 + s
@@ -189,7 +190,7 @@ def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
     ref = orc.nlist_brute(x, sig, L, c, s)
     old = os.environ.get("HDMD_BUILD_BLK")
     try:
-        for blk in (1, 2, 4, 64, 128, 256):
+        for blk in (1, 2, 4, 8, 16, 64, 128, 256):
             os.environ["HDMD_BUILD_BLK"] = str(blk)
             for prec in (H.HDMD_FP64, H.HDMD_MIXED):
                 sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4,
