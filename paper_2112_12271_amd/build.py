@@ -1,7 +1,9 @@
 """Builds libhdmd.so (gfx950) in-tree from csrc/ with hipcc.
 
 Every HIP translation unit is compiled with -ffp-contract=off (the list test
-must round exactly as written) and with packed FP32 arithmetic disabled.
+must round exactly as written), with packed FP32 arithmetic disabled, and with
+matrix-core results in ordinary vector registers (the list build reads their
+sign bits with vector instructions).
 The dimension-templated kernels are compiled once per d = 2..10 in parallel.
 """
 from __future__ import annotations
@@ -22,6 +24,7 @@ DIMS = range(2, 11)
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", INC, "-I", CSRC, "-Wno-unused-result"]
 
 

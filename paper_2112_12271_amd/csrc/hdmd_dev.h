@@ -48,6 +48,7 @@ constexpr int kQCap = 16;       // per-lane prefilter queue of the build
 constexpr int kSwapBatch = 256;   // SWAP attempts per batch (a multiple of 64)
 constexpr int kPotMorse = 2;     // hdmd_system.potential of the Morse form
 constexpr int kQScale = 250;    // int8 quantisation: subcell side = 250 units
+constexpr int kBuildMF = 1024;  // build-variant flag: candidate-lane build, pair tests on the matrix cores
 
 enum Mode : int32_t { MODE_NONE = 0, MODE_FIRE = 1, MODE_MD = 2, MODE_STATIC = 3 };
 enum Slot : int32_t { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };

@@ -35,6 +35,21 @@ void l_cellsort(bool mix, const KArgs& a, int grid, hipStream_t st) {
   else k_cellsort<D, double><<<grid, 256, 0, st>>>(a);
 }
 void l_build(int reach, bool wrap, int blk, const KArgs& a, int grid, hipStream_t st) {
+  if ((blk & kBuildMF) && !wrap) {
+    // candidate-lane build with the pair tests on the matrix cores
+    blk &= ~kBuildMF;
+    if (reach == 2) {
+      if (blk == 1) k_build_t<D, 1, false, 2, true><<<grid, 64, 0, st>>>(a);
+      else if (blk == 2) k_build_t<D, 2, false, 2, true><<<grid, 128, 0, st>>>(a);
+      else k_build_t<D, 4, false, 2, true><<<grid, 256, 0, st>>>(a);
+    } else {
+      if (blk == 1) k_build_t<D, 1, false, 1, true><<<grid, 64, 0, st>>>(a);
+      else if (blk == 2) k_build_t<D, 2, false, 1, true><<<grid, 128, 0, st>>>(a);
+      else k_build_t<D, 4, false, 1, true><<<grid, 256, 0, st>>>(a);
+    }
+    return;
+  }
+  blk &= ~kBuildMF;  // wrapped systems: the vector form
   if (reach == 2) {
     // half-size subcells, 5^d stencil (never wrapped)
     if (blk == 1) k_build_t<D, 1, false, 2><<<grid, 64, 0, st>>>(a);

@@ -650,6 +650,67 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef _Float16 hv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef unsigned uv2 __attribute__((ext_vector_type(2)));
+typedef unsigned uv4 __attribute__((ext_vector_type(4)));
+
+// Operands of the matrix-core form of the pair test.  A pair test
+//   S_ij = q_i.(2 q'_j) + C_j - B_i > 0   (C_j = T_j - A_j, B_i = |q_i|^2 - T_i)
+// is read off one entry of the product of a candidate matrix (rows) and a
+// home matrix (columns) over 16 slots:
+//   candidate [2q'_j,0 .. 2q'_j,d-1, 2048, 1, 1, floor(C_j/2048), C_j mod 2048, 0 ..]
+//   home      [-q_i,0 .. -q_i,d-1, floor(B_i/2048), B_i mod 2048, 1/2, -2048, -1, 0 ..]
+// gives 1/2 - S_ij, negative exactly when the test passes.  Every slot is an
+// integer of magnitude <= 2048 or 1/2 (exact in f16: |q| <= 127, |2q'| <=
+// 1254, -3.93e6 <= C < 2^22, |B| < 2^18) and every partial sum is a multiple
+// of 1/2 below 2^23 in magnitude, so the f32 accumulation is exact in any
+// order.  For d <= 6 a home atom's slots 8..15 are the same for all atoms.
+__device__ inline unsigned pack_h2(_Float16 lo, _Float16 hi) {
+  return (unsigned)__builtin_bit_cast(unsigned short, lo) |
+         ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
+}
+// f16 value of int16 half k of a packed word
+__device__ inline _Float16 i16_half(int w, int k) {
+  return (_Float16)(k ? (w >> 16) : (int)(short)(w & 0xffff));
+}
+// the 16 slots as 8 words (word t: slots 2t, 2t + 1)
+__device__ inline void slot_words(const _Float16 (&sl)[16], unsigned (&w)[8]) {
+#pragma unroll
+  for (int t = 0; t < 8; t++) w[t] = pack_h2(sl[2 * t], sl[2 * t + 1]);
+}
+// home slots from the atom's int16 offset words and its term B
+template <int D>
+__device__ inline void home_slots(const int* ow, int B, unsigned (&w)[8]) {
+  _Float16 sl[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) sl[k] = (_Float16)0;
+#pragma unroll
+  for (int k = 0; k < D; k++) sl[k] = -i16_half(ow[k / 2], k % 2);
+  sl[D] = (_Float16)(B >> 11);
+  sl[D + 1] = (_Float16)(B & 2047);
+  sl[D + 2] = (_Float16)0.5f;
+  sl[D + 3] = (_Float16)(-2048);
+  sl[D + 4] = (_Float16)(-1);
+  slot_words(sl, w);
+}
+// candidate slots from its shifted, doubled offset words and C (an empty
+// lane's C, below -2^22, becomes -2^22: its entries stay negative)
+template <int D>
+__device__ inline void cand_slots(const int* cw, int C, unsigned (&w)[8]) {
+  C = max(C, -4194304);
+  _Float16 sl[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) sl[k] = (_Float16)0;
+#pragma unroll
+  for (int k = 0; k < D; k++) sl[k] = i16_half(cw[k / 2], k % 2);
+  sl[D] = (_Float16)2048;
+  sl[D + 1] = (_Float16)1;
+  sl[D + 2] = (_Float16)1;
+  sl[D + 3] = (_Float16)(C >> 11);
+  sl[D + 4] = (_Float16)(C & 2047);
+  slot_words(sl, w);
+}
 
 // Uniform loads of the home records go through the scalar cache: read
 // through the constant address space, which tells the compiler that the
@@ -698,9 +759,10 @@ __device__ inline void wave_lds_sync() {
 // One home subcell of a system that rebuilds, split over G waves: gw (< G)
 // selects this wave's share of the home atoms; msk/cand are the wave's LDS
 // arrays.
-template <int D, int G, bool WR, int RAD = 1>
+template <int D, int G, bool WR, int RAD = 1, bool MF = false>
 __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long long* msk, int* cand) {
   static_assert(RAD == 1 || (RAD == 2 && !WR), "wrapped systems take the 3^d stencil");
+  static_assert(!(MF && WR), "the matrix-core test is for subcells of n_cell >= 3");
   constexpr int HW = (D + 1) / 2;        // int16 pair words of q
   // subcell slots of a row along the last axis: offsets -RAD..+RAD (wrapped:
   // the subcell itself and, for n_cell = 2, the other one; the third slot empty)
@@ -714,6 +776,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   typedef __attribute__((address_space(4))) const int cint;
   typedef short short2v __attribute__((ext_vector_type(2)));
   const int lane = threadIdx.x & 63;
+  // the position in a chunk of the candidate a lane takes: its lane, or for
+  // the matrix-core test (MF) the position whose sign bit lands in bit order
+  // (row 4g + v of candidate block cb = lane / 16: position 16g + 15 - 4cb - v)
+  const int cpos = MF ? 16 * ((lane >> 2) & 3) + 15 - 4 * (lane >> 4) - (lane & 3) : lane;
   // subcell starts come through the scalar cache (written by an earlier kernel)
   cint* flat = (cint*)uniform_ptr(s->cell_flat);
   const int c0h = flat[hc];
@@ -1035,8 +1101,146 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     };
     // (T_j - A_j) + q_i.(2 q'_j) > |q_i|^2 - T_i  <=>  |q'_j - q_i|^2 < T_i + T_j
     // for the kept home atoms of both sets against nch chunks (LDS slots nb..)
+    // The matrix-core form of the same tests (MF).  Per chunk and block of
+    // 16 kept home atoms of a set (columns, compacted; their slots staged in
+    // LDS in the chunk slots whose masks this call writes last), one
+    // 16x16x16 product per block of 16 candidates (rows): entry 1/2 - S_ij,
+    // whose sign bit is the test's outcome.  Lane l of the chunk holds the
+    // candidate at position cpos(l), so that the sign bits of the four
+    // result registers of the four candidate blocks, shifted in order into
+    // one word per lane, come out in position order: lane 16g + j holds home
+    // column j's bits of positions 16g .. 16g + 15.  Two half swaps join them
+    // into the two 32-bit halves of each home atom's 64-bit mask (lane r:
+    // positions 0..31 of compacted home r of a pair of blocks, lane 32 + r:
+    // positions 32..63), which are scattered at the end to the home atoms'
+    // slots (all others zero).
+    auto test_chunks_mf = [&](unsigned long long keep0, unsigned long long keep1, int nch,
+                              const int (&cw)[CB][HW], const int (&tA)[CB]) {
+      constexpr int EW = D <= 6 ? 4 : 8;  // staged words per home atom
+      static_assert(CB * 128 * 8 >= 2 * 64 * 4 * EW, "two sets of staged home slots fit CB chunk slots");
+      unsigned* stg = reinterpret_cast<unsigned*>(msk + nb * 128);  // free: nb + CB <= NB
+      const int nk0 = __builtin_popcountll(keep0), nk1 = __builtin_popcountll(keep1);
+      // stage the kept atoms' slots at their rank; returns, in lanes j and
+      // j + 32, the home lanes of compacted rows j (first) and 32 + j
+      // (second): kept atoms go to their rank, the others after them, a
+      // permutation of the lanes
+      auto stage = [&](unsigned long long km, int nk, const int (&ow)[HW + 1], unsigned* st, int& s0,
+                       int& s1) {
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(km >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u));
+        const bool kept = (km >> lane) & 1ull;
+        if (kept) {
+          unsigned w[8];
+          home_slots<D>(ow, ow[HW], w);
+          uv4* e = reinterpret_cast<uv4*>(st + EW * rank);
+          e[0] = uv4{w[0], w[1], w[2], w[3]};
+          if (EW == 8) e[1] = uv4{w[4], w[5], w[6], w[7]};
+        }
+        const int dst = kept ? rank : nk + (lane - rank);
+        const unsigned src = (unsigned)__builtin_amdgcn_ds_permute(dst * 4, lane);
+        const auto sw = __builtin_amdgcn_permlane32_swap(src, src, false, false);
+        s0 = (int)sw[0];
+        s1 = (int)sw[1];
+      };
+      int sa0, sb0, sa1, sb1;
+      stage(keep0, nk0, ow0, stg, sa0, sb0);
+      stage(keep1, nk1, ow1, stg + 64 * EW, sa1, sb1);
+      wave_lds_sync();
+      // the slot words 8..11 (lane group 2) and 12..15 (group 3) that every
+      // home atom shares when d <= 6
+      uv2 hconst = {0u, 0u};
+      if constexpr (EW == 4) {
+        unsigned w[8];
+        home_slots<D>(ow0, 0, w);
+        hconst = (lane & 16) ? uv2{w[6], w[7]} : uv2{w[4], w[5]};
+      }
+      const int q = lane >> 4;
+      // one set's home blocks 2p and 2p + 1 (compacted homes 32p ..) against
+      // the chunk's candidate blocks X: lane r < 32 receives positions 0..31
+      // of home 32p + r, lane 32 + r its positions 32..63
+      auto mf_pair = [&](const unsigned* st, int nk, int p, const hv4 (&X)[4])
+          __attribute__((always_inline)) -> unsigned {
+        unsigned R[2] = {0u, 0u};
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int b = 2 * p + h;
+          if (16 * b >= nk) break;
+          const uv2* e = reinterpret_cast<const uv2*>(st + EW * (16 * b + (lane & 15)));
+          uv2 hw = e[EW == 4 ? (q & 1) : q];
+          if (EW == 4 && q >= 2) hw = hconst;
+          const hv4 Hb = __builtin_bit_cast(hv4, hw);
+          unsigned P = 0u;
+#pragma unroll
+          for (int cb = 0; cb < 4; cb++) {
+            const fv4 zero = {};
+            const fv4 e4 = __builtin_amdgcn_mfma_f32_16x16x16f16(X[cb], Hb, zero, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; v++) P = __builtin_amdgcn_alignbit(P, __float_as_uint(e4[v]), 31u);
+          }
+          // lanes j, 16 + j: positions 0..31 of home j; lanes 32 + j, 48 + j: 32..63
+          const auto sw = __builtin_amdgcn_permlane16_swap(P, P, false, false);
+          R[h] = (unsigned)sw[0] | ((unsigned)sw[1] << 16);
+        }
+        return (lane & 16) ? R[1] : R[0];
+      };
+      unsigned r00[CB], r01[CB], r10[CB], r11[CB];  // set, pair of home blocks
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        r00[c] = r01[c] = r10[c] = r11[c] = 0u;
+        if (c >= nch) continue;
+        unsigned w[8];
+        cand_slots<D>(cw[c], tA[c], w);
+        // lane group g of block X[cb] takes slot words 2g, 2g + 1 of the
+        // candidate in lane 16 cb + (lane mod 16): a 4x4 transpose of lane
+        // groups and word pairs in two rounds of half swaps
+        unsigned W[4][2];
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+#pragma unroll
+          for (int g = 0; g < 4; g++) W[g][t] = w[2 * g + t];
+#pragma unroll
+          for (int g = 0; g < 2; g++) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(W[g][t], W[g + 2][t], false, false);
+            W[g][t] = sw[0];
+            W[g + 2][t] = sw[1];
+          }
+#pragma unroll
+          for (int g = 0; g < 4; g += 2) {
+            const auto sw = __builtin_amdgcn_permlane16_swap(W[g][t], W[g + 1][t], false, false);
+            W[g][t] = sw[0];
+            W[g + 1][t] = sw[1];
+          }
+        }
+        hv4 X[4];
+#pragma unroll
+        for (int g = 0; g < 4; g++) X[g] = __builtin_bit_cast(hv4, uv2{W[g][0], W[g][1]});
+        if (nk0 > 0) r00[c] = mf_pair(stg, nk0, 0, X);
+        if (nk0 > 32) r01[c] = mf_pair(stg, nk0, 1, X);
+        if (nk1 > 0) r10[c] = mf_pair(stg + 64 * EW, nk1, 0, X);
+        if (nk1 > 32) r11[c] = mf_pair(stg + 64 * EW, nk1, 1, X);
+      }
+      // (the stage has been read: one wave's LDS operations complete in order)
+      unsigned* mw = reinterpret_cast<unsigned*>(msk);
+      const int hf = lane >> 5, rj = lane & 31;
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        if (c >= nch) continue;
+        const int base = (nb + c) * 128;
+        msk[base + lane] = 0ull;
+        msk[base + 64 + lane] = 0ull;
+        if (rj < nk0) mw[2 * (base + sa0) + hf] = r00[c];
+        if (32 + rj < nk0) mw[2 * (base + sb0) + hf] = r01[c];
+        if (rj < nk1) mw[2 * (base + 64 + sa1) + hf] = r10[c];
+        if (32 + rj < nk1) mw[2 * (base + 64 + sb1) + hf] = r11[c];
+      }
+      nb += nch;
+    };
     auto test_chunks = [&](unsigned long long keep0, unsigned long long keep1, int nch,
                            const int (&cw)[CB][HW], const int (&tA)[CB]) {
+      if constexpr (MF) {
+        test_chunks_mf(keep0, keep1, nch, cw, tA);
+        return;
+      }
       unsigned m0lo[CB], m0hi[CB], m1lo[CB], m1hi[CB];
 #pragma unroll
       for (int c = 0; c < CB; c++) m0lo[c] = m0hi[c] = m1lo[c] = m1hi[c] = 0u;
@@ -1088,7 +1292,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           if (c >= nch) continue;
-          cand[(nb + c) * 64 + lane] = cand_words(k0 + c * 64 + lane, T, db, cum, Dp, cw[c], tA[c]);
+          cand[(nb + c) * 64 + cpos] = cand_words(k0 + c * 64 + cpos, T, db, cum, Dp, cw[c], tA[c]);
         }
         test_chunks(keep0, keep1, nch, cw, tA);
       }
@@ -1145,18 +1349,18 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 #pragma unroll
         for (int c = 0; c < CB; c++) {
           const int T = row + c < nrow ? Tr[c] : 0;
-          int j = fl[c][0] + lane, acc = fl[c][1] - fl[c][0];
+          int j = fl[c][0] + cpos, acc = fl[c][1] - fl[c][0];
           lv[c] = lshift(0);
 #pragma unroll
           for (int r = 1; r < NRS; r++) {
-            if (lane >= acc) {
-              j = fl[c][2 * r] - acc + lane;
+            if (cpos >= acc) {
+              j = fl[c][2 * r] - acc + cpos;
               lv[c] = lshift(r);
             }
             acc += fl[c][2 * r + 1] - fl[c][2 * r];
           }
-          jj[c] = lane < T ? j : -1;
-          const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(lane < T ? j : hb) * 8);
+          jj[c] = cpos < T ? j : -1;
+          const HDMD_GLOBAL int* src = gbl(qc16 + (size_t)(cpos < T ? j : hb) * 8);
 #pragma unroll
           for (int k = 0; k < HW; k++) rw[c][k] = src[k];
           rw[c][HW] = src[6];
@@ -1175,7 +1379,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
             cw[c][k] = __builtin_bit_cast(int, r2 + r2);
           }
           tA[c] = jj[c] >= 0 ? rw[c][HW] - A : -0x3fffffff;  // never passes for an empty lane
-          cand[(nb + c) * 64 + lane] = jj[c];
+          cand[(nb + c) * 64 + cpos] = jj[c];
         }
         test_chunks(k0m, k1m, CB, cw, tA);
       }
@@ -1199,7 +1403,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
   }
 }
 
-template <int D, int G, bool WR, int RAD = 1>
+template <int D, int G, bool WR, int RAD = 1, bool MF = false>
 __global__ __launch_bounds__(64 * G, G >= 8 ? 16 / G : 8) void k_build_t(KArgs a) {
   // per wave: survivor masks of up to 128 home atoms and the candidates of 8 chunks
   __shared__ unsigned long long msk_all[G][8 * 128];
@@ -1212,7 +1416,7 @@ __global__ __launch_bounds__(64 * G, G >= 8 ? 16 / G : 8) void k_build_t(KArgs a
     s = uniform_ptr(s);
     hc = uniform_int(hc);
     if (!running(s) || !need_rebuild(s) || uniform_int(s->reach) != RAD) continue;
-    build_t_tile<D, G, WR, RAD>(s, hc, wv, msk_all[wv], cand_all[wv]);
+    build_t_tile<D, G, WR, RAD, MF>(s, hc, wv, msk_all[wv], cand_all[wv]);
   }
 }
 

@@ -581,9 +581,10 @@ static int tune_build(const hdmd_system* sys, const Plan& pf, const double* pos,
       if (rc) return rc;
     }
     float best = 1e30f;
-    for (int cand : {1, 2, 4, 8, 16, 64, 128, 256}) {
-      if (reach == 2 && cand > 4) break;
+    for (int cand : {1, 2, 4, 1 | kBuildMF, 2 | kBuildMF, 4 | kBuildMF, 8, 16, 64, 128, 256}) {
+      if (reach == 2 && (cand & ~kBuildMF) > 4) break;
       if (!p.wrap && (cand == 8 || cand == 16)) continue;  // 8 and 16 waves: crowded subcells only
+      if (p.wrap && (cand & kBuildMF)) continue;  // matrix-core tests: n_cell >= 3 only
       build_single(p, dev, st, cand);  // warm-up
       HIPCHK(hipEventRecord(e0, st));
       build_single(p, dev, st, cand);

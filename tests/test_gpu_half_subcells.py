@@ -45,7 +45,8 @@ SIZES = {2: (9, 900), 3: (8, 1500), 4: (7, 1500), 5: (6, 1200), 6: (6, 1500), 7:
 
 @pytest.mark.parametrize("d", range(2, 11))
 def test_half_grid_lists_equal_definition(orc, d):
-    """Every candidate-lane variant (1, 2, 4 waves per subcell) and, for d <= 7,
+    """Every candidate-lane variant (1, 2, 4 waves per subcell; pair tests on
+    the vector units or the matrix cores) and, for d <= 7,
     the home-lane build (64/128/256 lanes) on half-size subcells give the
     definition's list in both precision forms (atoms placed in pairs 0.5 to
     1.1 r_l,max apart, diameters 1 and 1.4)."""
@@ -55,7 +56,7 @@ def test_half_grid_lists_equal_definition(orc, d):
     L = nh * 0.5 * rlmax * 1.02
     x, sig = partnered(d, n, L, 700 + d, rlmax)
     ref = orc.nlist_brute(x, sig, L, c, s)
-    for blk in (1, 2, 4) + ((64, 128, 256) if d <= 7 else ()):
+    for blk in (1, 2, 4, 1025, 1026, 1028) + ((64, 128, 256) if d <= 7 else ()):
         with _blk(blk):
             for prec in (H.HDMD_FP64, H.HDMD_MIXED):
                 sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4,

@@ -177,8 +177,9 @@ def test_full_size_sampled_rows(orc, name):
                                            (3, 2, 200), (6, 2, 40), (8, 2, 4), (4, 1, 300)])
 def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
     """Each list-build variant (candidate-lane with 1, 2 or 4 waves per subcell,
-    and 8 or 16 for the crowded subcells of n_cell <= 2, home-lane with
-    64/128/256 lanes), forced in turn, gives the definition's list; crowded
+    with the pair tests on the vector units or the matrix cores, 8 or 16 waves
+    for the crowded subcells of n_cell <= 2, home-lane with 64/128/256 lanes),
+    forced in turn, gives the definition's list; crowded
     subcells (more than 64 and 128 atoms) take several home passes; n_cell =
     2 and 1 take the wrapped-coordinate prefilter."""
     import os
@@ -190,11 +191,48 @@ def test_every_build_variant_equals_definition(orc, d, nc, per_cell):
     ref = orc.nlist_brute(x, sig, L, c, s)
     old = os.environ.get("HDMD_BUILD_BLK")
     try:
-        for blk in (1, 2, 4, 8, 16, 64, 128, 256):
+        for blk in (1, 2, 4, 1025, 1026, 1028, 8, 16, 64, 128, 256):
             os.environ["HDMD_BUILD_BLK"] = str(blk)
             for prec in (H.HDMD_FP64, H.HDMD_MIXED):
                 sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4,
                                 precision=prec, max_neighbors=16)
+                assert H.hdmd_cells_per_axis(sysd) == nc
+                got, _, _ = gpu_list(sysd, x, sig)
+                assert csr_equal(got, ref), (d, blk, prec)
+    finally:
+        if old is None:
+            os.environ.pop("HDMD_BUILD_BLK", None)
+        else:
+            os.environ["HDMD_BUILD_BLK"] = old
+
+
+# (d, subcells per axis, atoms): dense grids (rows of several chunks, up to
+# ~200 atoms per subcell: two home sets, two blocks of 32 kept atoms) down to
+# sparse ones (four rows per round)
+MF_CASES = [(2, 5, 5000), (3, 4, 9000), (4, 3, 8000), (5, 3, 9000), (6, 3, 12000),
+            (7, 3, 9000), (8, 3, 8000), (9, 3, 10000), (10, 3, 16000)]
+
+
+@pytest.mark.parametrize("d,nc,n", MF_CASES)
+def test_matrix_core_build_equals_definition(orc, d, nc, n):
+    """The candidate-lane build with its pair tests on the matrix cores (one
+    f16 32x32x16 product per 32 candidates and 32 kept home atoms, exact in
+    f32), with 1, 2 and 4 waves per subcell, gives the definition's list in
+    both precision forms for d = 2..10."""
+    import os
+    c, s = C6, 0.3
+    rlmax = c * 1.4 + s
+    L = nc * rlmax * 1.02
+    x, sig = partnered(d, n, L, 91 * d + nc, rlmax)
+    ref = orc.nlist_brute(x, sig, L, c, s)
+    old = os.environ.get("HDMD_BUILD_BLK")
+    try:
+        for blk in (1025, 1026, 1028):
+            os.environ["HDMD_BUILD_BLK"] = str(blk)
+            for prec in (H.HDMD_FP64, H.HDMD_MIXED):
+                sysd = H.System(d=d, n=n, box_l=L, cutoff=c, skin=s, sigma_max=1.4,
+                                precision=prec, max_neighbors=32,
+                                subcells=H.HDMD_SUBCELLS_FULL)
                 assert H.hdmd_cells_per_axis(sysd) == nc
                 got, _, _ = gpu_list(sysd, x, sig)
                 assert csr_equal(got, ref), (d, blk, prec)
