@@ -321,6 +321,11 @@ __device__ inline void load_rec(const double* __restrict__ xb, int i, double (&x
   const HDMD_GLOBAL vd2* p = gbl(reinterpret_cast<const vd2*>(xb + (size_t)i * Dims<D>::DR));
 #pragma unroll
   for (int k = 0; k < Dims<D>::NR; k++) {
+    if (2 * k == D) {
+      // (sigma, padding): sigma alone
+      sg = *reinterpret_cast<const HDMD_GLOBAL double*>(p + k);
+      continue;
+    }
     const vd2 t = p[k];
     if (2 * k < D) x[2 * k] = t.x;
     else sg = t.x;

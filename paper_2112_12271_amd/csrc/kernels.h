@@ -882,8 +882,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         }
       }
     };
-    own_q(ii0, qh0);
-    own_q(ii1, qh1);
+    if constexpr (WR) {  // (n_cell >= 3: the offsets come from the record words)
+      own_q(ii0, qh0);
+      own_q(ii1, qh1);
+    }
     // the lane's own home record (offset words and the home term), from
     // which the pair tests of n_cell >= 3 systems take each home atom's words
     // with v_readlane: the records of every wave of a CU (one subcell each)
@@ -899,60 +901,126 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     ow1[HW] = qc16[(size_t)ii1 * 8 + BW];
     int len0 = 0, len1 = 0, nb = 0;
 
-    // exact test of the survivors.  Each lane walks its own: home set 0
-    // before set 1, each in chunk and lane order (the row order), so the
-    // wave's trip count is the largest per-lane survivor count of the pass.
+    // exact test of the survivors, spread over the lanes.  The survivors of
+    // the pass are listed home atom by home atom (set 0, then set 1; each
+    // atom's in chunk and bit order, the row order) as 16-bit codes (home
+    // atom, chunk, bit) in the free chunk slots after the pass's masks (at
+    // least one: the passes start while nb + CB <= NB - 1), and taken 64 at
+    // a time, one per lane.  In a batch the survivors of one home atom are a
+    // run of consecutive lanes; a passing one goes to the atom's row at its
+    // length so far plus the passing survivors of its run on lower lanes, so
+    // every row takes its pairs in the row order.  (Walking each atom's own
+    // survivors in its lane instead leaves most lanes idle: in a pass only
+    // the atoms near its rows have survivors.)
     // The nearest image is taken with rint: with n_cell >= 3 the list radius
     // is at most L/3 (on half-size subcells, at least 5 per axis: 2L/5), so
     // every pair it can admit has all |dx_k| clear of L/2, where rint and
     // the definition's shift give the same value bit for bit; pairs with
     // some |dx_k| near L/2 are beyond the radius either way.
-    static_assert(NB <= 16, "chunk bits of both sets fit 32 bits");
+    static_assert(NB <= 8, "the chunk index fits three bits of a code");
     auto exact_pass = [&]() {
       wave_lds_sync();
-      unsigned ne = 0;  // bit set*NB + b: chunk b holds survivors of home set `set`
+      // survivor counts of the lane's two home atoms, and the chunks that
+      // hold any (bit set * NB + b)
+      int c0 = 0, c1 = 0;
+      unsigned ne = 0;
       for (int b = 0; b < nb; b++) {
-        if (msk[b * 128 + lane]) ne |= 1u << b;
-        if (two && msk[b * 128 + 64 + lane]) ne |= 1u << (NB + b);
+        const int n0 = __builtin_popcountll(msk[b * 128 + lane]);
+        const int n1 = two ? __builtin_popcountll(msk[b * 128 + 64 + lane]) : 0;
+        c0 += n0;
+        c1 += n1;
+        ne |= (n0 ? 1u << b : 0u) | (n1 ? 1u << (NB + b) : 0u);
       }
-      unsigned long long m = 0;
-      int cb = 0, cur = -1, i = 0;
-      double xi[D], si;  // own record, loaded when the walk reaches its set
-      while (true) {
-        if (m == 0) {
-          if (ne == 0) break;
-          cb = __builtin_ctz(ne);
-          ne &= ne - 1;
-          const int set = cb >= NB ? 1 : 0;
-          m = msk[(cb % NB) * 128 + set * 64 + lane];
-          if (set != cur) {
-            cur = set;
-            i = set ? i1 : i0;
-            load_rec<D>(xb, set ? ii1 : ii0, xi, si);
-          }
-        }
-        const int j = cand[(cb % NB) * 64 + __builtin_ctzll(m)];
-        m &= m - 1;
-        double xj[D], sj;
-        load_rec<D>(xb, j, xj, sj);
-        if (j != i) {
-          double r2 = 0.0;
+      int p0 = c0, p1 = c1;  // inclusive prefix sums over the lanes
 #pragma unroll
-          for (int k = 0; k < D; k++) {
-            const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
-                                 : near_image(xj[k] - xi[k], L, invL);
-            r2 = __builtin_fma(dx, dx, r2);
-            __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
-          }
-          if (r2 < list_r2(si, sj, cut, skin)) {
-            const int len = cur ? len1 : len0;
-            if (len < W) nl[(size_t)len * npad + i] = j;
-            if (cur) len1 = len + 1;
-            else len0 = len + 1;
-          }
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u0 = __shfl_up(p0, o), u1 = __shfl_up(p1, o);
+        if (lane >= o) {
+          p0 += u0;
+          p1 += u1;
         }
       }
-      wave_lds_sync();
+      const int S0 = __shfl(p0, 63), S = S0 + __shfl(p1, 63);
+      // first list index and count of each atom's survivors, packed
+      // (index < 7 * 64 * 128 < 2^16, count <= 7 * 64)
+      const unsigned r0 = ((unsigned)(p0 - c0) << 16) | (unsigned)c0;
+      const unsigned r1 = ((unsigned)(S0 + p1 - c1) << 16) | (unsigned)c1;
+      unsigned short* code = reinterpret_cast<unsigned short*>(msk + nb * 128);
+      const int cap = 512 * (NB - nb);
+      // each lane's walk over its survivors (set 0, then set 1; chunk and
+      // bit order), resumed round after round: list index e, current chunk
+      // cb and its remaining bits m
+      int e = (int)(r0 >> 16), cb = 0;
+      unsigned long long m = 0;
+      for (int e0 = 0; e0 < S; e0 += cap) {
+        const int e1 = min(S, e0 + cap);
+        // the codes of list entries e0 .. e1 - 1
+        while (e < e1) {
+          if (m == 0) {
+            if (ne == 0) break;
+            const int nx = __builtin_ctz(ne);
+            ne &= ne - 1;
+            if (nx >= NB && cb < NB) e = (int)(r1 >> 16);  // on to set 1's list entries
+            cb = nx;
+            m = msk[(cb % NB) * 128 + (cb >= NB ? 64 : 0) + lane];
+            if (e >= e1) break;
+          }
+          code[e - e0] = (unsigned short)((((cb >= NB ? 64 : 0) + lane) << 9) | ((cb % NB) << 6) |
+                                          __builtin_ctzll(m));
+          m &= m - 1;
+          e++;
+        }
+        wave_lds_sync();
+        for (int t = e0; t < e1; t += 64) {
+          const bool valid = t + lane < e1;
+          const int cd = valid ? (int)code[t + lane - e0] : 0;
+          const int h = cd >> 9;
+          const int i = hb + h;
+          const int j = valid ? cand[((cd >> 6) & 7) * 64 + (cd & 63)] : i;
+          // the lanes below this one in its run (the run's head: the highest
+          // lane at or below it whose home atom differs from the lane
+          // below's), and the atom's row length so far
+          const int hp = __shfl_up(h, 1);
+          const unsigned long long H = __ballot(lane == 0 || hp != h);
+          const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+          const int head = 63 - __builtin_clzll(H & (below | (1ull << lane)));
+          const unsigned long long run = below & ~((1ull << head) - 1);
+          const int la = __shfl(len0, h & 63), lb = __shfl(len1, h & 63);
+          const int base = h >= 64 ? lb : la;
+          __builtin_amdgcn_sched_barrier(0);
+          double xi[D], si, xj[D], sj;
+          load_rec<D>(xb, i, xi, si);
+          load_rec<D>(xb, j, xj, sj);
+          bool pass = false;
+          if (j != i) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+              const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
+                                   : near_image(xj[k] - xi[k], L, invL);
+              r2 = __builtin_fma(dx, dx, r2);
+              __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
+            }
+            pass = r2 < list_r2(si, sj, cut, skin);
+          }
+          const unsigned long long P = __ballot(pass);
+          const int pos = base + __builtin_popcountll(P & run);
+          if (pass && pos < W) nl[(size_t)pos * npad + i] = j;
+          // the lane's own atoms take their passing survivors of the batch
+          auto add = [&](unsigned rs, int& len) {
+            const int st = (int)(rs >> 16), c = (int)(rs & 0xffff);
+            const int lo = max(st - t, 0), hi = min(st + c - t, 64);
+            if (lo < hi) {
+              const unsigned long long mk =
+                  (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+              len += __builtin_popcountll(P & mk);
+            }
+          };
+          add(r0, len0);
+          add(r1, len1);
+        }
+        wave_lds_sync();  // the codes are read before the next round lists over them
+      }
       nb = 0;
     };
 
@@ -1033,6 +1101,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
 
     // home atoms that can reach a row: gap to the neighbouring faces along
     // the first d-1 axes, one quantisation unit short per axis
+    // the int16 offset of axis k from a home record's offset words (n_cell >= 3)
+    auto oq = [](const int (&w)[HW + 1], int k) -> int {
+      return (k % 2) ? (w[k / 2] >> 16) : (int)(short)(w[k / 2] & 0xffff);
+    };
     auto row_keep = [&](const int (&og)[D - 1], unsigned long long& keep0,
                         unsigned long long& keep1) {
       int S0 = 0, S1 = 0;
@@ -1044,16 +1116,16 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           g0 = o ? qh0[k] : 0;
           g1 = o ? qh1[k] : 0;
         } else if (RAD == 1) {
-          g0 = (kQScale / 2) - o * qh0[k] - 1;
-          g1 = (kQScale / 2) - o * qh1[k] - 1;
+          g0 = (kQScale / 2) - o * oq(ow0, k) - 1;
+          g1 = (kQScale / 2) - o * oq(ow1, k) - 1;
           g0 = (o == 0 || g0 < 0) ? 0 : g0;
           g1 = (o == 0 || g1 < 0) ? 0 : g1;
         } else {
           // the near face of a subcell |o| away: (|o| - 1/2) sides from the centre
           const int ao = o < 0 ? -o : o;
           const int face = (kQScale / 2) * (2 * ao - 1);
-          g0 = face - (o > 0 ? qh0[k] : -qh0[k]) - 1;
-          g1 = face - (o > 0 ? qh1[k] : -qh1[k]) - 1;
+          g0 = face - (o > 0 ? oq(ow0, k) : -oq(ow0, k)) - 1;
+          g1 = face - (o > 0 ? oq(ow1, k) : -oq(ow1, k)) - 1;
           g0 = (o == 0 || g0 < 0) ? 0 : g0;
           g1 = (o == 0 || g1 < 0) ? 0 : g1;
         }
@@ -1130,8 +1202,16 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
                                                         __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u));
         const bool kept = (km >> lane) & 1ull;
         if (kept) {
+          // (converted here, each time: hoisted out of the row loop, the
+          // slots of both sets would hold 16 registers through it)
+          int owl[HW + 1];
+#pragma unroll
+          for (int k = 0; k <= HW; k++) {
+            owl[k] = ow[k];
+            asm volatile("" : "+v"(owl[k]));
+          }
           unsigned w[8];
-          home_slots<D>(ow, ow[HW], w);
+          home_slots<D>(owl, owl[HW], w);
           uv4* e = reinterpret_cast<uv4*>(st + EW * rank);
           e[0] = uv4{w[0], w[1], w[2], w[3]};
           if (EW == 8) e[1] = uv4{w[4], w[5], w[6], w[7]};
@@ -1264,30 +1344,33 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       // rows: the waves that lag get the issue slots, and those of a SIMD
       // finish together.
       set_prio_by_progress(row, nrow);
-      int Dp[HW], og[D - 1];
-      const int P = row_base(row, Dp, og);
-      unsigned long long keep0, keep1;
-      row_keep(og, keep0, keep1);
-      if ((keep0 | keep1) == 0) return;
-      // the row's subcells in stencil order: (-RAD..+RAD) or, wrapped, (0, +1)
-      // (all scalar loads issued before the first is used)
-      int f[2 * NRS];
+      // The row's set-up is redone for each round of CB chunks, after any
+      // pass of exact tests: nothing of it stays live across that pass.
+      for (int k0 = 0;; k0 += CB * 64) {
+        if (nb + CB > NB - 1) exact_pass();
+        int Dp[HW], og[D - 1];
+        const int P = row_base(row, Dp, og);
+        unsigned long long keep0, keep1;
+        row_keep(og, keep0, keep1);
+        if ((keep0 | keep1) == 0) return;
+        // the row's subcells in stencil order: (-RAD..+RAD) or, wrapped, (0, +1)
+        // (all scalar loads issued before the first is used)
+        int f[2 * NRS];
 #pragma unroll
-      for (int r = 0; r < NRS; r++) {
-        f[2 * r] = lvalid(r) ? flat[P + lcell(r)] : 0;
-        f[2 * r + 1] = lvalid(r) ? flat[P + lcell(r) + 1] : 0;
-      }
-      int db[NRS], cum[NRS], T = 0;
+        for (int r = 0; r < NRS; r++) {
+          f[2 * r] = lvalid(r) ? flat[P + lcell(r)] : 0;
+          f[2 * r + 1] = lvalid(r) ? flat[P + lcell(r) + 1] : 0;
+        }
+        int db[NRS], cum[NRS], T = 0;
 #pragma unroll
-      for (int r = 0; r < NRS; r++) {
-        // run r starts at atom f[2r] and takes candidates T.. (T before it)
-        db[r] = r == 0 ? f[0] : (f[2 * r] - f[2 * r - 2]) - (cum[r - 1] - (r >= 2 ? cum[r - 2] : 0));
-        T += f[2 * r + 1] - f[2 * r];
-        cum[r] = T;
-      }
-      for (int k0 = 0; k0 < T; k0 += CB * 64) {
+        for (int r = 0; r < NRS; r++) {
+          // run r starts at atom f[2r] and takes candidates T.. (T before it)
+          db[r] = r == 0 ? f[0] : (f[2 * r] - f[2 * r - 2]) - (cum[r - 1] - (r >= 2 ? cum[r - 2] : 0));
+          T += f[2 * r + 1] - f[2 * r];
+          cum[r] = T;
+        }
+        if (k0 >= T) return;
         const int nch = min(CB, (T - k0 + 63) / 64);
-        if (nb + CB > NB) exact_pass();
         int cw[CB][HW], tA[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) {
@@ -1306,7 +1389,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       // the row-by-row walk, which a group with a longer row takes instead
       for (int row = 0; row < nrow; row += CB) {
         set_prio_by_progress(row, nrow);
-        if (nb + CB > NB) exact_pass();
+        if (nb + CB > NB - 1) exact_pass();
         // in phases, so that the scalar loads of all CB rows and then their
         // candidate loads are issued before any of them is waited for
         int P[CB], Dps[CB][HW];
