@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9   # vector lane-operations per second (MI355X)
+MF_FLAG = 1024                                  # build-variant flag: pair tests on the matrix cores
 
 
 def log(*a):
@@ -169,7 +170,17 @@ def run_windows(H, torch, cfg, X0, V0, SIG, L, prec, steps, warmup, windows, eve
     mean_row = cols.numel() / cfg.n
     nc = H.hdmd_cells_per_axis(sysd)
     cand = build_candidates(X.cpu().numpy(), L, nc) if nc >= 3 else None
-    return out, dict(mean_row=mean_row, width=sysd.max_neighbors, candidates=cand)
+    variant = H.hdmd_build_config(sysd)[3]
+    return out, dict(mean_row=mean_row, width=sysd.max_neighbors, candidates=cand,
+                     build_variant=variant)
+
+
+def build_kernel_name(d: int, variant: int) -> str:
+    """The list-build kernel a build variant launches (n_cell >= 3)."""
+    g = variant & ~MF_FLAG
+    if g >= 64:
+        return "k_build<%d,%d lanes>" % (d, g)
+    return "k_build_t<%d,%d%s>" % (d, g, ",matrix-core tests" if variant & MF_FLAG else "")
 
 
 def window_record(cfg, prec_mixed, win, meta, steps):
@@ -193,7 +204,7 @@ def window_record(cfg, prec_mixed, win, meta, steps):
                    build_ms=(st.build_kernel_ms / st.build_kernels if st.build_kernels else None),
                    builds_per_s=(1e3 * st.build_kernels / st.build_kernel_ms
                                  if st.build_kernels else None),
-                   build_candidates=meta["candidates"],
+                   build_candidates=meta["candidates"], build_variant=meta["build_variant"],
                    share_step_kernel=st.step_kernel_ms / ms,
                    share_build_kernel=st.build_kernel_ms / ms,
                    other_ms=other, share_other=other / ms)
@@ -589,19 +600,22 @@ def main():
                 "traffic": committed_traffic("step_kernel_c3_traffic.json"),
                 "kernel": "k_step<6,fp64>", "bytes_per_launch": cfg.n * f["step_bytes_per_atom"],
                 "launch_ms": f["step_kernel_ms"]}
-    # the list build against the vector ALU peak: every candidate pair of the
-    # subcell stencil (Sec. II.C) costs ceil(d/2) packed int16 dot products
-    # and a compare in the prefilter, one VALU lane-operation each; the peak
-    # is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second.
-    # (Row culling skips most candidates before any test, so the kernel's own
-    # VALU rate is lower than this algorithmic one.)
+    # the list build as a candidate rate against the vector ALU peak: every
+    # candidate pair of the subcell stencil (Sec. II.C) is priced at the
+    # vector prefilter's cost, ceil(d/2) packed int16 dot products and a
+    # compare, one VALU lane-operation each; the peak is 256 CUs x 4 SIMDs x
+    # 16 lanes x 2.4 GHz lane-operations per second.  (Row culling skips most
+    # candidates before any test, and the matrix-core variant runs the tests
+    # it does make as f16 products, so this is a rate, not the kernel's own
+    # VALU use.)
     roof_build = None
     if f.get("build_ms") and f.get("build_candidates"):
         ops = (cfg.d + 1) // 2 + 1
         ach = f["build_candidates"] * ops / (f["build_ms"] * 1e-3)
         roof_build = {"bound": "alu", "achieved": ach, "peak": VALU_LANE_OPS_PEAK,
                       "unit": "lane-op/s", "frac": ach / VALU_LANE_OPS_PEAK,
-                      "kernel": "k_build_t<6,1>", "candidates_per_build": f["build_candidates"],
+                      "kernel": build_kernel_name(cfg.d, f.get("build_variant", 1)),
+                      "candidates_per_build": f["build_candidates"],
                       "candidates_per_s": f["build_candidates"] / (f["build_ms"] * 1e-3),
                       "launch_ms": f["build_ms"], "lane_ops_per_candidate": ops}
     cpu = None

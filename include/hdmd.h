@@ -158,11 +158,14 @@ int hdmd_cells_per_axis(const hdmd_system* sys);
 /* The kernel configuration calls on sys use now.  List build (Sec. II.C):
  * *reach 1 (subcells of side >= r_l,max, 3^d stencil) or 2 (half-size
  * subcells, 5^d stencil), *cells_per_axis of that grid, and *variant 1, 2 or
- * 4 (waves per subcell of the candidate-lane build) or 64, 128, 256 (lanes
- * per workgroup of the home-lane build).  Forces (Sec. II.B getforce):
- * *lanes_per_atom 1, 2 or 4 lanes sharing an atom's row; the autotuner times
- * them on the first list built for each (d, precision form, expected row
- * length n V_d(r_l,max) / L^d in half-octaves), and every later system with
+ * 4 (waves per subcell of the candidate-lane build; plus 1024: its pair
+ * prefilter as f16 matrix-core products, exact in f32, n_cell >= 3 only; 8
+ * or 16 for crowded subcells, n_cell <= 2) or 64, 128, 256 (lanes per
+ * workgroup of the home-lane build); every variant builds the same lists,
+ * and the environment variable HDMD_BUILD_BLK forces one.  Forces (Sec. II.B
+ * getforce): *lanes_per_atom 1, 2 or 4 lanes sharing an atom's row; the
+ * autotuner times them on the first list built for each (d, precision form,
+ * expected row length n V_d(r_l,max) / L^d in half-octaves), and every later system with
  * that key, alone or in a batch, takes its choice (the lane count fixes the
  * rounding of the force sums); Morse systems and systems of fewer than 16384
  * atoms take one.

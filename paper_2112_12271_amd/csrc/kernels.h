@@ -945,6 +945,52 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       // (index < 7 * 64 * 128 < 2^16, count <= 7 * 64)
       const unsigned r0 = ((unsigned)(p0 - c0) << 16) | (unsigned)c0;
       const unsigned r1 = ((unsigned)(S0 + p1 - c1) << 16) | (unsigned)c1;
+      // Survivors spread evenly over the lanes (dense subcells, long rows:
+      // the largest lane count within a few times the mean) are walked lane
+      // by lane, each lane its own atoms' (set 0, then set 1; chunk and bit
+      // order), which needs no listing.
+      if (11 * wave_max_i(c0 + c1) <= S) {
+        unsigned long long m = 0;
+        int cb = 0, cur = -1, i = 0;
+        double xi[D], si;  // own record, loaded when the walk reaches its set
+        while (true) {
+          if (m == 0) {
+            if (ne == 0) break;
+            cb = __builtin_ctz(ne);
+            ne &= ne - 1;
+            const int set = cb >= NB ? 1 : 0;
+            m = msk[(cb % NB) * 128 + set * 64 + lane];
+            if (set != cur) {
+              cur = set;
+              i = set ? i1 : i0;
+              load_rec<D>(xb, set ? ii1 : ii0, xi, si);
+            }
+          }
+          const int j = cand[(cb % NB) * 64 + __builtin_ctzll(m)];
+          m &= m - 1;
+          double xj[D], sj;
+          load_rec<D>(xb, j, xj, sj);
+          if (j != i) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+              const double dx = WR ? min_image(xj[k] - xi[k], L, hL)
+                                   : near_image(xj[k] - xi[k], L, invL);
+              r2 = __builtin_fma(dx, dx, r2);
+              __builtin_amdgcn_sched_barrier(0);  // one axis at a time: few live registers
+            }
+            if (r2 < list_r2(si, sj, cut, skin)) {
+              const int len = cur ? len1 : len0;
+              if (len < W) nl[(size_t)len * npad + i] = j;
+              if (cur) len1 = len + 1;
+              else len0 = len + 1;
+            }
+          }
+        }
+        wave_lds_sync();
+        nb = 0;
+        return;
+      }
       unsigned short* code = reinterpret_cast<unsigned short*>(msk + nb * 128);
       const int cap = 512 * (NB - nb);
       // each lane's walk over its survivors (set 0, then set 1; chunk and
