@@ -945,11 +945,13 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
       // (index < 7 * 64 * 128 < 2^16, count <= 7 * 64)
       const unsigned r0 = ((unsigned)(p0 - c0) << 16) | (unsigned)c0;
       const unsigned r1 = ((unsigned)(S0 + p1 - c1) << 16) | (unsigned)c1;
-      // Survivors spread evenly over the lanes (dense subcells, long rows:
-      // the largest lane count within a few times the mean) are walked lane
-      // by lane, each lane its own atoms' (set 0, then set 1; chunk and bit
-      // order), which needs no listing.
-      if (11 * wave_max_i(c0 + c1) <= S) {
+      // Survivors spread evenly over the lanes (dense subcells and long rows
+      // in d <= 4: the largest lane count within a few times the mean) are
+      // walked lane by lane, each lane its own atoms' (set 0, then set 1;
+      // chunk and bit order), which needs no listing.  (In higher d a pass's
+      // rows are a small part of the stencil and its survivors crowd into
+      // few atoms; the walk is not compiled there.)
+      if (D <= 4 && 11 * wave_max_i(c0 + c1) <= S) {
         unsigned long long m = 0;
         int cb = 0, cur = -1, i = 0;
         double xi[D], si;  // own record, loaded when the walk reaches its set
