@@ -1013,10 +1013,16 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
             m = msk[(cb % NB) * 128 + (cb >= NB ? 64 : 0) + lane];
             if (e >= e1) break;
           }
-          code[e - e0] = (unsigned short)((((cb >= NB ? 64 : 0) + lane) << 9) | ((cb % NB) << 6) |
-                                          __builtin_ctzll(m));
+          // up to two codes per trip (the trips are set by the lane with most)
+          const int hc = (((cb >= NB ? 64 : 0) + lane) << 9) | ((cb % NB) << 6);
+          code[e - e0] = (unsigned short)(hc | __builtin_ctzll(m));
           m &= m - 1;
           e++;
+          if (m != 0 && e < e1) {
+            code[e - e0] = (unsigned short)(hc | __builtin_ctzll(m));
+            m &= m - 1;
+            e++;
+          }
         }
         wave_lds_sync();
         for (int t = e0; t < e1; t += 64) {
