@@ -665,7 +665,7 @@ typedef unsigned uv4 __attribute__((ext_vector_type(4)));
 // integer of magnitude <= 2048 or 1/2 (exact in f16: |q| <= 127, |2q'| <=
 // 1254, -3.93e6 <= C < 2^22, |B| < 2^18) and every partial sum is a multiple
 // of 1/2 below 2^23 in magnitude, so the f32 accumulation is exact in any
-// order.  For d <= 6 a home atom's slots 8..15 are the same for all atoms.
+// order.
 __device__ inline unsigned pack_h2(_Float16 lo, _Float16 hi) {
   return (unsigned)__builtin_bit_cast(unsigned short, lo) |
          ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
@@ -1187,7 +1187,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         S1 += g1 * g1;
       }
       keep0 = __ballot(v0 && S0 < tc0);
-      keep1 = __ballot(v1 && S1 < tc1);
+      keep1 = two ? __ballot(v1 && S1 < tc1) : 0ull;
     };
     // candidate tt of a row of T atoms whose subcell slot r (stencil order)
     // holds the candidates from cum[r-1] on, atom tt + db[0] + ... + db[r]:
@@ -1242,9 +1242,9 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // slots (all others zero).
     auto test_chunks_mf = [&](unsigned long long keep0, unsigned long long keep1, int nch,
                               const int (&cw)[CB][HW], const int (&tA)[CB]) {
-      constexpr int EW = D <= 6 ? 4 : 8;  // staged words per home atom
+      constexpr int EW = 8;  // staged words per home atom: all 16 slots
       static_assert(CB * 128 * 8 >= 2 * 64 * 4 * EW, "two sets of staged home slots fit CB chunk slots");
-      unsigned* stg = reinterpret_cast<unsigned*>(msk + nb * 128);  // free: nb + CB <= NB
+      unsigned* stg = reinterpret_cast<unsigned*>(msk + nb * 128);  // free: nb + CB <= NB - 1
       const int nk0 = __builtin_popcountll(keep0), nk1 = __builtin_popcountll(keep1);
       // stage the kept atoms' slots at their rank; returns, in lanes j and
       // j + 32, the home lanes of compacted rows j (first) and 32 + j
@@ -1268,7 +1268,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           home_slots<D>(owl, owl[HW], w);
           uv4* e = reinterpret_cast<uv4*>(st + EW * rank);
           e[0] = uv4{w[0], w[1], w[2], w[3]};
-          if (EW == 8) e[1] = uv4{w[4], w[5], w[6], w[7]};
+          e[1] = uv4{w[4], w[5], w[6], w[7]};
         }
         const int dst = kept ? rank : nk + (lane - rank);
         const unsigned src = (unsigned)__builtin_amdgcn_ds_permute(dst * 4, lane);
@@ -1276,18 +1276,10 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         s0 = (int)sw[0];
         s1 = (int)sw[1];
       };
-      int sa0, sb0, sa1, sb1;
+      int sa0, sb0, sa1 = 0, sb1 = 0;
       stage(keep0, nk0, ow0, stg, sa0, sb0);
-      stage(keep1, nk1, ow1, stg + 64 * EW, sa1, sb1);
+      if (nk1 > 0) stage(keep1, nk1, ow1, stg + 64 * EW, sa1, sb1);
       wave_lds_sync();
-      // the slot words 8..11 (lane group 2) and 12..15 (group 3) that every
-      // home atom shares when d <= 6
-      uv2 hconst = {0u, 0u};
-      if constexpr (EW == 4) {
-        unsigned w[8];
-        home_slots<D>(ow0, 0, w);
-        hconst = (lane & 16) ? uv2{w[6], w[7]} : uv2{w[4], w[5]};
-      }
       const int q = lane >> 4;
       // one set's home blocks 2p and 2p + 1 (compacted homes 32p ..) against
       // the chunk's candidate blocks X: lane r < 32 receives positions 0..31
@@ -1300,9 +1292,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
           const int b = 2 * p + h;
           if (16 * b >= nk) break;
           const uv2* e = reinterpret_cast<const uv2*>(st + EW * (16 * b + (lane & 15)));
-          uv2 hw = e[EW == 4 ? (q & 1) : q];
-          if (EW == 4 && q >= 2) hw = hconst;
-          const hv4 Hb = __builtin_bit_cast(hv4, hw);
+          const hv4 Hb = __builtin_bit_cast(hv4, e[q]);
           unsigned P = 0u;
 #pragma unroll
           for (int cb = 0; cb < 4; cb++) {
@@ -1361,7 +1351,7 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
         if (c >= nch) continue;
         const int base = (nb + c) * 128;
         msk[base + lane] = 0ull;
-        msk[base + 64 + lane] = 0ull;
+        if (two) msk[base + 64 + lane] = 0ull;
         if (rj < nk0) mw[2 * (base + sa0) + hf] = r00[c];
         if (32 + rj < nk0) mw[2 * (base + sb0) + hf] = r01[c];
         if (rj < nk1) mw[2 * (base + 64 + sa1) + hf] = r10[c];
