@@ -670,10 +670,13 @@ __device__ inline unsigned pack_h2(_Float16 lo, _Float16 hi) {
   return (unsigned)__builtin_bit_cast(unsigned short, lo) |
          ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
 }
-// f16 value of int16 half k of a packed word
+// f16 value of int16 half k of a packed word (converted from 16 bits: one
+// instruction, where a conversion from 32 bits goes through f32)
 __device__ inline _Float16 i16_half(int w, int k) {
-  return (_Float16)(k ? (w >> 16) : (int)(short)(w & 0xffff));
+  return (_Float16)(short)(k ? (w >> 16) : w);
 }
+// f16 value of a small integer (|v| <= 2048)
+__device__ inline _Float16 small_h(int v) { return (_Float16)(short)v; }
 // the 16 slots as 8 words (word t: slots 2t, 2t + 1)
 __device__ inline void slot_words(const _Float16 (&sl)[16], unsigned (&w)[8]) {
 #pragma unroll
@@ -687,8 +690,8 @@ __device__ inline void home_slots(const int* ow, int B, unsigned (&w)[8]) {
   for (int k = 0; k < 16; k++) sl[k] = (_Float16)0;
 #pragma unroll
   for (int k = 0; k < D; k++) sl[k] = -i16_half(ow[k / 2], k % 2);
-  sl[D] = (_Float16)(B >> 11);
-  sl[D + 1] = (_Float16)(B & 2047);
+  sl[D] = small_h(B >> 11);
+  sl[D + 1] = small_h(B & 2047);
   sl[D + 2] = (_Float16)0.5f;
   sl[D + 3] = (_Float16)(-2048);
   sl[D + 4] = (_Float16)(-1);
@@ -707,8 +710,8 @@ __device__ inline void cand_slots(const int* cw, int C, unsigned (&w)[8]) {
   sl[D] = (_Float16)2048;
   sl[D + 1] = (_Float16)1;
   sl[D + 2] = (_Float16)1;
-  sl[D + 3] = (_Float16)(C >> 11);
-  sl[D + 4] = (_Float16)(C & 2047);
+  sl[D + 3] = small_h(C >> 11);
+  sl[D + 4] = small_h(C & 2047);
   slot_words(sl, w);
 }
 
