@@ -67,7 +67,10 @@ __global__ __launch_bounds__(256) void k_scan1(KArgs a) {
     SysDev* s;
     int ch;
     if (!fetch_chunk_tile(a, t, s, ch)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     const int nc = s->ncells;
     const int c0 = ch * kChunk + tid * 4;
     int v[4], local = 0, mx = 0;
@@ -105,7 +108,10 @@ __global__ __launch_bounds__(256) void k_scan2(KArgs a) {
   for (int t = blockIdx.x;; t += gridDim.x) {
     SysDev* s;
     if (!fetch_sys(a, t, s)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     int carry = 0;
     for (int b = 0; b < s->nchunks; b += 256) {
       const int c = b + tid;
@@ -133,7 +139,10 @@ __global__ __launch_bounds__(kTile) void k_scatter(KArgs a) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     const int i = tile * kTile + threadIdx.x;
     if (i >= s->n) continue;
     const int c = s->cell_of[i];

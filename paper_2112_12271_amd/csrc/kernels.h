@@ -216,7 +216,10 @@ __global__ __launch_bounds__(kTile) void k_bin(KArgs a) {
     SysDev* s;
     int tile;
     if (!fetch_atom_tile(a, t, s, tile)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     bin_tile<D>(s, tile);
   }
 }
@@ -387,7 +390,10 @@ __global__ __launch_bounds__(256) void k_cellsort(KArgs a) {
     SysDev* s;
     int c;
     if (!fetch_cell_tile(a, t, s, c)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     cellsort_tile<D, VT>(s, c, sk, sv);
   }
 }
@@ -447,7 +453,10 @@ __global__ __launch_bounds__(BLK) void k_build(KArgs a) {
     SysDev* s;
     int hc;
     if (!fetch_cell_tile(a, t, s, hc)) break;
-    if (!running(s) || !need_rebuild(s)) continue;
+    if (!running(s) || !need_rebuild(s)) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     const int h0 = cell_start(s, hc), h1 = cell_start(s, hc + 1);
     if (h0 == h1) continue;
     const int nc = s->ncell, radix = s->radix, nst = s->nstencil, npad = s->npad;
@@ -1545,7 +1554,10 @@ __global__ __launch_bounds__(64 * G, G >= 8 ? 16 / G : 8) void k_build_t(KArgs a
     if (!fetch_cell_tile(a, t, s, hc)) break;
     s = uniform_ptr(s);
     hc = uniform_int(hc);
-    if (!running(s) || !need_rebuild(s) || uniform_int(s->reach) != RAD) continue;
+    if (!running(s) || !need_rebuild(s) || uniform_int(s->reach) != RAD) {
+      if (a.single) break;  // one system: the same for every tile
+      continue;
+    }
     build_t_tile<D, G, WR, RAD, MF>(s, hc, wv, msk_all[wv], cand_all[wv]);
   }
 }
