@@ -917,8 +917,8 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // the pass are listed home atom by home atom (set 0, then set 1; each
     // atom's in chunk and bit order, the row order) as 16-bit codes (home
     // atom, chunk, bit) in the free chunk slots after the pass's masks (at
-    // least one: the passes start while nb + CB <= NB - 1), and taken 64 at
-    // a time, one per lane.  In a batch the survivors of one home atom are a
+    // least one: chunks are tested only while nb + CB <= NB - 1), and taken
+    // 64 at a time, one per lane.  In a batch the survivors of one home atom are a
     // run of consecutive lanes; a passing one goes to the atom's row at its
     // length so far plus the passing survivors of its run on lower lanes, so
     // every row takes its pairs in the row order.  (Walking each atom's own
@@ -1247,11 +1247,11 @@ __device__ inline void build_t_tile(SysDev* s, int hc, int gw, unsigned long lon
     // candidate at position cpos(l), so that the sign bits of the four
     // result registers of the four candidate blocks, shifted in order into
     // one word per lane, come out in position order: lane 16g + j holds home
-    // column j's bits of positions 16g .. 16g + 15.  Two half swaps join them
-    // into the two 32-bit halves of each home atom's 64-bit mask (lane r:
-    // positions 0..31 of compacted home r of a pair of blocks, lane 32 + r:
-    // positions 32..63), which are scattered at the end to the home atoms'
-    // slots (all others zero).
+    // column j's bits of positions 16g .. 16g + 15.  A half swap per block,
+    // and a select between the two blocks of a pair, join them into the two
+    // 32-bit halves of each home atom's 64-bit mask (lane r: positions 0..31
+    // of compacted home r of the pair, lane 32 + r: positions 32..63), which
+    // are scattered at the end to the home atoms' slots (all others zero).
     auto test_chunks_mf = [&](unsigned long long keep0, unsigned long long keep1, int nch,
                               const int (&cw)[CB][HW], const int (&tA)[CB]) {
       constexpr int EW = 8;  // staged words per home atom: all 16 slots
